@@ -1,0 +1,290 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle itself:
+numbers printed in the paper, closed-form prices, an ODE integration of the Heston
+characteristic function, quadrature exactness, and a gate-by-gate QFT circuit."""
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+import cm_workloads as W
+from oracle import carr_madan as O
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "paper_printed_values.txt")
+
+
+def _golden(key):
+    out = {}
+    for line in open(GOLD):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        k, n, v, d = line.split()
+        if k == key:
+            out[int(n)] = (float(v), int(d))
+    return out
+
+
+def _window(p, lo=50.0, hi=150.0):
+    u = np.arange(2 ** p.n)
+    K = O.strike_of(p, u)
+    m = (K >= lo) & (K <= hi)
+    return u[m], K[m]
+
+
+# ------------------------------------------------------------------ paper-printed numbers
+
+def test_statevector_nrmse_matches_paper_printed_values():
+    """Section 4.2 prints the statevector NRMSE at n = 3, 4, 5; the oracle's grid, psi,
+    DFT and sqrt(p) reconstruction must reproduce them to the printed digits."""
+    for n, (val, digits) in _golden("statevector_nrmse").items():
+        p = W.paper_bs_grid(n)
+        u, K = _window(p)
+        C = O.qft_observable_prices(p, u)
+        e = O.nrmse(C, O.bs_call(100.0, K, 0.05, 0.0, 0.5, 0.3), 100.0)
+        half_ulp = 0.5 * 10 ** (math.floor(math.log10(val)) - (digits - 1))
+        assert abs(e - val) <= half_ulp, (n, e, val)
+
+
+def test_statevector_n3_discriminates_readout():
+    """At n=3 the Re(.) readout differs from the sqrt(p) readout beyond the printed digits,
+    so the pin above really fixes the reconstruction formula."""
+    p = W.paper_bs_grid(3)
+    u, K = _window(p)
+    C = O.prices_dense(p)[u]
+    e = O.nrmse(C, O.bs_call(100.0, K, 0.05, 0.0, 0.5, 0.3), 100.0)
+    assert abs(e - 9.30e-3) > 0.5e-5
+
+
+def test_fft_error_floor_order_of_magnitude():
+    """Section 4.1: the FFT arm saturates near NRMSE 4.4e-15 for n > 12."""
+    floor = _golden("fft_nrmse_floor")[0][0]
+    for n in (14, 16):
+        p = W.paper_bs_grid(n)
+        u, K = _window(p)
+        e = O.nrmse(O.prices_dense(p)[u], O.bs_call(100.0, K, 0.05, 0.0, 0.5, 0.3), 100.0)
+        assert floor / 30 < e < floor * 10, (n, e)
+
+
+# ------------------------------------------------------------------ characteristic functions
+
+def _rand_problems(seed=3):
+    g = np.random.default_rng(seed)
+    out = []
+    for _ in range(4):
+        out.append(W.Problem("bs", "simpson1", 10, 100.0, g.uniform(0, .06), g.uniform(0, .03),
+                             g.uniform(.2, 2), 1.5, .25, (g.uniform(.1, .5),)))
+        out.append(W.Problem("merton", "simpson1", 10, 100.0, g.uniform(0, .06), g.uniform(0, .03),
+                             g.uniform(.2, 2), 1.5, .25,
+                             (g.uniform(.1, .4), g.uniform(0, 1), g.uniform(-.2, .1), g.uniform(.05, .3))))
+    out += W.heston_batch(4, seed=seed, n=12)
+    return out
+
+
+def test_cf_normalisation_and_martingale():
+    """phi(0) = 1 and phi(-i) = E[S_T] = S0 e^{(r-q)T} for every model."""
+    for p in _rand_problems():
+        assert abs(O.char_fn(p, 0.0) - 1.0) < 1e-13
+        fwd = p.S0 * math.exp((p.r - p.q) * p.T)
+        assert abs(O.char_fn(p, -1j) / fwd - 1.0) < 1e-12, p
+
+
+def test_bs_second_moment():
+    """phi(-2i) = E[S_T^2] = S0^2 exp(2(r-q)T + sigma^2 T) for the lognormal law."""
+    p = W.bs_simpson_n12()
+    sig = p.params[0]
+    ref = p.S0 ** 2 * math.exp(2 * (p.r - p.q) * p.T + sig * sig * p.T)
+    assert abs(O.char_fn(p, -2j) / ref - 1.0) < 1e-13
+
+
+def _heston_riccati(p, u):
+    """E[exp(i u ln S_T)] from the Heston Riccati ODEs integrated numerically."""
+    kappa, theta, sv, rho, v0 = p.params
+
+    def rhs(t, y):
+        B = y[0] + 1j * y[1]
+        dB = 0.5 * sv * sv * B * B + (1j * u * rho * sv - kappa) * B - 0.5 * (u * u + 1j * u)
+        dA = kappa * theta * B
+        return [dB.real, dB.imag, dA.real, dA.imag]
+
+    sol = integrate.solve_ivp(rhs, (0.0, p.T), [0.0, 0.0, 0.0, 0.0], rtol=1e-12, atol=1e-14,
+                              method="DOP853")
+    B = sol.y[0, -1] + 1j * sol.y[1, -1]
+    A = sol.y[2, -1] + 1j * sol.y[3, -1]
+    return np.exp(1j * u * (math.log(p.S0) + (p.r - p.q) * p.T) + A + B * v0)
+
+
+def test_heston_cf_matches_riccati_ode():
+    """The closed-form Heston cf against a direct integration of its Riccati ODEs, at real
+    and at shifted complex arguments (where psi evaluates it)."""
+    for p in W.heston_batch(3, seed=11, n=16):
+        for u in (0.7, 3.0, 11.0, 2.0 - 2.5j, 9.0 - 2.5j):
+            a = O.char_fn(p, u)
+            b = _heston_riccati(p, u)
+            assert abs(a - b) <= 1e-8 * max(1.0, abs(b)), (p, u, a, b)
+
+
+def test_merton_without_jumps_is_bs():
+    p = W.merton_big(30).replace(n=12, eta=0.25, params=(0.15, 0.0, -0.1, 0.2))
+    q = W.Problem("bs", "simpson1", 12, p.S0, p.r, p.q, p.T, p.alpha, p.eta, (0.15,))
+    v = np.linspace(0, 40, 17)
+    assert np.abs(O.psi(p, v) - O.psi(q, v)).max() < 1e-12 * np.abs(O.psi(q, v)).max()
+
+
+# ------------------------------------------------------------------ quadrature and transform
+
+def test_simpson_weights_integrate_to_fourth_order():
+    """One-sided Simpson weights integrate a decaying smooth function with O(eta^4) error;
+    a wrong 0-indexed transcription does not converge."""
+    f = lambda v: np.exp(-v) * (1 + v * v)          # integral over [0, inf) = 3
+    errs = []
+    for eta in (0.2, 0.1):
+        p = W.bs_simpson_n12().replace(eta=eta)
+        j = np.arange(4096)
+        errs.append(abs((O.weights(p, j) * f(j * eta)).sum() - 3.0))
+    assert errs[1] < 1e-4 and errs[0] / errs[1] > 12.0, errs
+    wrong = 0.1 / 3 * (3 + (-1.0) ** np.arange(4096) - (np.arange(4096) == 0))
+    assert abs((wrong * f(np.arange(4096) * 0.1)).sum() - 3.0) > 1e-3
+
+
+def test_dft_plane_wave_and_parseval():
+    """Eq. dft: a plane wave exp(2 pi i j m / M) maps to sqrt(M) at u = m, zero elsewhere;
+    the map preserves the 2-norm; the direct and FFT evaluations agree."""
+    n = 10
+    M = 2 ** n
+    j = np.arange(M)
+    for m in (0, 1, 37, M - 1):
+        y = O.dft_direct(np.exp(2j * np.pi * j * m / M), j, np.arange(M), n)
+        e = np.zeros(M); e[m] = math.sqrt(M)
+        assert np.abs(y - e).max() < 1e-10
+    x = np.random.default_rng(0).standard_normal(M) + 1j * np.random.default_rng(1).standard_normal(M)
+    y1 = O.dft_direct(x, j, j, n)
+    y2 = O.dft_fft(x)
+    assert np.abs(y1 - y2).max() < 1e-10
+    assert abs(np.linalg.norm(y1) - np.linalg.norm(x)) < 1e-9
+
+
+def _qft_circuit_minus(n):
+    """Q_n assembled gate by gate: the QFT circuit (Hadamard, then controlled phase
+    R_k = diag(1, exp(2 pi i / 2^k)) from each later qubit) without its final SWAPs, with
+    the phases conjugated for the minus-sign transform (the adjoint gates, reversed order
+    of the commuting diagonal part is immaterial). Qubit 0 is the most significant bit."""
+    M = 2 ** n
+    H = np.array([[1, 1], [1, -1]]) / math.sqrt(2)
+    U = np.eye(M, dtype=complex)
+    idx = np.arange(M)
+    bit = lambda q: (idx >> (n - 1 - q)) & 1
+    for a in range(n):
+        Ha = np.kron(np.kron(np.eye(2 ** a), H), np.eye(2 ** (n - 1 - a)))
+        U = Ha @ U
+        for b in range(a + 1, n):
+            k = b - a + 1
+            ph = np.where((bit(a) == 1) & (bit(b) == 1), np.exp(-2j * np.pi / 2 ** k), 1.0)
+            U = ph[:, None] * U
+    return U
+
+
+def test_qn_matrix_equals_gate_circuit():
+    """Section 3.2: QFT = R_n Q_n; Q_n from the circuit equals the bit-reversed DFT."""
+    for n in (1, 2, 3, 4, 5, 6):
+        assert np.abs(_qft_circuit_minus(n) - O.qn_matrix(n)).max() < 1e-12, n
+
+
+def test_qn_is_bit_reversed_dft():
+    n = 6
+    Q = O.qn_matrix(n)
+    F = O.dft_fft(np.eye(2 ** n))      # columns = DFT of unit vectors
+    perm = O.bitrev(np.arange(2 ** n), n)
+    assert np.abs(Q - F[perm, :]).max() < 1e-12
+    assert np.abs(Q @ Q.conj().T - np.eye(2 ** n)).max() < 1e-12
+
+
+# ------------------------------------------------------------------ prices vs references
+
+def test_bs_rectangle_all_strikes_vs_closed_form():
+    """Config n=12, eta=0.25, alpha=1.5, symmetric rectangle rule: every one of the 4096
+    grid prices matches Eq. analytic_BS."""
+    p = W.bs_rect_n12()
+    u = np.arange(4096)
+    K = O.strike_of(p, u)
+    err = np.abs(O.prices_dense(p) - O.bs_call(100.0, K, 0.05, 0.0, 1.0, 0.2)).max() / 100.0
+    assert err < 1e-8, err
+
+
+def test_bs_simpson_alias_clean_strikes_vs_closed_form():
+    """One-sided Simpson: the half-period alias (1/3) e^{alpha pi/eta} C(k + pi/eta) spoils
+    the lowest strikes; on the alias-clean set the prices match the closed form."""
+    p = W.bs_simpson_n12()
+    u = np.arange(4096)
+    K = O.strike_of(p, u)
+    C = O.prices_dense(p)
+    ref = O.bs_call(100.0, K, 0.05, 0.0, 1.0, 0.2)
+    alias = np.exp(p.alpha * np.pi / p.eta) / 3 * O.bs_call(100.0, K * np.exp(np.pi / p.eta), 0.05, 0.0, 1.0, 0.2)
+    clean = alias < 1e-10 * 100
+    assert clean.sum() > 3000
+    assert np.abs(C - ref)[clean].max() / 100 < 1e-8
+    assert np.abs(C - ref)[~clean].max() / 100 > 1.0     # the alias is real
+
+
+@pytest.mark.parametrize("model", ["bs", "heston"])
+def test_alpha_invariance(model):
+    """Every admissible alpha gives the same price (Section 2.1, after Eq. psi)."""
+    p = W.bs_simpson_n12().replace(n=14, eta=0.1) if model == "bs" else W.heston_n24().replace(n=16)
+    u = W.window_strided(p, 256)
+    ref = O.prices_direct(p, u)
+    for a in (1.0, 2.0, 3.0):
+        C = O.prices_direct(p.replace(alpha=a), u)
+        assert np.abs(C - ref).max() / p.S0 < 1e-9, (a, np.abs(C - ref).max())
+
+
+@pytest.mark.parametrize("model", ["bs", "heston"])
+def test_put_call_parity(model):
+    """alpha = -2.5 transforms the damped put; C - P = S0 e^{-qT} - K e^{-rT}."""
+    p = W.bs_simpson_n12().replace(n=14, eta=0.1) if model == "bs" else W.heston_n24().replace(n=16)
+    u = W.window_strided(p, 256)
+    K = O.strike_of(p, u)
+    C = O.prices_direct(p, u)
+    P = O.prices_direct(p.replace(alpha=-2.5), u)
+    par = p.S0 * math.exp(-p.q * p.T) - K * math.exp(-p.r * p.T)
+    assert np.abs(C - P - par).max() / p.S0 < 1e-10
+
+
+def test_merton_series_near_money():
+    p = W.merton_big(30).replace(n=20, eta=W.eta_rule(20))
+    u = W.near_money(p, 64)
+    C = O.prices_direct(p, u)
+    ref = O.merton_call(p, O.strike_of(p, u))
+    assert np.abs(C - ref).max() / p.S0 < 1e-12
+
+
+def test_heston_gil_pelaez():
+    p = W.heston_n24().replace(n=18)
+    u = W.window_strided(p, 9)
+    C = O.prices_direct(p, u)
+    ref = O.heston_call_gil_pelaez(p, O.strike_of(p, u))
+    assert np.abs(C - ref).max() / p.S0 < 1e-10
+
+
+def test_direct_truncated_dft_matches_full_fft():
+    p = W.heston_n24().replace(n=18)
+    u = W.window_strided(p, 300)
+    assert np.abs(O.prices_direct(p, u) - O.prices_dense(p)[u]).max() / p.S0 < 1e-12
+
+
+def test_heston_explosion_time_matches_riccati_blowup():
+    """T*(omega) of the moment E[S_T^omega] against the blow-up time of the moment Riccati
+    ODE dB/dt = sigma^2 B^2/2 + (rho sigma omega - kappa) B + omega(omega-1)/2."""
+    kappa, sv, rho = 0.5, 0.8, -0.1
+    om = 2.5
+    Ts = O.heston_explosion_time(kappa, sv, rho, om)
+
+    def rhs(t, y):
+        return [0.5 * sv * sv * y[0] ** 2 + (rho * sv * om - kappa) * y[0] + 0.5 * om * (om - 1)]
+
+    ev = lambda t, y: y[0] - 1e8
+    ev.terminal = True
+    sol = integrate.solve_ivp(rhs, (0, 50), [0.0], events=ev, rtol=1e-11, atol=1e-12)
+    assert abs(sol.t_events[0][0] - Ts) < 1e-5 * Ts
+    # the whole batched-Heston parameter box keeps E[S^2.5] finite up to T = 2
+    assert Ts > 2.0
