@@ -1,0 +1,237 @@
+"""Benchmark: strike grids per second, batched SFFT vs dense FFT at n = 24.
+
+Workload: 4096 seeded Heston instances drawn over the batched parameter box
+(kappa~U[0.5,4], theta~U[0.01,0.1], sigma_v~U[0.1,0.8], rho~U[-0.9,-0.1], v0~U[0.01,0.1],
+T~U[0.1,2]), S0=100, r=0.03, alpha=1.5, Simpson weights, n forced to 24,
+eta = 40/2^12; complex64 contraction with FP64 factorisation, tolerance 1e-8.
+One step = the whole SFFT chain for the batch: QTT construction, SFFT apply (zip-up),
+TT rounding and readout of 4096 near-money prices per instance (the Q_n operator is built
+once and cached). A strike grid = one instance's priced M-point log-strike grid: the rounded
+output train, from which every grid price is readable, plus its 4096 read-out prices.
+The dense Stockham path (all 2^24 prices per instance written to HBM) is timed on the
+same problems for comparison.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import cm_workloads as W  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+FP64_VECTOR_TFLOPS = 78.6
+FP32_VECTOR_TFLOPS = 157.3
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--batch", type=int, default=4096)
+    ap.add_argument("--n", type=int, default=24)
+    ap.add_argument("--dense-instances", type=int, default=64)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-parity", action="store_true")
+    return ap.parse_args()
+
+
+def zipup_flops(xr, wr, yr_zip, n):
+    """Algorithmic FP operations of one zip-up (per instance), from the bond dimensions:
+    contraction chi*w*2*r*r' + chi*2*w*2*w'*r' complex MACs (8 real flops each) per site,
+    plus Householder QR of the (w'r') x (2chi) unfolding, 8(2 p s^2 - 2 s^3/3) with
+    s = min(p, 2chi), and one-sided Jacobi on the s x s factor (6 sweeps of s(s-1)/2
+    rotations, each 7 s complex MACs)."""
+    fl = 0.0
+    chi = 1
+    for l in range(n):
+        w0, w1, r0, r1 = wr[l], wr[l + 1], xr[l], xr[l + 1]
+        fl += 8.0 * (chi * w0 * 2 * r0 * r1 + chi * 2 * w0 * 2 * w1 * r1)
+        if l < n - 1:
+            p, m = w1 * r1, 2 * chi
+            s = min(p, m)
+            fl += 8.0 * (2 * max(p, m) * s * s - 2 * s ** 3 / 3)
+            fl += 8.0 * 6 * (s * (s - 1) / 2) * 7 * s
+            chi = yr_zip[l + 1]
+    return fl
+
+
+def cpu_baseline(problem, budget_s=20.0):
+    """The oracle's dense pricing (psi on all 2^n points, FFT, readout) timed on host cores
+    on a bounded number of grids."""
+    from oracle import carr_madan as O
+    done = 0
+    t0 = time.perf_counter()
+    while True:
+        O.prices_dense(problem)
+        done += 1
+        if time.perf_counter() - t0 > budget_s / 2 or done >= 4:
+            break
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    return {"value": done / dt, "unit": "strike grids/s", "cores": threads, "kind": "oracle",
+            "sample": f"{done} dense Heston grid(s) at n={problem.n} priced by the numpy FP64 oracle "
+                      f"(psi on all 2^{problem.n} points + FFT + readout), {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    import paper_2607_28435_amd as cm
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = "cuda"
+    stream = torch.cuda.current_stream()
+    probs = W.heston_batch(args.batch, seed=20261203, n=args.n)
+    nk = 4096
+    strikes = torch.from_numpy(np.stack([W.near_money(p, nk) for p in probs])).to(dev)
+    prices = torch.empty((args.batch, nk), dtype=torch.float64, device=dev)
+
+    t0 = time.perf_counter()
+    mpo = cm.MpoCache([args.n], 1e-9, 32, cm.CM_C64)
+    torch.cuda.synchronize()
+    mpo_s = time.perf_counter() - t0
+    pr = cm.SfftPricer(probs, cm.CM_C64, tol=1e-8, cap=32, mpo=mpo)
+
+    ev = {k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for k in ("build", "apply", "round", "read")}
+    acc = {k: 0.0 for k in ev}
+
+    def step(timed):
+        if timed:
+            ev["build"][0].record(stream)
+        pr.build()
+        if timed:
+            ev["build"][1].record(stream)
+            ev["apply"][0].record(stream)
+        cm.cm_sfft_apply(pr.mpo.w, pr.x, pr.tol, pr.cap, pr.y, pr.st_apply, pr.ws)
+        if timed:
+            ev["apply"][1].record(stream)
+            ev["round"][0].record(stream)
+        cm.cm_tt_round(pr.y, pr.tol, pr.cap, pr.round_err, pr.st_round, pr.ws)
+        if timed:
+            ev["round"][1].record(stream)
+            ev["read"][0].record(stream)
+        cm.cm_readout_prices(pr.y, pr.prob, strikes, nk, prices, pr.st_read)
+        if timed:
+            ev["read"][1].record(stream)
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+        torch.cuda.synchronize()
+        for k in ev:
+            acc[k] += ev[k][0].elapsed_time(ev[k][1])
+    torch.cuda.synchronize()
+    sfft_s = (time.perf_counter() - t0) / args.steps
+    sfft_gps = args.batch / sfft_s
+    stat = pr.statuses()
+    bad = {k: int((v != 0).sum()) for k, v in stat.items()}
+
+    # ranks for the flop model
+    xr = pr.x.ranks.cpu().numpy()
+    yr = pr.y.ranks.cpu().numpy()
+    wr = mpo.w.ranks[args.n].cpu().numpy()
+    # zip-up output ranks before rounding: rerun apply once (not timed) to read them
+    cm.cm_sfft_apply(pr.mpo.w, pr.x, pr.tol, pr.cap, pr.y, pr.st_apply, pr.ws)
+    torch.cuda.synchronize()
+    yz = pr.y.ranks.cpu().numpy()
+    flops = sum(zipup_flops(xr[b], wr, yz[b], args.n) for b in range(args.batch))
+    apply_ms = acc["apply"] / args.steps
+    achieved_tf = flops / (apply_ms * 1e-3) / 1e12
+
+    # dense baseline on a subset of the same problems (all 2^n prices per instance)
+    nd = min(args.dense_instances, args.batch)
+    dprob = cm.pack_problems(probs[:nd], dev)
+    dprices = torch.empty((nd, 2 ** args.n), dtype=torch.float32, device=dev)
+    dstat = torch.zeros(nd, dtype=torch.int32, device=dev)
+    dws = cm.Workspace(dev)
+    cm.cm_fft_price(dprob, nd, args.n, cm.CM_C64, None, 0, dprices, dstat, dws)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 2
+    e0.record(stream)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        cm.cm_fft_price(dprob, nd, args.n, cm.CM_C64, None, 0, dprices, dstat, dws)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    dense_s = (time.perf_counter() - t0) / (reps * nd)
+    dense_ms_ev = e0.elapsed_time(e1) / (reps * nd)
+    dense_gps = 1.0 / dense_s
+    M = 2 ** args.n
+    dense_bytes = 8 * M + (8 * M + 4 * M) if args.n > 14 else 4 * M   # pass-1 write, pass-2 read + price write
+    dense_gbs = dense_bytes / (dense_ms_ev * 1e-3) / 1e9
+
+    # parity on a sample of instances against the FP64 oracle
+    max_err = None
+    dense_err = None
+    if not args.no_parity:
+        from oracle import carr_madan as O
+        got = prices.cpu().numpy()
+        errs, derrs = [], []
+        idx_host = strikes.cpu().numpy()
+        dgot = dprices.cpu().numpy()
+        for b in range(0, min(nd, args.batch), max(1, nd // 4)):
+            sel = idx_host[b, :: nk // 256]
+            ref = O.prices_direct(probs[b], sel)
+            errs.append(np.abs(got[b, :: nk // 256] - ref).max() / probs[b].S0)
+            derrs.append(np.abs(dgot[b, sel] - ref).max() / probs[b].S0)
+        max_err = float(max(errs))
+        dense_err = float(max(derrs))
+
+    out = {
+        "metric": "strike grids/sec, batched SFFT vs dense FFT at n=24, max abs price err/S0",
+        "value": sfft_gps,
+        "unit": "strike grids/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sfft_s * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64 contraction / f64 factorisation",
+        "data": "synthetic seeded Heston parameter draws",
+        "config": {"workload": f"batched Heston SFFT, {args.batch} instances, n={args.n} "
+                               f"(M=2^{args.n}), eta=40/2^{args.n // 2}, tol 1e-8, {nk} read-out strikes",
+                   "batch": args.batch, "n": args.n, "parallelism": "none (1 GPU)"},
+        "dense_fft_grids_per_s": dense_gps,
+        "sfft_over_dense": sfft_gps / dense_gps,
+        "max_abs_err_over_S0": max_err,
+        "dense_max_abs_err_over_S0": dense_err,
+        "stage_ms": {k: acc[k] / args.steps for k in acc},
+        "mpo_build_s": mpo_s,
+        "status_errors": bad,
+        "ranks": {"x_max": int(xr[:, :args.n + 1].max()), "y_max": int(yr[:, :args.n + 1].max()),
+                  "w_max": int(wr[:args.n + 1].max())},
+        "roofline": {"kernel": "k_zipup (cm_sfft_apply)", "bound": "alu", "achieved": achieved_tf,
+                     "peak": FP64_VECTOR_TFLOPS, "unit": "TFLOP/s", "frac": achieved_tf / FP64_VECTOR_TFLOPS,
+                     "traffic": None},
+        "dense_roofline": {"kernel": "k_fft_first + k_fft_next", "bound": "hbm", "achieved": dense_gbs,
+                           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dense_gbs / HBM_PEAK_GBS},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(probs[0])
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

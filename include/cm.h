@@ -1,0 +1,184 @@
+/*
+ * cm.h -- C ABI of the MI355X SFFT Carr–Madan pricing library (libcm.so).
+ *
+ * The library prices European calls with the damped Fourier transform of Carr & Madan
+ * (paper Section 2.1) in two ways:
+ *   - the SFFT path (paper Section 3): a quantised tensor train (QTT) of the integrand x
+ *     (Eq. x), the tensor-train operator of the QFT without its bit reversal (Q_n,
+ *     Section 3.2), the zip-up application of that operator, TT rounding, and a readout of
+ *     bit-reversed prices (Eq. discretization_dft);
+ *   - the dense path: the integrand on all M = 2^n grid points and a Stockham FFT of the
+ *     minus-sign unitary DFT (Eq. dft), followed by the same readout.
+ *
+ * Conventions shared by every call
+ *   - Every call is stream-ordered on `stream` (a hipStream_t passed as void*; NULL is the
+ *     null stream). No call synchronises the stream, allocates device memory or keeps
+ *     global state, except cm_qft_mpo, which synchronises once to report operator ranks.
+ *   - All buffers are caller-owned. "device" means device memory of the current HIP
+ *     device; "host" means ordinary host memory.
+ *   - Complex numbers are interleaved (re, im): float2 for CM_C64, double2 for CM_C128.
+ *   - The return value reports call-level errors (bad arguments, undersized workspace,
+ *     HIP launch failures), detected before anything is enqueued where possible.
+ *     Data-dependent failures of one instance are written to a device status array
+ *     (one int32 per instance, cm_status values) and never abort the batch.
+ *   - Grid notation: M = 2^n, eta = frequency step, lambda = 2 pi / (M eta) the log-strike
+ *     step (grid relation of Section 2.1), k_u = k0 + lambda u, v_j = v0 + j eta.
+ */
+#ifndef CM_H
+#define CM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CM_MAX_N 48          /* largest supported grid exponent n (QTT length)       */
+#define CM_RANKS_STRIDE 49   /* int32 entries per instance in cm_tt_batch.ranks      */
+
+typedef enum {
+  CM_OK = 0,
+  CM_E_INVALID = 1,      /* bad argument, or a workspace smaller than cm_workspace_bytes */
+  CM_E_MOMENT = 2,       /* damping moment E[S_T^(alpha+1)] infinite (Eq. damping_moment_condition) */
+  CM_E_RANKCAP = 3,      /* a bond hit cap_rank while the truncation error exceeded tol; result still written */
+  CM_E_NOCONV = 4,       /* an iteration (Jacobi sweeps, QTT refinement) did not converge */
+  CM_E_NONFINITE = 5,    /* NaN or Inf met in the data */
+  CM_E_HIP = 6,          /* a HIP runtime call failed */
+  CM_E_UNSUPPORTED = 7,  /* valid request outside what this build supports (e.g. n too large for a path) */
+} cm_status;
+
+enum { CM_BS = 0, CM_MERTON = 1, CM_HESTON = 2 };
+/* CM_QUAD_RECT2: the paper's symmetric rectangle rule (Eq. Ck_from_psi), v0 = -M eta/2,
+ *                w_j = eta, price factor 1/(2 pi).
+ * CM_QUAD_SIMPSON1: one-sided Simpson rule folded into x (the higher-order option noted at
+ *                the end of Section 2.1), v0 = 0, w_j = (eta/3)(3 - (-1)^j - delta_j0),
+ *                price factor 1/pi. */
+enum { CM_QUAD_RECT2 = 0, CM_QUAD_SIMPSON1 = 1 };
+enum { CM_C64 = 0, CM_C128 = 1 };
+
+/* One pricing instance (128 bytes, plain data; arrays of it live in device memory).
+ *   p[] : BS {sigma}; Merton {sigma, lambda_J, mu_J, delta_J}; Heston {kappa, theta,
+ *         sigma_v, rho, v0}.
+ *   k0  : lowest log-strike; NaN selects ln(S0) - pi/eta (at-the-money at u = M/2). */
+typedef struct {
+  int32_t model, quad, n, flags;
+  double S0, r, q, T, alpha, eta;
+  double k0;
+  double p[5];
+  double reserved[2];
+} cm_problem;
+
+/* A ragged batch of tensor trains (d_in = 1) or tensor-train operators (d_in = 2).
+ * Instance b has n[b] cores; core l (0-based) is a dense array
+ *   [r_l][d_out][d_in][r_{l+1}]   (complex, row-major, r_0 = r_n = 1)
+ * starting at complex element core_off[b*CM_MAX_N + l] of `cores`. Bond dimensions live in
+ * ranks[b*CM_RANKS_STRIDE + l], l = 0..n[b]; calls that produce a TT write them.
+ * Core l of a TT of the integrand carries bit j_{l+1} of the frequency index with weight
+ * 2^(n-1-l) (most significant first, Eq. discretized_x); core l of an output TT carries
+ * the log-strike bit of weight 2^l (bit-reversed order, Section 3.2).
+ * Use cm_tt_layout to compute offsets that hold any rank up to cap_rank. */
+typedef struct {
+  int32_t batch;           /* number of trains                                        */
+  int32_t d_out, d_in;     /* physical dimensions per core: TT (2, 1), operator (2, 2) */
+  int32_t cap_rank;        /* every bond dimension is at most cap_rank (capacity)      */
+  int32_t n_max;           /* host: largest n[b] in the batch                          */
+  int32_t dtype;           /* CM_C64 or CM_C128                                        */
+  int32_t rank_max;        /* host: largest bond dimension, when known (0 = unknown)   */
+  int32_t reserved;
+  const int32_t *n;        /* device [batch]                                           */
+  int32_t *ranks;          /* device [batch * CM_RANKS_STRIDE]                         */
+  const int64_t *core_off; /* device [batch * CM_MAX_N]                                */
+  void *cores;             /* device, complex elements of dtype                        */
+} cm_tt_batch;
+
+/* Operation identifiers for cm_workspace_bytes. */
+enum { CM_OP_QFT_MPO = 0, CM_OP_BUILD_QTT = 1, CM_OP_SFFT_APPLY = 2, CM_OP_TT_ROUND = 3,
+       CM_OP_FFT_PRICE = 4 };
+
+/* Host helper. Writes the capacity layout of one train with n cores into off[0..n-1]
+ * (complex-element offsets relative to the train's first core; add a per-train base) and
+ * returns the number of complex elements the train needs. Interior bond l is bounded by
+ * min(cap_rank, (d_out d_in)^l); bonds 0 and n are 1. Returns -1 on bad arguments. */
+int64_t cm_tt_layout(int n, int d_out, int d_in, int cap_rank, int64_t *off);
+
+/* Host helper. Bytes of device workspace the operation needs for `batch` instances of
+ * chain length at most n_max and bond dimensions at most cap_rank (0 on bad arguments).
+ * For CM_OP_FFT_PRICE, n_max is the grid exponent and cap_rank is ignored. */
+size_t cm_workspace_bytes(int op, int batch, int n_max, int cap_rank, int dtype);
+
+/* Builds the tensor-train operator of Q_n: the minus-sign unitary DFT of Eq. dft without
+ * the final bit reversal (QFT = R_n Q_n, Section 3.2), so that output core l carries
+ * log-strike bit 2^l. The operator is assembled exactly from per-bond interpolation of its
+ * phase (a construction different from the paper's zip-up of the gate circuit, same
+ * operator) and then rounded to relative Frobenius tolerance `tol` with bonds at most
+ * cap_rank, leaving cores 1..n-1 right-orthonormal. The result goes to train `slot` of
+ * `w` (d_out = d_in = 2); w->n[slot] must already equal n on the device. Sets
+ * w->rank_max on the host (this call synchronises `stream` once to read the ranks).
+ * Workspace: cm_workspace_bytes(CM_OP_QFT_MPO, 1, n, cap_rank, dtype). */
+cm_status cm_qft_mpo(int n, double tol, int cap_rank, cm_tt_batch *w, int slot,
+                     void *ws, size_t ws_bytes, void *stream);
+
+/* Builds, for each problem b, the QTT of the integrand
+ *   x_j = w_j psi(v_j) exp(-i j eta k0)          (Eq. x; psi from Eq. psi)
+ * on j = 0..M-1 with M = 2^prob[b].n (MSB-first cores, Eq. discretized_x), rounded to
+ * relative tolerance tol (bond dims <= cap_rank) with cores 1..n-1 right-orthonormal.
+ * The exponential factor is the exact rank-1 train of Section 3.3; the smooth remainder
+ * is interpolated on an adaptive dyadic partition (piecewise Chebyshev) instead of the
+ * paper's TT-cross. prob: device [batch]. x: trains with x->n[b] == prob[b].n and
+ * d_out = 2, d_in = 1. status: device [batch] (CM_E_MOMENT for Heston instances whose
+ * damping moment explodes before T, CM_E_NONFINITE, CM_E_NOCONV, CM_E_RANKCAP).
+ * Workspace: cm_workspace_bytes(CM_OP_BUILD_QTT, batch, x->n_max, cap_rank, dtype). */
+cm_status cm_build_qtt(const cm_problem *prob, int batch, double tol, int cap_rank,
+                       cm_tt_batch *x, int32_t *status, void *ws, size_t ws_bytes, void *stream);
+
+/* SFFT step (Section 3.2-3.3, Eq. complexity_TTO): y_b = Q_n x_b for every train b,
+ * computed by a left-to-right zip-up contraction with truncated SVDs (relative tolerance
+ * tol per bond, bonds <= cap_rank). w_by_n holds one operator per chain length: train n
+ * of w_by_n is Q_n (so w_by_n->batch > n_max), built by cm_qft_mpo with cores 1..n-1
+ * right-orthonormal; x must have cores 1..n-1 right-orthonormal (cm_build_qtt and
+ * cm_tt_round leave them so). Contractions run in the storage precision (x->dtype ==
+ * y->dtype == w_by_n->dtype); Householder QR and Jacobi SVD run in FP64.
+ * y: trains with y->n[b] == x->n[b], d_out = 2, d_in = 1. status: device [batch].
+ * Workspace: cm_workspace_bytes(CM_OP_SFFT_APPLY, batch, x->n_max, cap_rank, dtype). */
+cm_status cm_sfft_apply(const cm_tt_batch *w_by_n, const cm_tt_batch *x, double tol, int cap_rank,
+                        cm_tt_batch *y, int32_t *status, void *ws, size_t ws_bytes, void *stream);
+
+/* TT rounding (Oseledets 2011; the recompression of Section 3.1) in place: a QR sweep
+ * left to right, then truncated SVDs right to left with per-bond threshold
+ * tol * ||t|| / sqrt(n-1), bonds <= cap_rank. Afterwards cores 1..n-1 are
+ * right-orthonormal. All factorisations in FP64. err_out (device [batch], may be NULL)
+ * receives the achieved relative Frobenius error bound. status: device [batch].
+ * Workspace: cm_workspace_bytes(CM_OP_TT_ROUND, batch, t->n_max, cap_rank, t->dtype). */
+cm_status cm_tt_round(cm_tt_batch *t, double tol, int cap_rank, double *err_out,
+                      int32_t *status, void *ws, size_t ws_bytes, void *stream);
+
+/* Prices from an SFFT output train (Eq. discretization_dft):
+ *   C(k_u) = Re[ exp(-alpha k_u)/(s pi) * exp(-i v0 k_u) * sqrt(M) * y_u ]
+ * with s = 2 (rectangle) or 1 (Simpson), where y_u is read from train b at the
+ * bit-reversed index of u. strike_idx: device int64 [batch][nk] log-strike indices u in
+ * [0, M); prices: device double [batch][nk]. status: device [batch] (may be NULL); an
+ * index outside [0, M) yields NaN and CM_E_INVALID for that instance. */
+cm_status cm_readout_prices(const cm_tt_batch *y, const cm_problem *prob, const int64_t *strike_idx,
+                            int nk, double *prices, int32_t *status, void *stream);
+
+/* Dense Carr–Madan baseline: evaluates x (Eq. x) on all M = 2^n points inside the first
+ * FFT pass, applies the minus-sign DFT with a Stockham FFT in the storage precision, and
+ * applies the readout scalars in the last pass. Every problem must have prob[b].n == n
+ * (n <= 30). If strike_idx is NULL, prices is [batch][M]; otherwise strike_idx is device
+ * int64 [batch][nk] and prices is [batch][nk] (gathered). prices holds float for CM_C64 and
+ * double for CM_C128. status: device [batch] (may be NULL).
+ * Workspace: cm_workspace_bytes(CM_OP_FFT_PRICE, batch, n, 0, dtype). */
+cm_status cm_fft_price(const cm_problem *prob, int batch, int n, int dtype, const int64_t *strike_idx,
+                       int nk, void *prices, int32_t *status, void *ws, size_t ws_bytes, void *stream);
+
+/* Short English text for a status code (static storage). */
+const char *cm_status_str(cm_status s);
+
+/* Library version string (static storage). */
+const char *cm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CM_H */

@@ -1,0 +1,400 @@
+// cm_build_qtt: quantised tensor train of the Carr–Madan integrand (Eq. x).
+//
+// Index j has bits j_1 (weight 2^(n-1)) ... j_n (weight 1); core l carries j_l
+// (Eq. discretized_x). The integrand factors exactly as
+//   x_j = w(j_n) * exp(i v0 m_f) * exp(i j theta) * h(v0 + j eta),  theta = eta (m_f - k0),
+// where exp(i j theta) is the rank-1 train of Section 3.3 (one phase per bit), the
+// quadrature weight depends on the last bit only (Simpson: 2eta/3, 4eta/3, with the j = 0
+// weight eta/3 folded into the value at j = 0), and h (cm_cf.h) is smooth.
+//
+// h is represented on an adaptive dyadic partition of [0, M): an interval [c, c + 2^m) is
+//   - a zero leaf if |h| stays below eps(m) on its Chebyshev nodes and check points,
+//   - a polynomial leaf if the degree P-1 Chebyshev interpolant matches h at P-1 check
+//     points to eps(m),
+//   - exact if 2^m <= P (values at all points), otherwise it is split in two.
+// eps(m) = 0.1 tol |h(0)| 2^(-m/2) bounds each leaf's contribution to ||x||_2.
+// Polynomials in the remaining suffix share one P-dimensional bond space (values at the
+// suffix interval's Chebyshev nodes; Lagrange cores pass them down exactly), so the bond
+// dimension before rounding is (#split intervals at that depth) + min(P, 2^m). The train is
+// then rounded to `tol` by the shared FP64 sweep. This replaces the TT-cross of the paper
+// (Section 3.3) with a deterministic construction whose cost is O(#leaves * P) evaluations
+// of h plus O(n P^3) assembly, independent of the grid size 2^n.
+#include "cm_cf.h"
+#include "cm_tt.h"
+
+namespace {
+
+constexpr int QP = 24;          // Chebyshev nodes per polynomial leaf
+constexpr int QNC = 64;         // max candidate intervals per depth
+constexpr int QI = QNC / 2;     // max split intervals per depth
+constexpr int QNPT = 2 * QP - 1;
+constexpr int PRE_CAP = QI + QP + 1;   // bond bound before rounding (<= 64)
+
+struct TreeDepth {
+  int n_int;                 // split intervals at this depth
+  int n_cand;                // candidates = 2 * split intervals of the previous depth
+  int64_t int_a[QI];         // prefixes of split intervals
+  int8_t kind[QNC];          // 0 zero leaf, 1 split, 2 value leaf
+  int8_t idx[QNC];           // index into int_a (kind 1)
+  double2 vals[QNC][QP];     // values of value leaves at their nodes (or points)
+};
+
+struct QttSlab {
+  TreeDepth *tree;    // [n+1]
+  double2 *pre;       // pre-rounding train, n cores of PRE_CAP*2*PRE_CAP
+  int32_t *pre_ranks; // [CM_MAX_N + 1]
+  int64_t *pre_off;   // [CM_MAX_N]
+  RoundScratch rs;
+};
+
+__host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Slab layout (bytes) for one workgroup; also used by the host workspace query.
+__host__ __device__ inline size_t qtt_slab_bytes(int n_max, int cap, size_t *parts) {
+  const int capm = cap > PRE_CAP ? cap : PRE_CAP;
+  const size_t core_cap = (size_t)capm * 2 * capm;
+  size_t o = 0;
+  parts[0] = o; o += align256(sizeof(TreeDepth) * (size_t)(n_max + 1));
+  parts[1] = o; o += align256(sizeof(double2) * (size_t)PRE_CAP * 2 * PRE_CAP * n_max);
+  parts[2] = o; o += align256(sizeof(int32_t) * (CM_MAX_N + 1));
+  parts[3] = o; o += align256(sizeof(int64_t) * CM_MAX_N);
+  parts[4] = o; o += align256(sizeof(double2) * core_cap * n_max);  // rs.tt
+  parts[5] = o; o += align256(sizeof(double2) * core_cap * 6);      // rs.Y..C
+  return o;
+}
+
+__device__ __forceinline__ double node_pos(double Lm1, double c) { return Lm1 * 0.5 * (1.0 - c); }
+
+// barycentric weight of Chebyshev points of the second kind
+__device__ __forceinline__ double bary_w(int q) {
+  double w = (q & 1) ? -1.0 : 1.0;
+  return (q == 0 || q == QP - 1) ? 0.5 * w : w;
+}
+
+// Lagrange basis value L_p(x) on nodes t_q = Lm1 (1 - cos(pi q/(P-1)))/2.
+__device__ double lagrange(int p, double x, double Lm1, const double *cq) {
+  double den = 0.0, mine = 0.0;
+  for (int q = 0; q < QP; ++q) {
+    const double t = node_pos(Lm1, cq[q]);
+    const double dx = x - t;
+    if (fabs(dx) <= 1e-13 * (Lm1 + 1.0)) return q == p ? 1.0 : 0.0;
+    const double w = bary_w(q) / dx;
+    den += w;
+    if (q == p) mine = w;
+  }
+  return mine / den;
+}
+
+}  // namespace
+
+// theta = eta (m_f - k0) as phase fraction of bit weight 2^s.
+__device__ __forceinline__ double theta_frac(const cm_problem &pr, int s) {
+  const double rq = (pr.r - pr.q) * pr.T;
+  if (k0_is_default(pr)) {
+    // k0 = ln S0 - pi/eta: theta = eta (r - q) T + pi
+    double f = prod_cycles_frac(pr.eta, rq, s);
+    if (s == 0) { f += 0.5; f -= floor(f); }
+    return f;
+  }
+  const double a = (log(pr.S0) - pr.k0) + rq;
+  return prod_cycles_frac(pr.eta, a, s);
+}
+
+// exp(i v0 m_f) as phase fraction (v0 = -eta 2^(n-1) for the symmetric rule, else 0).
+__device__ __forceinline__ double v0mf_frac(const cm_problem &pr) {
+  if (pr.quad != CM_QUAD_RECT2) return 0.0;
+  const double v0 = -ldexp(pr.eta, pr.n - 1);
+  const double f1 = prod_cycles_frac(v0, log(pr.S0), 0);
+  const double f2 = prod_cycles_frac(v0, (pr.r - pr.q) * pr.T, 0);
+  double f = f1 + f2;
+  return f - floor(f);
+}
+
+template <typename OutT>
+__global__ __launch_bounds__(CM_WG) void k_build_qtt(const cm_problem *__restrict__ prob, int batch,
+                                                     double tol, int cap, TTView x,
+                                                     int32_t *__restrict__ status,
+                                                     char *__restrict__ ws, size_t slab_bytes, int n_max) {
+  extern __shared__ double2 dyn[];
+  __shared__ la::Sh sh;
+  __shared__ double cq[QP], ck[QP];
+  __shared__ int code_sh;
+  __shared__ int8_t kind_sh[QNC];
+  __shared__ double err_sh[QNC];
+  const int tid = threadIdx.x;
+  // LDS: tree phase uses dyn as vals[QNC][QNPT]; rounding phase uses it as S, J (64x64 each)
+  double2 *vals = dyn;
+  double2 *S = dyn, *J = dyn + 64 * 64;
+  size_t parts[6];
+  qtt_slab_bytes(n_max, cap, parts);
+  char *slab = ws + (size_t)blockIdx.x * slab_bytes;
+  QttSlab W;
+  W.tree = (TreeDepth *)(slab + parts[0]);
+  W.pre = (double2 *)(slab + parts[1]);
+  W.pre_ranks = (int32_t *)(slab + parts[2]);
+  W.pre_off = (int64_t *)(slab + parts[3]);
+  const int capm = cap > PRE_CAP ? cap : PRE_CAP;
+  W.rs.core_cap = (int64_t)capm * 2 * capm;
+  W.rs.tt = (double2 *)(slab + parts[4]);
+  double2 *mats = (double2 *)(slab + parts[5]);
+  W.rs.Y = mats; W.rs.X = mats + W.rs.core_cap; W.rs.Z = mats + 2 * W.rs.core_cap;
+  W.rs.L = mats + 3 * W.rs.core_cap; W.rs.R = mats + 4 * W.rs.core_cap; W.rs.C = mats + 5 * W.rs.core_cap;
+  if (tid < QP) {
+    cq[tid] = cos(M_PI * tid / (QP - 1));
+    ck[tid] = cos(M_PI * (tid + 0.5) / (QP - 1));
+  }
+  __syncthreads();
+
+  for (int b = blockIdx.x; b < batch; b += gridDim.x) {
+    const cm_problem pr = prob[b];
+    if (tid == 0) {
+      int c = check_problem(pr);
+      if (c == CM_OK && x.n[b] != pr.n) c = CM_E_INVALID;
+      if (c == CM_OK && pr.n > n_max) c = CM_E_INVALID;
+      code_sh = c;
+    }
+    __syncthreads();
+    const int n = pr.n;
+    if (code_sh != CM_OK) {
+      // leave a valid rank-1 zero train so later stages stay well defined
+      if (code_sh != CM_E_INVALID || (x.n[b] == n && n >= 1 && n <= n_max)) {
+        OutT *cores = (OutT *)x.cores;
+        for (int l = 0; l < n; ++l)
+          for (int e = tid; e < 2; e += CM_WG) cstore<OutT>::st(cores, x.coff(b, l) + e, cmk(0.0, 0.0));
+        for (int l = tid; l <= n; l += CM_WG) x.rk(b)[l] = 1;
+      }
+      if (tid == 0 && status) status[b] = code_sh;
+      __syncthreads();
+      continue;
+    }
+    const CfModel<double> cm = make_model<double>(pr);
+    const bool simpson = pr.quad == CM_QUAD_SIMPSON1;
+    const double eta = pr.eta;
+    const double v0 = simpson ? 0.0 : -ldexp(eta, n - 1);
+    const int64_t jpeak = simpson ? 0 : ((int64_t)1 << (n - 1));
+    const double2 hpk = [&] { cx<double> z = h_centered<double>(cm, v0 + (double)jpeak * eta); return cmk(z.x, z.y); }();
+    const double hscale = sqrt(cabs2(hpk));
+    const double eps_rel = 0.1 * tol;
+
+    // ---------------- tree
+    TreeDepth *T = W.tree;
+    if (tid == 0) { T[0].n_int = 1; T[0].n_cand = 1; T[0].int_a[0] = 0; T[0].kind[0] = 1; T[0].idx[0] = 0; }
+    __syncthreads();
+    int depth_done = 0;
+    for (int d = 1; d <= n; ++d) {
+      const int I_prev = T[d - 1].n_int;
+      const int NC = 2 * I_prev;
+      const int m = n - d;
+      const int64_t L = (int64_t)1 << m;
+      const bool exact = L <= QP;
+      const int npts = exact ? (int)L : QNPT;
+      const double Lm1 = (double)(L - 1);
+      if (NC > QNC) {
+        if (tid == 0) code_sh = CM_E_NOCONV;
+        __syncthreads();
+        break;
+      }
+      if (tid == 0) T[d].n_cand = NC;
+      for (int e = tid; e < NC * npts; e += CM_WG) {
+        const int ci = e / npts, q = e % npts;
+        const int64_t c = T[d - 1].int_a[ci >> 1] + ((int64_t)(ci & 1) << m);
+        double pos;
+        if (exact) pos = (double)q;
+        else pos = (q < QP) ? node_pos(Lm1, cq[q]) : node_pos(Lm1, ck[q - QP]);
+        const double v = v0 + ((double)c + pos) * eta;
+        const cx<double> h = h_centered<double>(cm, v);
+        vals[ci * QNPT + q] = cmk(h.x, h.y);
+      }
+      __syncthreads();
+      const double eps = eps_rel * hscale * exp2(-0.5 * m);
+      if (tid < NC) {
+        const int ci = tid;
+        const int64_t c = T[d - 1].int_a[ci >> 1] + ((int64_t)(ci & 1) << m);
+        const bool forced = simpson && c == 0;
+        int kind;
+        if (exact) {
+          kind = 2;
+          if (simpson && c == 0) vals[ci * QNPT] = cscale(vals[ci * QNPT], 0.5);
+        } else {
+          double mx = 0.0;
+          for (int q = 0; q < QNPT; ++q) mx = fmax(mx, sqrt(cabs2(vals[ci * QNPT + q])));
+          if (!(mx == mx) || isinf(mx)) { kind = -1; }
+          else if (mx <= eps && !forced) kind = 0;
+          else {
+            double err = 0.0;
+            for (int k = 0; k < QP - 1; ++k) {
+              const double xk = node_pos(Lm1, ck[k]);
+              double2 num = cmk(0.0, 0.0);
+              double den = 0.0;
+              for (int q = 0; q < QP; ++q) {
+                const double w = bary_w(q) / (xk - node_pos(Lm1, cq[q]));
+                den += w;
+                num = cadd(num, cscale(vals[ci * QNPT + q], w));
+              }
+              const double2 p = cscale(num, 1.0 / den);
+              err = fmax(err, sqrt(cabs2(csub(p, vals[ci * QNPT + QP + k]))));
+            }
+            kind = (err <= eps && !forced) ? 2 : 1;
+          }
+        }
+        kind_sh[ci] = (int8_t)kind;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        int ni = 0;
+        for (int ci = 0; ci < NC; ++ci) {
+          int k = kind_sh[ci];
+          if (k < 0) { code_sh = CM_E_NONFINITE; k = 0; }
+          if (k == 1) {
+            if (ni >= QI) { code_sh = CM_E_NOCONV; k = 0; }
+            else { T[d].int_a[ni] = T[d - 1].int_a[ci >> 1] + ((int64_t)(ci & 1) << m); T[d].idx[ci] = (int8_t)ni; ++ni; }
+          }
+          T[d].kind[ci] = (int8_t)k;
+        }
+        T[d].n_int = ni;
+      }
+      __syncthreads();
+      const int pv = exact ? (int)L : QP;
+      for (int e = tid; e < NC * pv; e += CM_WG) {
+        const int ci = e / pv, q = e % pv;
+        T[d].vals[ci][q] = vals[ci * QNPT + q];
+      }
+      __syncthreads();
+      depth_done = d;
+      if (code_sh != CM_OK) break;
+    }
+    (void)depth_done;
+    if (code_sh != CM_OK) {
+      if (tid == 0 && status) status[b] = code_sh;
+      OutT *cores = (OutT *)x.cores;
+      for (int l = 0; l < n; ++l)
+        for (int e = tid; e < 2; e += CM_WG) cstore<OutT>::st(cores, x.coff(b, l) + e, cmk(0.0, 0.0));
+      for (int l = tid; l <= n; l += CM_WG) x.rk(b)[l] = 1;
+      __syncthreads();
+      continue;
+    }
+
+    // ---------------- assembly of the pre-rounding train (FP64)
+    // active[d]: some value leaf exists at depth <= d
+    __shared__ int active[CM_MAX_N + 1];
+    __shared__ int rks[CM_MAX_N + 1];
+    if (tid == 0) {
+      int a = 0;
+      for (int d = 0; d <= n; ++d) {
+        if (d > 0)
+          for (int ci = 0; ci < T[d].n_cand; ++ci) a |= (T[d].kind[ci] == 2);
+        active[d] = a;
+        const int m = n - d;
+        const int pb = (m >= 5) ? QP : ((1 << m) < QP ? (1 << m) : QP);
+        rks[d] = (d == 0) ? 1 : (T[d].n_int + (a ? pb : 0));
+      }
+      if (rks[n] < 1) rks[n] = 1;  // all-zero integrand: keep a valid (zero) train
+      for (int d = 0; d <= n; ++d) W.pre_ranks[d] = rks[d] < 1 ? 1 : rks[d];
+      for (int l = 0; l < n; ++l) W.pre_off[l] = (int64_t)l * PRE_CAP * 2 * PRE_CAP;
+    }
+    __syncthreads();
+    const double vf = v0mf_frac(pr);
+    for (int l = 1; l <= n; ++l) {  // core l maps bond l-1 -> bond l
+      const int m = n - l;          // suffix bits after this core; bit weight 2^m
+      const int rl = W.pre_ranks[l - 1], rr = W.pre_ranks[l];
+      const int Il = T[l - 1].n_int;
+      const int Ir = (l < n) ? T[l].n_int : 0;
+      const int pbl = (m + 1 >= 5) ? QP : ((1 << (m + 1)) < QP ? (1 << (m + 1)) : QP);
+      const int pbr = (m >= 5) ? QP : ((1 << m) < QP ? (1 << m) : QP);
+      const bool actl = active[l - 1] && l > 1;
+      const bool actr = active[l];
+      const bool exl = ((int64_t)1 << (m + 1)) <= QP;
+      const bool exr = ((int64_t)1 << m) <= QP;
+      const double Lm1l = (double)(((int64_t)1 << (m + 1)) - 1);
+      const double Lm1r = (double)(((int64_t)1 << m) - 1);
+      double2 *G = W.pre + W.pre_off[l - 1];
+      // rank-1 factors of this core
+      const double2 ph1 = turn(theta_frac(pr, m));
+      double2 wt0 = cmk(1.0, 0.0), wt1 = ph1;
+      if (l == n) {
+        const double w0 = simpson ? 2.0 * eta / 3.0 : eta, w1 = simpson ? 4.0 * eta / 3.0 : eta;
+        wt0 = cscale(wt0, w0);
+        wt1 = cscale(wt1, w1);
+      }
+      if (l == 1) {
+        const double2 g = turn(vf);
+        wt0 = cmul(wt0, g);
+        wt1 = cmul(wt1, g);
+      }
+      for (int e = tid; e < rl * 2 * rr; e += CM_WG) {
+        const int i = e / (2 * rr), beta = (e / rr) & 1, jr = e % rr;
+        double2 v = cmk(0.0, 0.0);
+        if (i < Il || l == 1) {
+          // split interval i (at depth l-1), child ci = 2 i + beta
+          const int ci = 2 * (l == 1 ? 0 : i) + beta;
+          const int k = T[l].kind[ci];
+          if (k == 1) {
+            if (jr == T[l].idx[ci]) v = cmk(1.0, 0.0);
+          } else if (k == 2) {
+            if (jr >= Ir && actr && jr - Ir < pbr) v = T[l].vals[ci][jr - Ir];
+          }
+        } else if (actl) {
+          const int p = i - Il;
+          if (jr >= Ir && actr) {
+            const int q = jr - Ir;
+            const double tq = exr ? (double)q : node_pos(Lm1r, cq[q]);
+            const double xq = beta * ldexp(1.0, m) + tq;
+            double lv;
+            if (exl) lv = (fabs(xq - (double)p) < 0.5) ? 1.0 : 0.0;
+            else lv = lagrange(p, xq, Lm1l, cq);
+            v = cmk(lv, 0.0);
+          }
+        }
+        v = cmul(v, beta ? wt1 : wt0);
+        G[e] = v;
+      }
+      __syncthreads();
+    }
+
+    // ---------------- rounding into x
+    CoreSrc src;
+    src.cores = W.pre; src.off = W.pre_off; src.ranks = W.pre_ranks; src.dtype = CM_C128;
+    OutT *xc = (OutT *)x.cores;
+    const double err = round_train<OutT>(n, 2, src, tol, cap, xc, x.off + (int64_t)b * CM_MAX_N, x.rk(b),
+                                         W.rs, S, J, sh, &code_sh);
+    (void)err;
+    __syncthreads();
+    if (tid == 0 && status) status[b] = code_sh;
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ host side
+extern "C" size_t cm_qtt_slab_bytes(int n_max, int cap) {
+  size_t parts[6];
+  return qtt_slab_bytes(n_max, cap, parts);
+}
+
+extern "C" int cm_slots_for(int batch);
+
+extern "C" cm_status cm_build_qtt(const cm_problem *prob, int batch, double tol, int cap_rank,
+                                  cm_tt_batch *x, int32_t *status, void *ws, size_t ws_bytes,
+                                  void *stream) {
+  if (!prob || !x || batch < 0 || !(tol > 0.0) || cap_rank < 1 || cap_rank > 64) return CM_E_INVALID;
+  if (batch == 0) return CM_OK;
+  if (x->d_out != 2 || x->d_in != 1 || x->batch < batch || x->n_max < 1 || x->n_max > CM_MAX_N) return CM_E_INVALID;
+  if (cap_rank > x->cap_rank) return CM_E_INVALID;
+  if (x->dtype != CM_C64 && x->dtype != CM_C128) return CM_E_INVALID;
+  const size_t need = cm_workspace_bytes(CM_OP_BUILD_QTT, batch, x->n_max, cap_rank, x->dtype);
+  if (!ws || ws_bytes < need) return CM_E_INVALID;
+  const int slots = cm_slots_for(batch);
+  const size_t slab = cm_qtt_slab_bytes(x->n_max, cap_rank);
+  const size_t lds = sizeof(double2) * (size_t)(QNC * QNPT > 2 * 64 * 64 ? QNC * QNPT : 2 * 64 * 64);
+  TTView v = tt_view(x);
+  hipStream_t s = (hipStream_t)stream;
+  CM_HIP_CHECK(cm_allow_lds(k_build_qtt<float2>, lds));
+  CM_HIP_CHECK(cm_allow_lds(k_build_qtt<double2>, lds));
+  if (x->dtype == CM_C64)
+    hipLaunchKernelGGL(k_build_qtt<float2>, dim3(slots), dim3(CM_WG), lds, s, prob, batch, tol, cap_rank, v,
+                       status, (char *)ws, slab, x->n_max);
+  else
+    hipLaunchKernelGGL(k_build_qtt<double2>, dim3(slots), dim3(CM_WG), lds, s, prob, batch, tol, cap_rank, v,
+                       status, (char *)ws, slab, x->n_max);
+  CM_LAUNCH_CHECK();
+  return CM_OK;
+}

@@ -1,0 +1,86 @@
+// cm_tt_round: in-place TT rounding (the recompression of Section 3.1, after Oseledets
+// 2011) of every train in a batch, one workgroup per train, FP64 factorisations.
+#include "cm_tt.h"
+
+namespace {
+__host__ __device__ inline size_t al256r(size_t x) { return (x + 255) & ~(size_t)255; }
+__host__ __device__ inline size_t round_slab_bytes(int n_max, int d, int cap) {
+  const size_t core_cap = (size_t)cap * d * cap;
+  return al256r(sizeof(double2) * core_cap * n_max) + al256r(sizeof(double2) * core_cap * 6);
+}
+}  // namespace
+
+template <typename T>
+__global__ __launch_bounds__(CM_WG) void k_tt_round(TTView t, int batch, double tol, int cap, int incap,
+                                                    double *__restrict__ err_out, int32_t *__restrict__ status,
+                                                    char *__restrict__ ws, size_t slab_bytes, int n_max, int dtype) {
+  extern __shared__ double2 dyn[];
+  __shared__ la::Sh sh;
+  __shared__ int code_sh;
+  const int tid = threadIdx.x;
+  char *slab = ws + (size_t)blockIdx.x * slab_bytes;
+  RoundScratch rs;
+  rs.core_cap = (int64_t)incap * t.d * incap;
+  rs.tt = (double2 *)slab;
+  double2 *mats = (double2 *)(slab + al256r(sizeof(double2) * rs.core_cap * n_max));
+  rs.Y = mats; rs.X = mats + rs.core_cap; rs.Z = mats + 2 * rs.core_cap;
+  rs.L = mats + 3 * rs.core_cap; rs.R = mats + 4 * rs.core_cap; rs.C = mats + 5 * rs.core_cap;
+  for (int b = blockIdx.x; b < batch; b += gridDim.x) {
+    const int n = t.n[b];
+    if (tid == 0) {
+      int c = CM_OK;
+      if (n < 1 || n > n_max) c = CM_E_INVALID;
+      else
+        for (int l = 0; l <= n; ++l)
+          if (t.rk(b)[l] < 1 || t.rk(b)[l] > incap) c = CM_E_INVALID;
+      code_sh = c;
+    }
+    __syncthreads();
+    if (code_sh != CM_OK) {
+      if (tid == 0) { if (status) status[b] = code_sh; if (err_out) err_out[b] = NAN; }
+      __syncthreads();
+      continue;
+    }
+    CoreSrc src;
+    src.cores = t.cores; src.off = t.off + (int64_t)b * CM_MAX_N; src.ranks = t.rk(b); src.dtype = dtype;
+    const double e = round_train<T>(n, t.d, src, tol, cap, (T *)t.cores, t.off + (int64_t)b * CM_MAX_N, t.rk(b), rs,
+                                    dyn, dyn + 64 * 64, sh, &code_sh);
+    __syncthreads();
+    if (tid == 0) {
+      if (status) status[b] = code_sh;
+      if (err_out) err_out[b] = e;
+    }
+    __syncthreads();
+  }
+}
+
+extern "C" size_t cm_round_slab_bytes(int n_max, int d, int cap) { return round_slab_bytes(n_max, d, cap); }
+extern "C" int cm_slots_for(int batch);
+
+extern "C" cm_status cm_tt_round(cm_tt_batch *t, double tol, int cap_rank, double *err_out, int32_t *status,
+                                 void *ws, size_t ws_bytes, void *stream) {
+  if (!t || !(tol >= 0.0) || cap_rank < 1 || cap_rank > 64) return CM_E_INVALID;
+  if (t->batch < 0 || t->n_max < 1 || t->n_max > CM_MAX_N) return CM_E_INVALID;
+  if (t->dtype != CM_C64 && t->dtype != CM_C128) return CM_E_INVALID;
+  if (t->d_out < 1 || t->d_in < 1 || t->d_out * t->d_in > 4) return CM_E_INVALID;
+  if (t->cap_rank < 1 || t->cap_rank > 64) return CM_E_UNSUPPORTED;
+  if (t->batch == 0) return CM_OK;
+  const size_t need = cm_workspace_bytes(CM_OP_TT_ROUND, t->batch, t->n_max, t->cap_rank, t->dtype);
+  if (!ws || ws_bytes < need) return CM_E_INVALID;
+  const int d = t->d_out * t->d_in;
+  const int slots = cm_slots_for(t->batch);
+  const size_t slab = round_slab_bytes(t->n_max, d, t->cap_rank);
+  const size_t lds = sizeof(double2) * 2 * 64 * 64;
+  TTView v = tt_view(t);
+  hipStream_t s = (hipStream_t)stream;
+  CM_HIP_CHECK(cm_allow_lds(k_tt_round<float2>, lds));
+  CM_HIP_CHECK(cm_allow_lds(k_tt_round<double2>, lds));
+  if (t->dtype == CM_C64)
+    hipLaunchKernelGGL(k_tt_round<float2>, dim3(slots), dim3(CM_WG), lds, s, v, t->batch, tol, cap_rank, t->cap_rank,
+                       err_out, status, (char *)ws, slab, t->n_max, t->dtype);
+  else
+    hipLaunchKernelGGL(k_tt_round<double2>, dim3(slots), dim3(CM_WG), lds, s, v, t->batch, tol, cap_rank, t->cap_rank,
+                       err_out, status, (char *)ws, slab, t->n_max, t->dtype);
+  CM_LAUNCH_CHECK();
+  return CM_OK;
+}

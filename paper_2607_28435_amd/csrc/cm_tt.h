@@ -1,0 +1,168 @@
+// Tensor-train sweeps shared by the library entry points: the FP64 rounding sweep
+// (QR left-to-right, truncated SVD right-to-left) and exact phase reduction helpers.
+#pragma once
+
+#include "cm_linalg.h"
+
+// ------------------------------------------------------------------ exact phases
+// 1/(2 pi) as a double-double.
+#define CM_INV2PI_HI 0.15915494309189535
+#define CM_INV2PI_LO (-9.839338337591243e-18)
+#define CM_2PI 6.283185307179586
+
+__host__ __device__ __forceinline__ void two_sum(double a, double b, double &s, double &e) {
+  s = a + b;
+  double bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+// Double-double cycles c = (hi + lo) / (2 pi); returns the fractional part of c * 2^s.
+__host__ __device__ __forceinline__ double cycles_frac(double hi, double lo, int s) {
+  double ch = hi * CM_INV2PI_HI;
+  double cl = fma(hi, CM_INV2PI_HI, -ch) + hi * CM_INV2PI_LO + lo * CM_INV2PI_HI;
+  double sc = ldexp(1.0, s);
+  return frac2(ch * sc, cl * sc);
+}
+
+// exp(i * 2 pi * f), f a fraction of a turn
+__host__ __device__ __forceinline__ double2 turn(double f) {
+  double sn, cs;
+  sincos(CM_2PI * f, &sn, &cs);
+  return cmk(cs, sn);
+}
+
+// Angle a*b (both doubles, product formed exactly) as a fraction of a turn, times 2^s.
+__host__ __device__ __forceinline__ double prod_cycles_frac(double a, double b, int s) {
+  double p, e;
+  two_prod(a, b, p, e);
+  return cycles_frac(p, e, s);
+}
+
+// ------------------------------------------------------------------ rounding sweep
+// Per-workgroup scratch for one rounding job (FP64 complex, global memory). `tt` holds n
+// cores of core_cap elements; Y, X, Z, L, R, C hold mat_cap elements each.
+struct RoundScratch {
+  double2 *tt;
+  int64_t core_cap;
+  double2 *Y, *X, *Z, *L, *R, *C;
+};
+
+// Source train for the rounding sweep: core l element (t, ph, j) is at
+// off[l] + (t*d + ph)*r_{l+1} + j, stored as float2 (CM_C64) or double2 (otherwise).
+struct CoreSrc {
+  const void *cores;
+  const int64_t *off;
+  const int32_t *ranks;
+  int dtype;
+  __device__ __forceinline__ double2 get(int l, int64_t e) const {
+    if (dtype == CM_C64) return cstore<float2>::ld((const float2 *)cores, off[l] + e);
+    return ((const double2 *)cores)[off[l] + e];
+  }
+};
+
+__device__ __forceinline__ void merge_flags(const la::Sh &sh, int *code) {
+  if (threadIdx.x == 0) {
+    if (sh.nonfinite && *code == CM_OK) *code = CM_E_NONFINITE;
+    if (sh.noconv && *code == CM_OK) *code = CM_E_NOCONV;
+    if (sh.rankcap && *code == CM_OK) *code = CM_E_RANKCAP;
+  }
+}
+
+// Rounds a train of n cores with physical size d from `src` into dst (storage OutT, core
+// offsets dst_off, ranks dst_ranks). Phase A orthogonalises left to right with thin QR;
+// phase B truncates right to left with the per-bond threshold tol*||t||/sqrt(n-1) and
+// bonds <= cap (cap <= 64). Afterwards cores 1..n-1 are right-orthonormal and the norm sits
+// in core 0. dst may alias src (every source core is read in phase A, before phase B
+// writes). Returns the relative Frobenius error bound; *code receives a cm_status (thread 0
+// writes; first error wins).
+template <typename OutT>
+__device__ double round_train(int n, int d, const CoreSrc &src, double tol, int cap,
+                              OutT *dst_cores, const int64_t *dst_off, int32_t *dst_ranks,
+                              const RoundScratch &w, double2 *S, double2 *J, la::Sh &sh,
+                              int *code) {
+  const int tid = threadIdx.x;
+  __shared__ int rk[CM_MAX_N + 1];
+  __shared__ double norm2_sh;
+  if (tid == 0) { rk[0] = 1; norm2_sh = 0.0; w.C[0] = cmk(1.0, 0.0); }
+  __syncthreads();
+  // ---- phase A: carry C (kprev x r_l, ld kprev), starts as [1]
+  int kprev = 1;
+  for (int l = 0; l < n; ++l) {
+    const int rl = src.ranks[l], rr = src.ranks[l + 1];
+    const int rows = kprev * d;
+    for (int e = tid; e < rows * rr; e += CM_WG) {
+      const int i = e % rows, j = e / rows;
+      const int a = i / d, ph = i % d;
+      double2 acc = cmk(0.0, 0.0);
+      for (int t = 0; t < rl; ++t)
+        cfma(acc, w.C[a + kprev * t], src.get(l, ((int64_t)t * d + ph) * rr + j));
+      w.Y[e] = acc;
+    }
+    __syncthreads();
+    double2 *core = w.tt + (int64_t)l * w.core_cap;
+    if (l == n - 1) {
+      double part = 0.0;
+      for (int e = tid; e < rows * rr; e += CM_WG) {
+        core[e] = w.Y[e];
+        part += cabs2(w.Y[e]);
+      }
+      const double nrm2 = la::wg_sum(part, sh.red);
+      if (tid == 0) { norm2_sh = nrm2; rk[l + 1] = rr; }
+      __syncthreads();
+      break;
+    }
+    const int kq = la::qr_thin(w.Y, rows, rr, w.Z, w.L, sh);
+    for (int e = tid; e < rows * kq; e += CM_WG) core[e] = w.Z[e];
+    for (int e = tid; e < kq * rr; e += CM_WG) w.C[e] = w.L[e];
+    if (tid == 0) rk[l + 1] = kq;
+    __syncthreads();
+    kprev = kq;
+  }
+  const double nrm = sqrt(norm2_sh);
+  if (tid == 0 && (!(nrm == nrm) || isinf(nrm)) && *code == CM_OK) *code = CM_E_NONFINITE;
+  const double delta2 = (n > 1) ? (tol * nrm) * (tol * nrm) / (double)(n - 1) : 0.0;
+  // ---- phase B: carry C (kr x rpp, ld kr), starts as [1]
+  double err2 = 0.0;
+  int rpp = 1;
+  if (tid == 0) w.C[0] = cmk(1.0, 0.0);
+  __syncthreads();
+  for (int l = n - 1; l >= 0; --l) {
+    const int kl = rk[l], kr = rk[l + 1];
+    const double2 *core = w.tt + (int64_t)l * w.core_cap;  // column-major (kl*d) x kr
+    const int b = d * rpp;
+    for (int e = tid; e < kl * b; e += CM_WG) {
+      const int i = e % kl, c = e / kl;
+      const int ph = c / rpp, j = c % rpp;
+      double2 acc = cmk(0.0, 0.0);
+      for (int t = 0; t < kr; ++t)
+        cfma(acc, core[(i * d + ph) + (int64_t)(kl * d) * t], w.C[t + kr * j]);
+      w.Y[e] = acc;
+    }
+    __syncthreads();
+    OutT *out = dst_cores + dst_off[l];
+    if (l == 0) {
+      // kl == 1; core 0 = Y (1 x d*rpp), element (0, ph, j) at ph*rpp + j == column index
+      for (int e = tid; e < b; e += CM_WG) cstore<OutT>::st(out, e, w.Y[e]);
+      if (tid == 0) { dst_ranks[0] = 1; dst_ranks[1] = rpp; }
+      __syncthreads();
+      break;
+    }
+    const int k = la::svd_trunc_rows(w.Y, kl, b, delta2, cap, w.X, w.Z, S, J, w.L, w.R, sh);
+    merge_flags(sh, code);
+    err2 += sh.err2;
+    // core l = Rk (k x b, ld k) as [k][d][rpp]
+    for (int e = tid; e < k * b; e += CM_WG) {
+      const int i = e % k, c = e / k;
+      const int ph = c / rpp, j = c % rpp;
+      cstore<OutT>::st(out, ((int64_t)i * d + ph) * rpp + j, w.R[e]);
+    }
+    // carry = L (kl x k, ld kl)
+    for (int e = tid; e < kl * k; e += CM_WG) w.C[e] = w.L[e];
+    if (tid == 0) { dst_ranks[l + 1] = rpp; }
+    __syncthreads();
+    rpp = k;
+  }
+  if (tid == 0) dst_ranks[n] = 1;
+  __syncthreads();
+  return sqrt(err2) / (nrm > 0 ? nrm : 1.0);
+}

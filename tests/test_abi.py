@@ -1,0 +1,65 @@
+"""Host-side checks of the C ABI library: it loads, exports every function declared in
+include/cm.h, and its pure host helpers (layout, workspace sizes, status strings) behave.
+No GPU compute is called here."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2607_28435_amd as cm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "cm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(cm_\w+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_function():
+    L = cm.lib()
+    names = _declared()
+    assert {"cm_qft_mpo", "cm_build_qtt", "cm_sfft_apply", "cm_tt_round", "cm_readout_prices",
+            "cm_fft_price"} <= set(names)
+    for nm in names:
+        assert hasattr(L, nm), nm
+
+
+def test_problem_struct_layout():
+    assert cm.PROBLEM_DTYPE.itemsize == 128
+    assert cm.PROBLEM_DTYPE.fields["S0"][1] == 16
+    assert cm.PROBLEM_DTYPE.fields["k0"][1] == 64
+    import ctypes
+    assert ctypes.sizeof(cm.CmTTBatch) == 64
+
+
+def test_tt_layout_bounds():
+    total, off = cm.cm_tt_layout(6, 2, 1, 3)
+    # interior bonds min(3, 2^l): 1,2,3,3,3,3,1
+    r = [1, 2, 3, 3, 3, 3, 1]
+    assert total == sum(r[l] * 2 * r[l + 1] for l in range(6))
+    assert list(off) == list(np.cumsum([0] + [r[l] * 2 * r[l + 1] for l in range(5)]))
+    total4, _ = cm.cm_tt_layout(5, 2, 2, 64)
+    r4 = [1, 4, 16, 64, 64, 1]
+    assert total4 == sum(r4[l] * 4 * r4[l + 1] for l in range(5))
+    with pytest.raises(cm.CmError):
+        cm.cm_tt_layout(0, 2, 1, 4)
+
+
+def test_workspace_sizes():
+    for op in (cm.CM_OP_QFT_MPO, cm.CM_OP_BUILD_QTT, cm.CM_OP_SFFT_APPLY, cm.CM_OP_TT_ROUND):
+        a = cm.cm_workspace_bytes(op, 4, 24, 32, cm.CM_C64)
+        b = cm.cm_workspace_bytes(op, 4, 24, 64, cm.CM_C64)
+        assert 0 < a <= b
+    assert cm.cm_workspace_bytes(cm.CM_OP_FFT_PRICE, 1, 24, 0, cm.CM_C64) >= 8 * 2 ** 24
+    assert cm.cm_workspace_bytes(cm.CM_OP_BUILD_QTT, 4, 24, 65, cm.CM_C64) == 0
+    assert cm.cm_workspace_bytes(99, 4, 24, 32, cm.CM_C64) == 0
+
+
+def test_status_strings():
+    for code in range(8):
+        assert cm.cm_status_str(code)
+    assert "moment" in cm.cm_status_str(cm.CM_E_MOMENT)
+    assert cm.cm_version().startswith("cm-sfft")

@@ -1,0 +1,241 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Tolerances (written here, derived in the design doc): FP64 paths <= 1e-6 S0 max abs price
+error, complex64 paths <= 1e-4 S0, on the strike sets named in each test."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import cm_workloads as W
+from oracle import carr_madan as O
+from tests.tt_host import contract_mpo, contract_tt, right_orthonormality_error
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2607_28435_amd as cm  # noqa: E402
+
+FP64_TOL = 1e-6
+C64_TOL = 1e-4
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    cm.lib()
+    yield
+    torch.cuda.synchronize()
+
+
+def _strikes_dev(idx_list):
+    return torch.from_numpy(np.stack(idx_list).astype(np.int64)).cuda()
+
+
+# ------------------------------------------------------------------ operator
+
+@pytest.mark.parametrize("n", [1, 2, 4, 7, 10])
+def test_qft_mpo_equals_bit_reversed_dft(n):
+    say("mpo n", n)
+    m = cm.MpoCache([n], 1e-13, 64, cm.CM_C128)
+    cores = m.w.host_cores(n)
+    Q = contract_mpo(cores)
+    assert np.abs(Q - O.qn_matrix(n)).max() < 1e-11
+    assert right_orthonormality_error(cores) < 1e-12
+
+
+def test_qft_mpo_rank_is_small():
+    """Section 3.2 quotes r_SFFT ~ 10; the rounded Q_n has bonds of that size."""
+    say("mpo ranks")
+    m = cm.MpoCache([12, 24], 1e-9, 64, cm.CM_C128)
+    for n in (12, 24):
+        rk = m.w.ranks[n].cpu().numpy()[: n + 1]
+        assert 8 <= rk.max() <= 14, rk
+
+
+# ------------------------------------------------------------------ QTT of the integrand
+
+@pytest.mark.parametrize("name", ["bs_rect", "bs_simpson", "heston16", "merton16", "heston_rect14"])
+def test_build_qtt_matches_integrand(name):
+    say("qtt", name)
+    p = {"bs_rect": W.bs_rect_n12(), "bs_simpson": W.bs_simpson_n12(),
+         "heston16": W.heston_n24().replace(n=16),
+         "merton16": W.merton_big(30).replace(n=16, eta=W.eta_rule(16)),
+         "heston_rect14": W.heston_n24().replace(n=14, quad="rect2", eta=0.1)}[name]
+    pr = cm.SfftPricer([p], cm.CM_C128, tol=1e-10, cap=32)
+    pr.build()
+    torch.cuda.synchronize()
+    assert pr.st_build.cpu().numpy()[0] == cm.CM_OK
+    x = contract_tt(pr.x.host_cores(0))
+    ref = O.integrand(p, np.arange(2 ** p.n))
+    rel = np.linalg.norm(x - ref) / np.linalg.norm(ref)
+    assert rel < 1e-9, rel
+    assert right_orthonormality_error(pr.x.host_cores(0)) < 1e-10
+
+
+# ------------------------------------------------------------------ full pipelines, FP64
+
+def test_sfft_bs_n12_fp64_all_strikes():
+    """Rectangle rule, FP64, tol 1e-10: every one of the 4096 prices within 1e-6 S0 of the
+    oracle (and of the Black–Scholes formula)."""
+    say("sfft bs n12 fp64")
+    p = W.bs_rect_n12()
+    pr = cm.SfftPricer([p], cm.CM_C128, tol=1e-10, cap=32)
+    u = W.all_strikes(p)
+    got = pr.run(_strikes_dev([u])).cpu().numpy()[0]
+    st = pr.statuses()
+    assert all(v[0] == cm.CM_OK for v in st.values()), st
+    ref = O.prices_dense(p)
+    assert np.abs(got - ref).max() / p.S0 < FP64_TOL, np.abs(got - ref).max()
+
+
+def test_sfft_bs_n12_simpson_fp64():
+    say("sfft bs simpson")
+    p = W.bs_simpson_n12()
+    pr = cm.SfftPricer([p], cm.CM_C128, tol=1e-10, cap=32)
+    u = W.all_strikes(p)
+    got = pr.run(_strikes_dev([u])).cpu().numpy()[0]
+    ref = O.prices_dense(p)
+    K = O.strike_of(p, u)
+    win = (K >= 50) & (K <= 150)
+    assert np.abs(got - ref)[win].max() / p.S0 < FP64_TOL
+    # outside the window the Simpson alias makes prices huge; agreement is relative there
+    big = np.abs(ref) > 1e3 * p.S0
+    assert np.all(np.abs(got - ref)[big] <= 1e-6 * np.abs(ref)[big])
+
+
+@pytest.mark.parametrize("quad", ["rect2", "simpson1"])
+def test_dense_fft_fp64_n12_all_strikes(quad):
+    say("dense fp64", quad)
+    p = W.bs_rect_n12().replace(quad=quad)
+    got, st = cm.dense_prices([p], cm.CM_C128)
+    got = got.cpu().numpy()[0]
+    assert st.cpu().numpy()[0] == cm.CM_OK
+    ref = O.prices_dense(p)
+    err = np.abs(got - ref)
+    assert np.all(err <= FP64_TOL * p.S0 + 1e-12 * np.abs(ref)), err.max()
+
+
+def _dft_roundoff_bound(p, rel=1e-13):
+    """Per-strike bound on the price error that FP64 rounding of the DFT can cause:
+    rel * sum_j |x_j| scaled by the readout factor exp(-alpha k_u)/(s pi)."""
+    g = O.grid(p)
+    u = np.arange(g.M)
+    x1 = np.abs(O.integrand(p, u)).sum()
+    return rel * x1 * np.exp(-p.alpha * g.k(u)) / (g.s * math.pi)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 9, 13, 14, 17])
+def test_dense_fft_fp64_sizes(n):
+    """Single- and multi-pass plans (ragged radix splits) against the oracle's FFT, within the
+    FP64 rounding bound of the transform (the paper's grid spans extreme strikes where the
+    factor exp(-alpha k) amplifies rounding; Section 4 notes the same)."""
+    say("dense fp64 n", n)
+    p = W.paper_bs_grid(n)
+    got, st = cm.dense_prices([p], cm.CM_C128)
+    ref = O.prices_dense(p)
+    err = np.abs(got.cpu().numpy()[0] - ref)
+    bound = _dft_roundoff_bound(p) + 1e-12 * p.S0
+    assert np.all(err <= bound), (err / bound).max()
+
+
+def test_paper_grid_statevector_pin_through_gpu():
+    """The paper's grid (Section 4) priced on the GPU dense path reproduces the oracle's
+    FFT NRMSE floor order (~1e-15) at n = 14."""
+    p = W.paper_bs_grid(14)
+    got, _ = cm.dense_prices([p], cm.CM_C128)
+    u = np.arange(2 ** 14)
+    K = O.strike_of(p, u)
+    w = (K >= 50) & (K <= 150)
+    e = O.nrmse(got.cpu().numpy()[0][w], O.bs_call(100.0, K[w], 0.05, 0.0, 0.5, 0.3), 100.0)
+    assert e < 1e-13
+
+
+# ------------------------------------------------------------------ complex64 paths
+
+def test_heston_n24_c64_sfft_and_dense_vs_oracle():
+    """Heston n = 24, eta = 0.05: SFFT (tol 1e-8, cap 64) and the dense Stockham FFT, both
+    complex64, against the FP64 oracle on 4096 strikes strided through 0.5 <= K/S0 <= 1.5."""
+    say("heston n24 c64")
+    p = W.heston_n24()
+    u = W.window_strided(p, 4096)
+    ref = O.prices_direct(p, u)
+    pr = cm.SfftPricer([p], cm.CM_C64, tol=1e-8, cap=64)
+    got = pr.run(_strikes_dev([u])).cpu().numpy()[0]
+    st = pr.statuses()
+    assert all(v[0] == cm.CM_OK for v in st.values()), st
+    e_sfft = np.abs(got - ref).max() / p.S0
+    dense, _ = cm.dense_prices([p], cm.CM_C64, strikes=_strikes_dev([u]))
+    e_dense = np.abs(dense.cpu().numpy()[0] - ref).max() / p.S0
+    say("errors sfft", e_sfft, "dense", e_dense)
+    assert e_sfft < C64_TOL and e_dense < C64_TOL
+
+
+def test_batched_heston_ragged_c64():
+    """Seeded Heston draws over the batched parameter box with uneven n (16..20): every
+    instance within 1e-4 S0 of the oracle on 64 near-money strikes."""
+    say("batched heston")
+    probs = W.heston_batch(24, seed=5, n_range=(16, 20))
+    u = [W.near_money(p, 64) for p in probs]
+    pr = cm.SfftPricer(probs, cm.CM_C64, tol=1e-8, cap=32)
+    got = pr.run(_strikes_dev(u)).cpu().numpy()
+    st = pr.statuses()
+    for k, v in st.items():
+        assert np.all(v == cm.CM_OK), (k, v)
+    for b, p in enumerate(probs):
+        ref = O.prices_direct(p, u[b])
+        assert np.abs(got[b] - ref).max() / p.S0 < C64_TOL, (b, p)
+
+
+@pytest.mark.parametrize("n", [30, 40])
+def test_merton_large_grid_vs_series(n):
+    """Merton, n = 30 and 40 (the 2^40 grid is never materialised): SFFT complex64 prices at
+    4096 near-money strikes against the Merton series."""
+    say("merton n", n)
+    p = W.merton_big(n)
+    u = W.near_money(p, 4096)
+    pr = cm.SfftPricer([p], cm.CM_C64, tol=1e-8, cap=32)
+    got = pr.run(_strikes_dev([u])).cpu().numpy()[0]
+    st = pr.statuses()
+    assert all(v[0] == cm.CM_OK for v in st.values()), st
+    ref = O.merton_call(p, O.strike_of(p, u))
+    assert np.abs(got - ref).max() / p.S0 < C64_TOL
+
+
+# ------------------------------------------------------------------ status codes and edges
+
+def test_status_codes_per_instance():
+    say("status codes")
+    good = W.bs_simpson_n12()
+    bad_sigma = good.replace(params=(-0.2,))
+    # Heston draw whose E[S^(alpha+1)] explodes before T (kappa 0.5, sigma_v 0.8, rho -0.1)
+    moment = W.Problem("heston", "simpson1", 12, 100.0, 0.03, 0.0, 4.0, 1.5, 0.25, (0.5, 0.04, 0.8, -0.1, 0.04))
+    pr = cm.SfftPricer([good, bad_sigma, moment], cm.CM_C128, tol=1e-10, cap=32)
+    u = np.stack([W.near_money(good, 16)] * 3)
+    u[0, 3] = 2 ** 12 + 5   # out of range strike for instance 0
+    got = pr.run(torch.from_numpy(u).cuda()).cpu().numpy()
+    st = pr.statuses()
+    assert st["build"][0] == cm.CM_OK
+    assert st["build"][1] == cm.CM_E_INVALID
+    assert st["build"][2] == cm.CM_E_MOMENT
+    assert st["read"][0] == cm.CM_E_INVALID and math.isnan(got[0, 3])
+    ok = np.delete(np.arange(16), 3)
+    ref = O.prices_direct(good, u[0, ok])
+    assert np.abs(got[0, ok] - ref).max() / 100 < FP64_TOL
+
+
+def test_call_level_errors():
+    good = W.bs_simpson_n12()
+    pr = cm.SfftPricer([good], cm.CM_C128, tol=1e-10, cap=32)
+    with pytest.raises(cm.CmError) as e:
+        cm.cm_build_qtt(pr.prob, 1, 1e-10, 65, pr.x, pr.st_build, pr.ws)
+    assert e.value.code == cm.CM_E_INVALID
+    with pytest.raises(cm.CmError):
+        cm.cm_tt_round(pr.x, -1.0, 8, None, None, pr.ws)
