@@ -87,13 +87,18 @@ __device__ __forceinline__ void set_status(int32_t *status, int b, int code) {
 }
 
 // ------------------------------------------------------------------ phase reduction
+// The error-free transforms below must not be fused with neighbouring operations: with
+// contraction enabled, a product feeding `hi - floor(hi)` becomes one FMA that already
+// carries the product's rounding error, which the low part then adds a second time.
 // Error-free product a*b = p + e (fma based).
 __host__ __device__ __forceinline__ void two_prod(double a, double b, double &p, double &e) {
+#pragma clang fp contract(off)
   p = a * b;
   e = fma(a, b, -p);
 }
 // Fractional part (in [0,1)) of x = hi + lo where hi is a double and lo small.
 __host__ __device__ __forceinline__ double frac2(double hi, double lo) {
+#pragma clang fp contract(off)
   double f = hi - floor(hi);
   f += lo;
   f -= floor(f);

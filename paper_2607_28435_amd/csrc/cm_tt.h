@@ -11,6 +11,7 @@
 #define CM_2PI 6.283185307179586
 
 __host__ __device__ __forceinline__ void two_sum(double a, double b, double &s, double &e) {
+#pragma clang fp contract(off)
   s = a + b;
   double bb = s - a;
   e = (a - (s - bb)) + (b - bb);
@@ -18,6 +19,7 @@ __host__ __device__ __forceinline__ void two_sum(double a, double b, double &s, 
 
 // Double-double cycles c = (hi + lo) / (2 pi); returns the fractional part of c * 2^s.
 __host__ __device__ __forceinline__ double cycles_frac(double hi, double lo, int s) {
+#pragma clang fp contract(off)
   double ch = hi * CM_INV2PI_HI;
   double cl = fma(hi, CM_INV2PI_HI, -ch) + hi * CM_INV2PI_LO + lo * CM_INV2PI_HI;
   double sc = ldexp(1.0, s);
