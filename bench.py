@@ -48,22 +48,22 @@ def parse():
 
 
 def zipup_flops(xr, wr, yr_zip, n):
-    """Algorithmic FP operations of one zip-up (per instance), from the bond dimensions:
-    contraction chi*w*2*r*r' + chi*2*w*2*w'*r' complex MACs (8 real flops each) per site,
-    plus Householder QR of the (w'r') x (2chi) unfolding, 8(2 p s^2 - 2 s^3/3) with
-    s = min(p, 2chi), and one-sided Jacobi on the s x s factor (6 sweeps of s(s-1)/2
-    rotations, each 7 s complex MACs)."""
+    """Algorithmic FP operations of one zip-up (per instance), from the bond dimensions.
+    Per site: the contraction chi*w*2*r*r' + chi*2*w*2*w'*r' complex MACs (8 real flops each);
+    the pivoted Householder QR of the (2chi) x (w'r') matrix stopped at rank k,
+    sum_{i<k} 16 (m-i)(p-i) (reflector application) plus 8 (m-i)(p-i) (norm refresh);
+    and forming Q_k, sum_{i<k} 16 (m-i) k."""
     fl = 0.0
     chi = 1
     for l in range(n):
         w0, w1, r0, r1 = wr[l], wr[l + 1], xr[l], xr[l + 1]
         fl += 8.0 * (chi * w0 * 2 * r0 * r1 + chi * 2 * w0 * 2 * w1 * r1)
         if l < n - 1:
-            p, m = w1 * r1, 2 * chi
-            s = min(p, m)
-            fl += 8.0 * (2 * max(p, m) * s * s - 2 * s ** 3 / 3)
-            fl += 8.0 * 6 * (s * (s - 1) / 2) * 7 * s
-            chi = yr_zip[l + 1]
+            m, p = 2 * chi, w1 * r1
+            k = yr_zip[l + 1]
+            for i in range(k):
+                fl += 24.0 * (m - i) * (p - i) + 16.0 * (m - i) * k
+            chi = k
     return fl
 
 

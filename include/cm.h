@@ -85,12 +85,21 @@ typedef struct {
   int32_t n_max;           /* host: largest n[b] in the batch                          */
   int32_t dtype;           /* CM_C64 or CM_C128                                        */
   int32_t rank_max;        /* host: largest bond dimension, when known (0 = unknown)   */
-  int32_t reserved;
+  int32_t flags;           /* host: CM_TT_* hints about the cores' canonical form      */
   const int32_t *n;        /* device [batch]                                           */
   int32_t *ranks;          /* device [batch * CM_RANKS_STRIDE]                         */
   const int64_t *core_off; /* device [batch * CM_MAX_N]                                */
   void *cores;             /* device, complex elements of dtype                        */
 } cm_tt_batch;
+
+/* cm_tt_batch.flags (host-side hints, set by the calls that produce a train):
+ *   CM_TT_LEFT_ORTHO  cores 0..n-2 are left-orthonormal (cm_sfft_apply output); cm_tt_round
+ *                     then skips its orthogonalising sweep.
+ *   CM_TT_RIGHT_ORTHO cores 1..n-1 are right-orthonormal (cm_build_qtt, cm_tt_round,
+ *                     cm_qft_mpo output), the form cm_sfft_apply expects of its inputs.
+ * A caller that edits cores must clear the flags. */
+#define CM_TT_LEFT_ORTHO 1
+#define CM_TT_RIGHT_ORTHO 2
 
 /* Operation identifiers for cm_workspace_bytes. */
 enum { CM_OP_QFT_MPO = 0, CM_OP_BUILD_QTT = 1, CM_OP_SFFT_APPLY = 2, CM_OP_TT_ROUND = 3,
@@ -147,7 +156,8 @@ cm_status cm_sfft_apply(const cm_tt_batch *w_by_n, const cm_tt_batch *x, double 
 /* TT rounding (Oseledets 2011; the recompression of Section 3.1) in place: a QR sweep
  * left to right, then truncated SVDs right to left with per-bond threshold
  * tol * ||t|| / sqrt(n-1), bonds <= cap_rank. Afterwards cores 1..n-1 are
- * right-orthonormal. All factorisations in FP64. err_out (device [batch], may be NULL)
+ * right-orthonormal. If t->flags has CM_TT_LEFT_ORTHO the first sweep is skipped (the
+ * cores are already left-orthonormal). All factorisations in FP64. err_out (device [batch], may be NULL)
  * receives the achieved relative Frobenius error bound. status: device [batch].
  * Workspace: cm_workspace_bytes(CM_OP_TT_ROUND, batch, t->n_max, cap_rank, t->dtype). */
 cm_status cm_tt_round(cm_tt_batch *t, double tol, int cap_rank, double *err_out,

@@ -29,6 +29,7 @@ CM_BS, CM_MERTON, CM_HESTON = range(3)
 CM_QUAD_RECT2, CM_QUAD_SIMPSON1 = range(2)
 CM_C64, CM_C128 = range(2)
 CM_OP_QFT_MPO, CM_OP_BUILD_QTT, CM_OP_SFFT_APPLY, CM_OP_TT_ROUND, CM_OP_FFT_PRICE = range(5)
+CM_TT_LEFT_ORTHO, CM_TT_RIGHT_ORTHO = 1, 2
 
 _MODEL = {"bs": CM_BS, "merton": CM_MERTON, "heston": CM_HESTON}
 _QUAD = {"rect2": CM_QUAD_RECT2, "simpson1": CM_QUAD_SIMPSON1}
@@ -44,7 +45,7 @@ assert PROBLEM_DTYPE.itemsize == 128
 class CmTTBatch(C.Structure):
     _fields_ = [
         ("batch", C.c_int32), ("d_out", C.c_int32), ("d_in", C.c_int32), ("cap_rank", C.c_int32),
-        ("n_max", C.c_int32), ("dtype", C.c_int32), ("rank_max", C.c_int32), ("reserved", C.c_int32),
+        ("n_max", C.c_int32), ("dtype", C.c_int32), ("rank_max", C.c_int32), ("flags", C.c_int32),
         ("n", C.c_void_p), ("ranks", C.c_void_p), ("core_off", C.c_void_p), ("cores", C.c_void_p),
     ]
 

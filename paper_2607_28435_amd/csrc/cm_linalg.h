@@ -63,7 +63,7 @@ struct Sh {
 // R lies on and above the diagonal (real diagonal), reflector tails below it, tau[c] in
 // sh.tau. Reflector H_c = I - tau_c v v^H with v = (0..0, 1, Y[c+1:, c]);
 // Q = H_0 H_1 ... H_{s-1}.
-__device__ void qr_householder(double2 *Y, int lda, int m, int s, int ntot, Sh &sh) {
+__device__ __forceinline__ void qr_householder(double2 *Y, int lda, int m, int s, int ntot, Sh &sh) {
   const int tid = threadIdx.x;
   for (int c = 0; c < s; ++c) {
     double part = 0.0;
@@ -117,7 +117,7 @@ __device__ void qr_householder(double2 *Y, int lda, int m, int s, int ntot, Sh &
 }
 
 // Z (m x k, ldz) <- Q Z with Q from qr_householder(Y, lda, m, s).
-__device__ void qr_apply_q(const double2 *Y, int lda, int m, int s, const Sh &sh, double2 *Z, int ldz, int k) {
+__device__ __forceinline__ void qr_apply_q(const double2 *Y, int lda, int m, int s, const Sh &sh, double2 *Z, int ldz, int k) {
   const int tid = threadIdx.x;
   const int G = group_for(k), groups = CM_WG / G, lane = tid % G;
   for (int c = s - 1; c >= 0; --c) {
@@ -148,7 +148,7 @@ __device__ void qr_apply_q(const double2 *Y, int lda, int m, int s, const Sh &sh
 // the rotations in J (s x s, LDS). On return the columns of S are mutually orthogonal,
 // S_in J = S_out, and sh.sig2[i] / sh.perm[i] list squared column norms in descending
 // order. Sets sh.noconv if the sweep limit was reached, sh.nonfinite on NaN/Inf.
-__device__ void jacobi_onesided(double2 *S, double2 *J, int s, Sh &sh) {
+__device__ __forceinline__ void jacobi_onesided(double2 *S, double2 *J, int s, Sh &sh) {
   const int tid = threadIdx.x;
   for (int e = tid; e < s * s; e += CM_WG) J[e] = cmk((e % s) == (e / s) ? 1.0 : 0.0, 0.0);
   if (tid == 0) { sh.noconv = 0; sh.nonfinite = 0; }
@@ -157,8 +157,29 @@ __device__ void jacobi_onesided(double2 *S, double2 *J, int s, Sh &sh) {
   const int npairs = N / 2;
   const int G = group_for(npairs);
   const int lane = tid % G, pi = tid / G;
-  const double tol = 2.3e-16 * (s > 8 ? s : 8);
-  const int max_sweeps = 40;
+  // A pair is rotated while its cosine |<s_p, s_q>| / (|s_p| |s_q|) exceeds 1e-13, far below
+  // any truncation threshold used (singular values then carry relative errors of that
+  // order). Columns below 1e-32 of the largest squared norm are numerically null and are left
+  // alone; the product of two tiny norms is never formed, so nothing underflows.
+  double amax_part = 0.0;
+  if (tid < s) {
+    double a = 0.0;
+    for (int i = 0; i < s; ++i) a += cabs2(S[i + s * tid]);
+    amax_part = a;
+  }
+  __syncthreads();
+  {
+    double v = amax_part;
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    if ((tid & 63) == 0) sh.red[tid >> 6] = v;
+  }
+  __syncthreads();
+  double amax = 0.0;
+  for (int i = 0; i < CM_WG / 64; ++i) amax = fmax(amax, sh.red[i]);
+  __syncthreads();
+  const double null2 = 1e-32 * amax;
+  const double tol = 1e-13;
+  const int max_sweeps = 30;
   int sweep = 0;
   for (; sweep < max_sweeps; ++sweep) {
     if (tid == 0) sh.flag = 0;
@@ -182,26 +203,28 @@ __device__ void jacobi_onesided(double2 *S, double2 *J, int s, Sh &sh) {
       }
       a = grp_sum(a, G); b = grp_sum(b, G); gr = grp_sum(gr, G); gi = grp_sum(gi, G);
       if (p >= 0) {
-        const double ag = sqrt(gr * gr + gi * gi);
-        if (ag > tol * sqrt(a * b) && ag > 1e-300) {
-          const double zeta = (b - a) / (2.0 * ag);
-          const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          const double c = 1.0 / sqrt(1.0 + t * t);
-          const double sn = c * t;
-          const double2 e = cmk(gr / ag, gi / ag);
-          const double2 se = cscale(e, sn);          // s e
-          const double2 sce = cscale(cconj(e), sn);  // s conj(e)
-          for (int i = lane; i < s; i += G) {
-            double2 xp = S[i + s * p], xq = S[i + s * q];
-            S[i + s * p] = csub(cscale(xp, c), cmul(sce, xq));
-            S[i + s * q] = cadd(cmul(se, xp), cscale(xq, c));
-            double2 vp = J[i + s * p], vq = J[i + s * q];
-            J[i + s * p] = csub(cscale(vp, c), cmul(sce, vq));
-            J[i + s * q] = cadd(cmul(se, vp), cscale(vq, c));
-          }
-          if (lane == 0) sh.flag = 1;
-        } else if (!(a == a) || !(b == b)) {
+        if (!(a == a) || !(b == b)) {
           if (lane == 0) sh.nonfinite = 1;
+        } else if (a > null2 && b > null2) {
+          const double ag = sqrt(gr * gr + gi * gi);
+          if (ag > tol * sqrt(a) * sqrt(b)) {
+            const double zeta = (b - a) / (2.0 * ag);
+            const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+            const double c = 1.0 / sqrt(1.0 + t * t);
+            const double sn = c * t;
+            const double2 e = cmk(gr / ag, gi / ag);
+            const double2 se = cscale(e, sn);          // s e
+            const double2 sce = cscale(cconj(e), sn);  // s conj(e)
+            for (int i = lane; i < s; i += G) {
+              double2 xp = S[i + s * p], xq = S[i + s * q];
+              S[i + s * p] = csub(cscale(xp, c), cmul(sce, xq));
+              S[i + s * q] = cadd(cmul(se, xp), cscale(xq, c));
+              double2 vp = J[i + s * p], vq = J[i + s * q];
+              J[i + s * p] = csub(cscale(vp, c), cmul(sce, vq));
+              J[i + s * q] = cadd(cmul(se, vp), cscale(vq, c));
+            }
+            if (lane == 0) sh.flag = 1;
+          }
         }
       }
       __syncthreads();
@@ -264,7 +287,7 @@ __device__ __forceinline__ void choose_rank_t0(Sh &sh, int s, double delta2, int
 //   S, J : LDS, s*s complex each, s = min(a,b) <= 64
 //   L (ld a) and R (ld k) : global outputs.
 // Returns k (uniform).
-__device__ int svd_trunc_rows(double2 *Y, int a, int b, double delta2, int cap,
+__device__ __forceinline__ int svd_trunc_rows(double2 *Y, int a, int b, double delta2, int cap,
                               double2 *X, double2 *Z, double2 *S, double2 *J,
                               double2 *L, double2 *R, Sh &sh) {
   const int tid = threadIdx.x;
@@ -333,7 +356,7 @@ __device__ int svd_trunc_rows(double2 *Y, int a, int b, double delta2, int cap,
 
 // Thin QR: Y (m x p, ld m, destroyed) = Q Rr with Q (m x kq, orthonormal columns) and
 // Rr (kq x p, upper trapezoidal), kq = min(m, p). Q -> Qout (ld m), Rr -> Rout (ld kq).
-__device__ int qr_thin(double2 *Y, int m, int p, double2 *Qout, double2 *Rout, Sh &sh) {
+__device__ __forceinline__ int qr_thin(double2 *Y, int m, int p, double2 *Qout, double2 *Rout, Sh &sh) {
   const int tid = threadIdx.x;
   const int kq = m < p ? m : p;
   qr_householder(Y, m, m, kq, p, sh);
@@ -349,6 +372,154 @@ __device__ int qr_thin(double2 *Y, int m, int p, double2 *Qout, double2 *Rout, S
   __syncthreads();
   qr_apply_q(Y, m, m, kq, sh, Qout, m, kq);
   return kq;
+}
+
+// Truncated column-pivoted Householder QR of T (m x p, column-major ld m, destroyed):
+// T P = Q R. Columns are pivoted by largest remaining norm; the factorisation stops at the
+// first k >= 1 with ||R_22||_F^2 <= delta2 (the exact squared Frobenius norm of what is
+// dropped), or at k = cap (then sh.rankcap is set if the tail still exceeds delta2).
+// Outputs: Qk (m x k, ld m) with orthonormal columns; the k x p factor B = R[:k,:] P^T is
+// written to B (ld k). nrm (p doubles) and perm (p ints) are scratch. Returns k; sh.err2
+// holds the dropped squared norm. p <= 1024.
+__device__ __forceinline__ int cpqr_trunc(double2 *T, int m, int p, double delta2, int cap, double2 *Qk,
+                                          double2 *B, double *nrm, int *perm, Sh &sh) {
+  const int tid = threadIdx.x;
+  const int kmax = m < p ? m : p;
+  // column norms
+  {
+    const int G = group_for(p), groups = CM_WG / G, lane = tid % G;
+    for (int cb = 0; cb < p; cb += groups) {
+      const int c = cb + tid / G;
+      double a = 0.0;
+      if (c < p)
+        for (int r = lane; r < m; r += G) a += cabs2(T[r + (int64_t)m * c]);
+      a = grp_sum(a, G);
+      if (c < p && lane == 0) { nrm[c] = a; perm[c] = c; }
+    }
+  }
+  __shared__ double tail_sh;
+  __shared__ int piv_sh;
+  __shared__ int k_sh;
+  __syncthreads();
+  {
+    double part = 0.0;
+    for (int c = tid; c < p; c += CM_WG) part += nrm[c];
+    const double t = wg_sum(part, sh.red);
+    if (tid == 0) { tail_sh = t; k_sh = 0; sh.rankcap = 0; sh.nonfinite = !(t == t) || isinf(t); }
+    __syncthreads();
+  }
+  for (int i = 0; i < kmax; ++i) {
+    const double tail = tail_sh;
+    if (i >= 1 && tail <= delta2) break;
+    if (i == cap) {
+      if (tid == 0) sh.rankcap = 1;
+      break;
+    }
+    // pivot: argmax nrm[c], c >= i (wave 0)
+    if (tid < 64) {
+      double best = -1.0;
+      int bi = i;
+      for (int c = i + tid; c < p; c += 64) {
+        const double v = nrm[c];
+        if (v > best) { best = v; bi = c; }
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ob = __shfl_xor(best, o, 64);
+        const int oi = __shfl_xor(bi, o, 64);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+      }
+      if (tid == 0) piv_sh = bi;
+    }
+    __syncthreads();
+    const int pv = piv_sh;
+    if (pv != i) {
+      for (int r = tid; r < m; r += CM_WG) {
+        const double2 t = T[r + (int64_t)m * i];
+        T[r + (int64_t)m * i] = T[r + (int64_t)m * pv];
+        T[r + (int64_t)m * pv] = t;
+      }
+      if (tid == 0) {
+        const double t = nrm[i]; nrm[i] = nrm[pv]; nrm[pv] = t;
+        const int q = perm[i]; perm[i] = perm[pv]; perm[pv] = q;
+      }
+    }
+    __syncthreads();
+    // Householder reflector for T[i:m, i]
+    double part = 0.0;
+    for (int r = i + 1 + tid; r < m; r += CM_WG) part += cabs2(T[r + (int64_t)m * i]);
+    const double xn2 = wg_sum(part, sh.red);
+    if (tid == 0) {
+      const double2 a = T[i + (int64_t)m * i];
+      if (xn2 == 0.0 && a.y == 0.0) {
+        sh.tau[i] = cmk(0.0, 0.0);
+        sh.scal = cmk(0.0, 0.0);
+      } else {
+        const double beta = -copysign(sqrt(a.x * a.x + a.y * a.y + xn2), a.x);
+        sh.tau[i] = cmk((beta - a.x) / beta, -a.y / beta);
+        sh.scal = cdiv(cmk(1.0, 0.0), csub(a, cmk(beta, 0.0)));
+        T[i + (int64_t)m * i] = cmk(beta, 0.0);
+      }
+      k_sh = i + 1;
+    }
+    __syncthreads();
+    const double2 tc = sh.tau[i];
+    const bool refl = !(tc.x == 0.0 && tc.y == 0.0);
+    if (refl) {
+      const double2 sc = sh.scal;
+      for (int r = i + 1 + tid; r < m; r += CM_WG) T[r + (int64_t)m * i] = cmul(T[r + (int64_t)m * i], sc);
+      __syncthreads();
+    }
+    // apply H^H to trailing columns; refresh their norms below row i
+    const int ncols = p - i - 1;
+    double tpart = 0.0;
+    if (ncols > 0) {
+      const int G = group_for(ncols), groups = CM_WG / G, lane = tid % G;
+      const double2 ctc = cconj(tc);
+      for (int jb = 0; jb < ncols; jb += groups) {
+        const int j = i + 1 + jb + tid / G;
+        const bool ok = j < p;
+        double2 w = cmk(0.0, 0.0);
+        if (ok && refl) {
+          if (lane == 0) w = T[i + (int64_t)m * j];
+          for (int r = i + 1 + lane; r < m; r += G) ccfma(w, T[r + (int64_t)m * i], T[r + (int64_t)m * j]);
+        }
+        w.x = grp_sum(w.x, G);
+        w.y = grp_sum(w.y, G);
+        double a = 0.0;
+        if (ok) {
+          if (refl) {
+            w = cmul(ctc, w);
+            if (lane == 0) T[i + (int64_t)m * j] = csub(T[i + (int64_t)m * j], w);
+          }
+          for (int r = i + 1 + lane; r < m; r += G) {
+            double2 v = T[r + (int64_t)m * j];
+            if (refl) { v = csub(v, cmul(T[r + (int64_t)m * i], w)); T[r + (int64_t)m * j] = v; }
+            a += cabs2(v);
+          }
+        }
+        a = grp_sum(a, G);
+        if (ok && lane == 0) { nrm[j] = a; tpart += a; }
+      }
+    }
+    const double t = wg_sum(tpart, sh.red);
+    if (tid == 0) tail_sh = t;
+    __syncthreads();
+  }
+  const int k = k_sh;
+  if (tid == 0) sh.err2 = tail_sh;
+  // B = R[:k, :] P^T  (rows r < k; R[r, c] = 0 for r > c)
+  for (int e = tid; e < k * p; e += CM_WG) {
+    const int r = e % k, c = e / k;
+    B[r + (int64_t)k * perm[c]] = (r <= c) ? T[r + (int64_t)m * c] : cmk(0.0, 0.0);
+  }
+  // Qk = H_0 ... H_{k-1} [I_k; 0]
+  for (int e = tid; e < m * k; e += CM_WG) {
+    const int r = e % m, c = e / m;
+    Qk[e] = cmk(r == c ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+  qr_apply_q(T, m, m, k, sh, Qk, m, k);
+  return k;
 }
 
 }  // namespace la

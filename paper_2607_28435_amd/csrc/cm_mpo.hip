@@ -16,7 +16,8 @@
 
 namespace {
 
-constexpr int MP = 24;  // Chebyshev points per interpolated bond
+constexpr int MP = 24;            // Chebyshev points per interpolated bond
+constexpr int MLDS = 128 * 1024;  // LDS arena (the operator is built by a single workgroup)
 
 __host__ __device__ inline size_t align256m(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -29,6 +30,7 @@ __host__ __device__ inline size_t mpo_slab_bytes(int n, int cap, size_t *parts) 
   parts[2] = o; o += align256m(sizeof(int64_t) * CM_MAX_N);
   parts[3] = o; o += align256m(sizeof(double2) * core_cap * n);
   parts[4] = o; o += align256m(sizeof(double2) * core_cap * 6);
+  parts[5] = o; o += align256m(sizeof(double2) * 2 * 64 * 64);
   return o;
 }
 
@@ -65,12 +67,12 @@ __device__ double lagr01(int q, double x, const double *cn) {
 template <typename OutT>
 __global__ __launch_bounds__(CM_WG) void k_qft_mpo(int n, double tol, int cap, TTView w, int slot,
                                                    char *__restrict__ ws, int32_t *__restrict__ code_out) {
-  extern __shared__ double2 dyn[];
+  extern __shared__ __align__(16) char lds_arena[];
   __shared__ la::Sh sh;
   __shared__ double cn[MP];
   __shared__ int code_sh;
   const int tid = threadIdx.x;
-  size_t parts[5];
+  size_t parts[6];
   mpo_slab_bytes(n, cap, parts);
   double2 *pre = (double2 *)(ws + parts[0]);
   int32_t *pre_ranks = (int32_t *)(ws + parts[1]);
@@ -82,6 +84,8 @@ __global__ __launch_bounds__(CM_WG) void k_qft_mpo(int n, double tol, int cap, T
   double2 *mats = (double2 *)(ws + parts[4]);
   rs.Y = mats; rs.X = mats + rs.core_cap; rs.Z = mats + 2 * rs.core_cap;
   rs.L = mats + 3 * rs.core_cap; rs.R = mats + 4 * rs.core_cap; rs.C = mats + 5 * rs.core_cap;
+  rs.S = (double2 *)(ws + parts[5]);
+  rs.J = rs.S + 64 * 64;
   if (tid < MP) cn[tid] = cos(M_PI * tid / (MP - 1));
   if (tid == 0) code_sh = CM_OK;
   for (int l = tid; l <= n; l += CM_WG) pre_ranks[l] = bond_dim(l, n);
@@ -108,14 +112,14 @@ __global__ __launch_bounds__(CM_WG) void k_qft_mpo(int n, double tol, int cap, T
   __syncthreads();
   CoreSrc src;
   src.cores = pre; src.off = pre_off; src.ranks = pre_ranks; src.dtype = CM_C128;
-  round_train<OutT>(n, 4, src, tol, cap, (OutT *)w.cores, w.off + (int64_t)slot * CM_MAX_N, w.rk(slot), rs,
-                    dyn, dyn + 64 * 64, sh, &code_sh);
+  round_train_auto<OutT>(n, 4, src, tol, cap, (OutT *)w.cores, w.off + (int64_t)slot * CM_MAX_N, w.rk(slot), rs,
+                         lds_arena, MLDS, sh, &code_sh);
   __syncthreads();
   if (tid == 0) *code_out = code_sh;
 }
 
 extern "C" size_t cm_mpo_ws_bytes(int n, int cap) {
-  size_t parts[5];
+  size_t parts[6];
   return mpo_slab_bytes(n, cap, parts) + 256;
 }
 
@@ -130,7 +134,7 @@ extern "C" cm_status cm_qft_mpo(int n, double tol, int cap_rank, cm_tt_batch *w,
   // status word lives at the end of the workspace
   int32_t *code_d = (int32_t *)((char *)ws + need - 256);
   TTView v = tt_view(w);
-  const size_t lds = sizeof(double2) * 2 * 64 * 64;
+  const size_t lds = MLDS;
   CM_HIP_CHECK(cm_allow_lds(k_qft_mpo<float2>, lds));
   CM_HIP_CHECK(cm_allow_lds(k_qft_mpo<double2>, lds));
   if (w->dtype == CM_C64)
@@ -147,5 +151,6 @@ extern "C" cm_status cm_qft_mpo(int n, double tol, int cap_rank, cm_tt_batch *w,
   int rmax = 0;
   for (int l = 0; l <= n; ++l) rmax = ranks[l] > rmax ? ranks[l] : rmax;
   if (rmax > w->rank_max) w->rank_max = rmax;
+  w->flags = CM_TT_RIGHT_ORTHO;
   return (cm_status)code;
 }

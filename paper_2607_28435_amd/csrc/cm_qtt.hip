@@ -24,11 +24,12 @@
 
 namespace {
 
-constexpr int QP = 24;          // Chebyshev nodes per polynomial leaf
+constexpr int QP = 16;          // Chebyshev nodes per polynomial leaf
 constexpr int QNC = 64;         // max candidate intervals per depth
 constexpr int QI = QNC / 2;     // max split intervals per depth
 constexpr int QNPT = 2 * QP - 1;
 constexpr int PRE_CAP = QI + QP + 1;   // bond bound before rounding (<= 64)
+constexpr int QLDS = 76 * 1024;        // LDS arena per workgroup (two workgroups per CU)
 
 struct TreeDepth {
   int n_int;                 // split intervals at this depth
@@ -60,6 +61,7 @@ __host__ __device__ inline size_t qtt_slab_bytes(int n_max, int cap, size_t *par
   parts[3] = o; o += align256(sizeof(int64_t) * CM_MAX_N);
   parts[4] = o; o += align256(sizeof(double2) * core_cap * n_max);  // rs.tt
   parts[5] = o; o += align256(sizeof(double2) * core_cap * 6);      // rs.Y..C
+  parts[6] = o; o += align256(sizeof(double2) * 2 * 64 * 64);        // global Jacobi pair
   return o;
 }
 
@@ -115,17 +117,17 @@ __global__ __launch_bounds__(CM_WG) void k_build_qtt(const cm_problem *__restric
                                                      double tol, int cap, TTView x,
                                                      int32_t *__restrict__ status,
                                                      char *__restrict__ ws, size_t slab_bytes, int n_max) {
-  extern __shared__ double2 dyn[];
+  extern __shared__ __align__(16) char lds_arena[];
   __shared__ la::Sh sh;
   __shared__ double cq[QP], ck[QP];
   __shared__ int code_sh;
   __shared__ int8_t kind_sh[QNC];
   __shared__ double err_sh[QNC];
   const int tid = threadIdx.x;
-  // LDS: tree phase uses dyn as vals[QNC][QNPT]; rounding phase uses it as S, J (64x64 each)
-  double2 *vals = dyn;
-  double2 *S = dyn, *J = dyn + 64 * 64;
-  size_t parts[6];
+  // LDS arena: the tree phase keeps candidate values (vals[QNC][QNPT]) there; the rounding
+  // phase reuses it for its matrices
+  double2 *vals = (double2 *)lds_arena;
+  size_t parts[7];
   qtt_slab_bytes(n_max, cap, parts);
   char *slab = ws + (size_t)blockIdx.x * slab_bytes;
   QttSlab W;
@@ -139,6 +141,8 @@ __global__ __launch_bounds__(CM_WG) void k_build_qtt(const cm_problem *__restric
   double2 *mats = (double2 *)(slab + parts[5]);
   W.rs.Y = mats; W.rs.X = mats + W.rs.core_cap; W.rs.Z = mats + 2 * W.rs.core_cap;
   W.rs.L = mats + 3 * W.rs.core_cap; W.rs.R = mats + 4 * W.rs.core_cap; W.rs.C = mats + 5 * W.rs.core_cap;
+  W.rs.S = (double2 *)(slab + parts[6]);
+  W.rs.J = W.rs.S + 64 * 64;
   if (tid < QP) {
     cq[tid] = cos(M_PI * tid / (QP - 1));
     ck[tid] = cos(M_PI * (tid + 0.5) / (QP - 1));
@@ -355,8 +359,8 @@ __global__ __launch_bounds__(CM_WG) void k_build_qtt(const cm_problem *__restric
     CoreSrc src;
     src.cores = W.pre; src.off = W.pre_off; src.ranks = W.pre_ranks; src.dtype = CM_C128;
     OutT *xc = (OutT *)x.cores;
-    const double err = round_train<OutT>(n, 2, src, tol, cap, xc, x.off + (int64_t)b * CM_MAX_N, x.rk(b),
-                                         W.rs, S, J, sh, &code_sh);
+    const double err = round_train_auto<OutT>(n, 2, src, tol, cap, xc, x.off + (int64_t)b * CM_MAX_N, x.rk(b),
+                                              W.rs, lds_arena, QLDS, sh, &code_sh);
     (void)err;
     __syncthreads();
     if (tid == 0 && status) status[b] = code_sh;
@@ -366,7 +370,7 @@ __global__ __launch_bounds__(CM_WG) void k_build_qtt(const cm_problem *__restric
 
 // ------------------------------------------------------------------ host side
 extern "C" size_t cm_qtt_slab_bytes(int n_max, int cap) {
-  size_t parts[6];
+  size_t parts[7];
   return qtt_slab_bytes(n_max, cap, parts);
 }
 
@@ -384,7 +388,8 @@ extern "C" cm_status cm_build_qtt(const cm_problem *prob, int batch, double tol,
   if (!ws || ws_bytes < need) return CM_E_INVALID;
   const int slots = cm_slots_for(batch);
   const size_t slab = cm_qtt_slab_bytes(x->n_max, cap_rank);
-  const size_t lds = sizeof(double2) * (size_t)(QNC * QNPT > 2 * 64 * 64 ? QNC * QNPT : 2 * 64 * 64);
+  const size_t lds = QLDS;
+  static_assert(sizeof(double2) * QNC * QNPT <= QLDS, "tree values must fit the LDS arena");
   TTView v = tt_view(x);
   hipStream_t s = (hipStream_t)stream;
   CM_HIP_CHECK(cm_allow_lds(k_build_qtt<float2>, lds));
@@ -396,5 +401,6 @@ extern "C" cm_status cm_build_qtt(const cm_problem *prob, int batch, double tol,
     hipLaunchKernelGGL(k_build_qtt<double2>, dim3(slots), dim3(CM_WG), lds, s, prob, batch, tol, cap_rank, v,
                        status, (char *)ws, slab, x->n_max);
   CM_LAUNCH_CHECK();
+  x->flags = CM_TT_RIGHT_ORTHO;
   return CM_OK;
 }

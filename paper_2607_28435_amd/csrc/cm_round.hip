@@ -4,17 +4,20 @@
 
 namespace {
 __host__ __device__ inline size_t al256r(size_t x) { return (x + 255) & ~(size_t)255; }
+constexpr int RLDS = 76 * 1024;  // LDS arena per workgroup (two workgroups per CU)
 __host__ __device__ inline size_t round_slab_bytes(int n_max, int d, int cap) {
   const size_t core_cap = (size_t)cap * d * cap;
-  return al256r(sizeof(double2) * core_cap * n_max) + al256r(sizeof(double2) * core_cap * 6);
+  return al256r(sizeof(double2) * core_cap * n_max) + al256r(sizeof(double2) * core_cap * 6) +
+         al256r(sizeof(double2) * 2 * 64 * 64);
 }
 }  // namespace
 
 template <typename T>
 __global__ __launch_bounds__(CM_WG) void k_tt_round(TTView t, int batch, double tol, int cap, int incap,
                                                     double *__restrict__ err_out, int32_t *__restrict__ status,
-                                                    char *__restrict__ ws, size_t slab_bytes, int n_max, int dtype) {
-  extern __shared__ double2 dyn[];
+                                                    char *__restrict__ ws, size_t slab_bytes, int n_max, int dtype,
+                                                    int skip_a) {
+  extern __shared__ __align__(16) char lds_arena[];
   __shared__ la::Sh sh;
   __shared__ int code_sh;
   const int tid = threadIdx.x;
@@ -25,6 +28,8 @@ __global__ __launch_bounds__(CM_WG) void k_tt_round(TTView t, int batch, double 
   double2 *mats = (double2 *)(slab + al256r(sizeof(double2) * rs.core_cap * n_max));
   rs.Y = mats; rs.X = mats + rs.core_cap; rs.Z = mats + 2 * rs.core_cap;
   rs.L = mats + 3 * rs.core_cap; rs.R = mats + 4 * rs.core_cap; rs.C = mats + 5 * rs.core_cap;
+  rs.S = (double2 *)((char *)mats + al256r(sizeof(double2) * rs.core_cap * 6));
+  rs.J = rs.S + 64 * 64;
   for (int b = blockIdx.x; b < batch; b += gridDim.x) {
     const int n = t.n[b];
     if (tid == 0) {
@@ -43,8 +48,8 @@ __global__ __launch_bounds__(CM_WG) void k_tt_round(TTView t, int batch, double 
     }
     CoreSrc src;
     src.cores = t.cores; src.off = t.off + (int64_t)b * CM_MAX_N; src.ranks = t.rk(b); src.dtype = dtype;
-    const double e = round_train<T>(n, t.d, src, tol, cap, (T *)t.cores, t.off + (int64_t)b * CM_MAX_N, t.rk(b), rs,
-                                    dyn, dyn + 64 * 64, sh, &code_sh);
+    const double e = round_train_auto<T>(n, t.d, src, tol, cap, (T *)t.cores, t.off + (int64_t)b * CM_MAX_N,
+                                         t.rk(b), rs, lds_arena, RLDS, sh, &code_sh, skip_a != 0);
     __syncthreads();
     if (tid == 0) {
       if (status) status[b] = code_sh;
@@ -70,17 +75,19 @@ extern "C" cm_status cm_tt_round(cm_tt_batch *t, double tol, int cap_rank, doubl
   const int d = t->d_out * t->d_in;
   const int slots = cm_slots_for(t->batch);
   const size_t slab = round_slab_bytes(t->n_max, d, t->cap_rank);
-  const size_t lds = sizeof(double2) * 2 * 64 * 64;
+  const size_t lds = RLDS;
   TTView v = tt_view(t);
   hipStream_t s = (hipStream_t)stream;
+  const int skip = (t->flags & CM_TT_LEFT_ORTHO) ? 1 : 0;
   CM_HIP_CHECK(cm_allow_lds(k_tt_round<float2>, lds));
   CM_HIP_CHECK(cm_allow_lds(k_tt_round<double2>, lds));
   if (t->dtype == CM_C64)
     hipLaunchKernelGGL(k_tt_round<float2>, dim3(slots), dim3(CM_WG), lds, s, v, t->batch, tol, cap_rank, t->cap_rank,
-                       err_out, status, (char *)ws, slab, t->n_max, t->dtype);
+                       err_out, status, (char *)ws, slab, t->n_max, t->dtype, skip);
   else
     hipLaunchKernelGGL(k_tt_round<double2>, dim3(slots), dim3(CM_WG), lds, s, v, t->batch, tol, cap_rank, t->cap_rank,
-                       err_out, status, (char *)ws, slab, t->n_max, t->dtype);
+                       err_out, status, (char *)ws, slab, t->n_max, t->dtype, skip);
   CM_LAUNCH_CHECK();
+  t->flags = CM_TT_RIGHT_ORTHO;
   return CM_OK;
 }

@@ -47,6 +47,7 @@ struct RoundScratch {
   double2 *tt;
   int64_t core_cap;
   double2 *Y, *X, *Z, *L, *R, *C;
+  double2 *S, *J;  // global fallback for the Jacobi pair (64 x 64 each)
 };
 
 // Source train for the rounding sweep: core l element (t, ph, j) is at
@@ -78,18 +79,28 @@ __device__ __forceinline__ void merge_flags(const la::Sh &sh, int *code) {
 // writes). Returns the relative Frobenius error bound; *code receives a cm_status (thread 0
 // writes; first error wins).
 template <typename OutT>
-__device__ double round_train(int n, int d, const CoreSrc &src, double tol, int cap,
+__device__ __forceinline__ double round_train(int n, int d, const CoreSrc &src, double tol, int cap,
                               OutT *dst_cores, const int64_t *dst_off, int32_t *dst_ranks,
                               const RoundScratch &w, double2 *S, double2 *J, la::Sh &sh,
-                              int *code) {
+                              int *code, bool skip_a = false) {
   const int tid = threadIdx.x;
   __shared__ int rk[CM_MAX_N + 1];
   __shared__ double norm2_sh;
   if (tid == 0) { rk[0] = 1; norm2_sh = 0.0; w.C[0] = cmk(1.0, 0.0); }
   __syncthreads();
-  // ---- phase A: carry C (kprev x r_l, ld kprev), starts as [1]
+  // ---- phase A: carry C (kprev x r_l, ld kprev), starts as [1]. Skipped when the source
+  // cores 0..n-2 are already left-orthonormal; then only the norm of the last core is needed.
+  if (skip_a) {
+    const int rl = src.ranks[n - 1];
+    double part = 0.0;
+    for (int e = tid; e < rl * d; e += CM_WG) part += cabs2(src.get(n - 1, e));
+    const double nrm2 = la::wg_sum(part, sh.red);
+    if (tid == 0) norm2_sh = nrm2;
+    for (int l = tid; l <= n; l += CM_WG) rk[l] = src.ranks[l];
+    __syncthreads();
+  }
   int kprev = 1;
-  for (int l = 0; l < n; ++l) {
+  for (int l = 0; l < n && !skip_a; ++l) {
     const int rl = src.ranks[l], rr = src.ranks[l + 1];
     const int rows = kprev * d;
     for (int e = tid; e < rows * rr; e += CM_WG) {
@@ -136,8 +147,11 @@ __device__ double round_train(int n, int d, const CoreSrc &src, double tol, int 
       const int i = e % kl, c = e / kl;
       const int ph = c / rpp, j = c % rpp;
       double2 acc = cmk(0.0, 0.0);
-      for (int t = 0; t < kr; ++t)
-        cfma(acc, core[(i * d + ph) + (int64_t)(kl * d) * t], w.C[t + kr * j]);
+      if (skip_a) {
+        for (int t = 0; t < kr; ++t) cfma(acc, src.get(l, ((int64_t)i * d + ph) * kr + t), w.C[t + kr * j]);
+      } else {
+        for (int t = 0; t < kr; ++t) cfma(acc, core[(i * d + ph) + (int64_t)(kl * d) * t], w.C[t + kr * j]);
+      }
       w.Y[e] = acc;
     }
     __syncthreads();
@@ -167,4 +181,34 @@ __device__ double round_train(int n, int d, const CoreSrc &src, double tol, int 
   if (tid == 0) dst_ranks[n] = 1;
   __syncthreads();
   return sqrt(err2) / (nrm > 0 ? nrm : 1.0);
+}
+
+// round_train with the hot matrices (Y, X, Z and the Jacobi pair) in the LDS arena when the
+// train's largest bond allows it, and in the global scratch otherwise.
+template <typename OutT>
+__device__ __forceinline__ double round_train_auto(int n, int d, const CoreSrc &src, double tol, int cap,
+                                                   OutT *dst_cores, const int64_t *dst_off, int32_t *dst_ranks,
+                                                   const RoundScratch &wg, char *arena, size_t arena_bytes,
+                                                   la::Sh &sh, int *code, bool skip_a = false) {
+  __shared__ int rmax_sh;
+  if (threadIdx.x == 0) {
+    int r = 1;
+    for (int l = 0; l <= n; ++l) r = src.ranks[l] > r ? src.ranks[l] : r;
+    rmax_sh = r;
+  }
+  __syncthreads();
+  const int64_t rmax = rmax_sh;
+  const int64_t mat = rmax * d * rmax;
+  const size_t need = sizeof(double2) * (size_t)(3 * mat + 3 * rmax * rmax);
+  if (need <= arena_bytes && rmax <= 64) {
+    RoundScratch w = wg;
+    w.Y = (double2 *)arena;
+    w.X = w.Y + mat;
+    w.Z = w.X + mat;
+    double2 *S = w.Z + mat;
+    double2 *J = S + rmax * rmax;
+    w.C = J + rmax * rmax;
+    return round_train<OutT>(n, d, src, tol, cap, dst_cores, dst_off, dst_ranks, w, S, J, sh, code, skip_a);
+  }
+  return round_train<OutT>(n, d, src, tol, cap, dst_cores, dst_off, dst_ranks, wg, wg.S, wg.J, sh, code, skip_a);
 }

@@ -1,40 +1,45 @@
 // cm_sfft_apply: y = Q_n x by a left-to-right zip-up (Section 3.2-3.3; cost per site
-// O(chi w r (r' + w' chi)) plus an FP64 factorisation, linear in n as in Eq. complexity_TTO).
+// O(chi w r (r' + w' chi)) for the contraction plus an FP64 factorisation, linear in n as in
+// Eq. complexity_TTO).
 //
 // Site l receives the carry C[chi][w][r] (the already-truncated left part of y, contracted
 // with the open operator bond w and input bond r), forms
-//   T[chi][u][w'][r'] = sum_{w, j, r} C[chi][w][r] A_l[r][j][r'] W_l[w][u][j][w'],
-// and factors T as a (2 chi) x (w' r') matrix: T ~= U_k B with orthonormal U_k (the output
-// core) and B the next carry. Truncation keeps the smallest k whose discarded singular
-// values have squared sum <= tol^2 ||x||^2 / (n-1). With both operator and input in
+//   T[(chi, u)][(w', r')] = sum_{w, j, r} C[chi][w][r] A_l[r][j][r'] W_l[w][u][j][w'],
+// and factors the (2 chi) x (w' r') matrix T by Householder QR with column pivoting,
+// stopping as soon as the dropped block's Frobenius norm is below tol ||x|| / sqrt(n-1).
+// Q (orthonormal) is the output core, R P^T the next carry. With operator and input in
 // right-canonical form the right environment is close to orthonormal, so this per-step
-// truncation is accurate; a following cm_tt_round makes the ranks optimal.
-// The contraction runs in the storage precision (FP32 complex for CM_C64); the
-// Householder QR and Jacobi SVD run in FP64.
+// truncation is accurate; the following cm_tt_round makes the ranks optimal with SVDs.
+// The contraction runs in the storage precision (FP32 complex for CM_C64); the pivoted QR
+// runs in FP64. Per-site matrices live in LDS when they fit (the common case), otherwise in
+// the workgroup's global slab.
 #include "cm_tt.h"
 
 namespace {
 
-constexpr int ZCHI = 32;   // zip-up bond limit (Jacobi size 2*ZCHI <= 64)
-constexpr int ZW = 24;     // largest operator bond supported by the workspace layout
+constexpr int ZCHI = 32;          // zip-up bond limit
+constexpr int ZW = 24;            // largest operator bond supported by the workspace layout
+constexpr int ZLDS = 72 * 1024;   // LDS arena per workgroup (two workgroups per CU)
 
 __host__ __device__ inline size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// global per-workgroup slab: carry C (FP64), D (storage), and the fallback arena
 __host__ __device__ inline size_t zip_mat_cap(int cap) {
   const int chi = cap < ZCHI ? cap : ZCHI;
   return (size_t)2 * chi * ZW * cap;
 }
-
+__host__ __device__ inline size_t zip_arena_bytes(int cap) {
+  const int chi = cap < ZCHI ? cap : ZCHI;
+  const size_t m = 2 * chi, p = (size_t)ZW * cap;
+  return al256(16 * m * p) + al256(16 * m * (m < p ? m : p)) + al256(8 * p) + al256(4 * p) +
+         al256(16 * (size_t)ZW * 4 * ZW) + al256(16 * (size_t)cap * 2 * cap);
+}
 __host__ __device__ inline size_t zip_slab_bytes(int cap, size_t *parts) {
   const size_t mc = zip_mat_cap(cap);
   size_t o = 0;
   parts[0] = o; o += al256(sizeof(double2) * mc);   // carry C
-  parts[1] = o; o += al256(sizeof(double2) * mc);   // D (storage type, sized for FP64)
-  parts[2] = o; o += al256(sizeof(double2) * mc);   // Y
-  parts[3] = o; o += al256(sizeof(double2) * mc);   // X
-  parts[4] = o; o += al256(sizeof(double2) * mc);   // Z
-  parts[5] = o; o += al256(sizeof(double2) * mc);   // L
-  parts[6] = o; o += al256(sizeof(double2) * mc);   // R
+  parts[1] = o; o += al256(sizeof(double2) * mc);   // D
+  parts[2] = o; o += zip_arena_bytes(cap);          // fallback arena
   return o;
 }
 
@@ -54,29 +59,112 @@ template <> struct acc_t<double2> {
   __device__ __forceinline__ static double2 to(double2 v) { return v; }
 };
 
+struct SiteDims {
+  int chi, w0, w1, r0, r1;
+};
+
+// Arena layout for one site (byte offsets).
+__host__ __device__ inline size_t site_bytes(const SiteDims &s, size_t *o) {
+  const size_t m = 2 * s.chi, p = (size_t)s.w1 * s.r1;
+  size_t x = 0;
+  o[0] = x; x += al256(16 * m * p);                   // T (FP64)
+  o[1] = x; x += al256(16 * m * (m < p ? m : p));     // Qk (FP64)
+  o[2] = x; x += al256(8 * p);                        // column norms
+  o[3] = x; x += al256(4 * p);                        // permutation
+  o[4] = x; x += al256(16 * (size_t)s.w0 * 4 * s.w1); // operator core
+  o[5] = x; x += al256(16 * (size_t)s.r0 * 2 * s.r1); // input core
+  return x;
+}
+
+// One zip-up site; `arena` is LDS or global memory (the caller specialises the call so that
+// LDS accesses compile to LDS instructions).
+template <typename T>
+__device__ __forceinline__ int zip_site(char *arena, const SiteDims &sd, const T *__restrict__ Wl,
+                                        const T *__restrict__ Al, double2 *C, T *D, T *Yout, bool last,
+                                        double delta2, int kcap, la::Sh &sh, int *code) {
+  using A = acc_t<T>;
+  const int tid = threadIdx.x;
+  size_t o[6];
+  site_bytes(sd, o);
+  double2 *Tm = (double2 *)(arena + o[0]);
+  double2 *Qk = (double2 *)(arena + o[1]);
+  double *nrm = (double *)(arena + o[2]);
+  int *perm = (int *)(arena + o[3]);
+  T *Wc = (T *)(arena + o[4]);
+  T *Ac = (T *)(arena + o[5]);
+  const int chi = sd.chi, w0 = sd.w0, w1 = sd.w1, r0 = sd.r0, r1 = sd.r1;
+  const int m = 2 * chi, p = w1 * r1;
+  for (int e = tid; e < w0 * 4 * w1; e += CM_WG) Wc[e] = Wl[e];
+  for (int e = tid; e < r0 * 2 * r1; e += CM_WG) Ac[e] = Al[e];
+  __syncthreads();
+  // D[chi][w0][j][r1] = sum_r C[chi][w0][r] A[r][j][r1]
+  for (int e = tid; e < chi * w0 * 2 * r1; e += CM_WG) {
+    const int rp = e % r1, j = (e / r1) & 1, ww = (e / (2 * r1)) % w0, ch = e / (2 * r1 * w0);
+    typename A::type acc = A::zero();
+    const double2 *crow = C + ((int64_t)ch * w0 + ww) * r0;
+    for (int r = 0; r < r0; ++r) A::fma_(acc, A::from(crow[r]), Ac[(r * 2 + j) * r1 + rp]);
+    D[e] = acc;
+  }
+  __syncthreads();
+  // T[(ch, u)][(wp, rp)] = sum_{w0, j} D[ch][w0][j][rp] W[w0][u][j][wp]
+  for (int e = tid; e < m * p; e += CM_WG) {
+    const int row = e % m, col = e / m;
+    const int ch = row >> 1, u = row & 1, wp = col / r1, rp = col % r1;
+    typename A::type acc = A::zero();
+    const T *dd = D + ((int64_t)ch * w0 * 2) * r1 + rp;
+    const T *wl = Wc + (u * 2) * w1 + wp;
+    for (int ww = 0; ww < w0; ++ww) {
+      A::fma_(acc, dd[(ww * 2) * r1], wl[(ww * 4) * w1]);
+      A::fma_(acc, dd[(ww * 2 + 1) * r1], wl[(ww * 4 + 1) * w1]);
+    }
+    Tm[e] = A::to(acc);
+  }
+  __syncthreads();
+  if (last) {
+    // p == 1: output core (chi x 2 x 1)
+    for (int e = tid; e < m; e += CM_WG) cstore<T>::st(Yout, e, Tm[e]);
+    __syncthreads();
+    return 1;
+  }
+  // pivoted QR; B = R P^T (k x p, column-major ld k) lands in C
+  const int k = la::cpqr_trunc(Tm, m, p, delta2, kcap, Qk, C, nrm, perm, sh);
+  if (tid == 0) {
+    if (sh.rankcap && *code == CM_OK) *code = CM_E_RANKCAP;
+    if (sh.nonfinite && *code == CM_OK) *code = CM_E_NONFINITE;
+  }
+  // output core l = Qk as [chi][u][k]
+  for (int e = tid; e < m * k; e += CM_WG) {
+    const int row = e % m, i = e / m;
+    cstore<T>::st(Yout, (int64_t)row * k + i, Qk[row + (int64_t)m * i]);
+  }
+  // carry for the next site as row-major [k][w1][r1]: transpose B through the (now free) T
+  for (int e = tid; e < k * p; e += CM_WG) Tm[e] = C[e];
+  __syncthreads();
+  for (int e = tid; e < k * p; e += CM_WG) {
+    const int i = e / p, col = e % p;
+    C[e] = Tm[i + (int64_t)k * col];
+  }
+  __syncthreads();
+  return k;
+}
+
 }  // namespace
 
 template <typename T>
 __global__ __launch_bounds__(CM_WG) void k_zipup(TTView w, TTView x, TTView y, double tol, int cap,
                                                  int batch, int32_t *__restrict__ status,
                                                  char *__restrict__ ws, size_t slab_bytes, int64_t mat_cap) {
-  using A = acc_t<T>;
-  extern __shared__ double2 dyn[];
+  extern __shared__ __align__(16) char lds_arena[];
   __shared__ la::Sh sh;
   __shared__ int code_sh;
   __shared__ double xn2_sh;
   const int tid = threadIdx.x;
-  double2 *S = dyn, *J = dyn + 64 * 64;
-  size_t parts[7];
+  size_t parts[3];
   zip_slab_bytes(cap, parts);
   char *slab = ws + (size_t)blockIdx.x * slab_bytes;
   double2 *C = (double2 *)(slab + parts[0]);
   T *D = (T *)(slab + parts[1]);
-  double2 *Y = (double2 *)(slab + parts[2]);
-  double2 *X = (double2 *)(slab + parts[3]);
-  double2 *Z = (double2 *)(slab + parts[4]);
-  double2 *Lm = (double2 *)(slab + parts[5]);
-  double2 *Rm = (double2 *)(slab + parts[6]);
+  char *garena = slab + parts[2];
   const int chicap = cap < ZCHI ? cap : ZCHI;
   const T *Wc = (const T *)w.cores;
   const T *Xc = (const T *)x.cores;
@@ -97,7 +185,6 @@ __global__ __launch_bounds__(CM_WG) void k_zipup(TTView w, TTView x, TTView y, d
     }
     const int32_t *wr = w.rk(n);
     const int32_t *xr = x.rk(b);
-    // ||x|| from core 0 (x is right-canonical)
     {
       const int cnt = 2 * xr[1];
       double part = 0.0;
@@ -111,68 +198,32 @@ __global__ __launch_bounds__(CM_WG) void k_zipup(TTView w, TTView x, TTView y, d
     __syncthreads();
     int chi = 1;
     for (int l = 0; l < n; ++l) {
-      const int w0 = wr[l], w1 = wr[l + 1];
-      const int r0 = xr[l], r1 = xr[l + 1];
-      const int rows = 2 * chi, cols = w1 * r1;
-      if ((int64_t)chi * w0 * 2 * r1 > mat_cap || (int64_t)rows * cols > mat_cap || w0 > ZW || w1 > ZW) {
+      SiteDims sd;
+      sd.chi = chi; sd.w0 = wr[l]; sd.w1 = wr[l + 1]; sd.r0 = xr[l]; sd.r1 = xr[l + 1];
+      const int m = 2 * chi, p = sd.w1 * sd.r1;
+      if ((int64_t)chi * sd.w0 * 2 * sd.r1 > mat_cap || (int64_t)m * p > mat_cap || sd.w0 > ZW || sd.w1 > ZW ||
+          sd.r0 > cap || sd.r1 > cap) {
         if (tid == 0) code_sh = CM_E_RANKCAP;
         __syncthreads();
         break;
       }
-      const T *Wl = Wc + w.coff(n, l);   // [w0][2 u][2 j][w1]
-      const T *Al = Xc + x.coff(b, l);   // [r0][2 j][r1]
-      // D[chi][w0][j][r1] = sum_r C[chi][w0][r] A[r][j][r1]  (C row-major [chi][w0][r0])
-      for (int e = tid; e < chi * w0 * 2 * r1; e += CM_WG) {
-        const int rp = e % r1, j = (e / r1) & 1, ww = (e / (2 * r1)) % w0, ch = e / (2 * r1 * w0);
-        typename A::type acc = A::zero();
-        const double2 *crow = C + ((int64_t)ch * w0 + ww) * r0;
-        for (int r = 0; r < r0; ++r) A::fma_(acc, A::from(crow[r]), Al[((int64_t)r * 2 + j) * r1 + rp]);
-        D[e] = acc;
-      }
-      __syncthreads();
-      // T[chi][u][w1][r1] = sum_{w0, j} D[chi][w0][j][r1] W[w0][u][j][w1]
-      T *Yout = Yc + y.coff(b, l);
+      size_t o[6];
+      const size_t need = site_bytes(sd, o);
       const bool last = (l == n - 1);
-      for (int e = tid; e < rows * cols; e += CM_WG) {
-        const int rp = e % r1, wp = (e / r1) % w1, u = (e / cols) & 1, ch = e / (2 * cols);
-        typename A::type acc = A::zero();
-        for (int ww = 0; ww < w0; ++ww) {
-          const T *dd = D + (((int64_t)ch * w0 + ww) * 2) * r1 + rp;
-          const T *wl = Wl + (((int64_t)ww * 2 + u) * 2) * w1 + wp;
-          A::fma_(acc, dd[0], wl[0]);
-          A::fma_(acc, dd[r1], wl[w1]);
-        }
-        const double2 tv = A::to(acc);
-        if (last) {
-          // cols == 1: output core (chi x 2 x 1)
-          cstore<T>::st(Yout, (int64_t)ch * 2 + u, tv);
-        } else {
-          // Y = T^H as (cols x rows), column-major ld cols
-          const int row = ch * 2 + u, col = wp * r1 + rp;
-          Y[col + (int64_t)cols * row] = cconj(tv);
-        }
+      const T *Wl = Wc + w.coff(n, l);
+      const T *Al = Xc + x.coff(b, l);
+      T *Yout = Yc + y.coff(b, l);
+      int k;
+      if (need <= (size_t)ZLDS)
+        k = zip_site<T>(lds_arena, sd, Wl, Al, C, D, Yout, last, delta2, chicap, sh, &code_sh);
+      else
+        k = zip_site<T>(garena, sd, Wl, Al, C, D, Yout, last, delta2, chicap, sh, &code_sh);
+      if (tid == 0) {
+        if (last) { y.rk(b)[l] = chi; y.rk(b)[l + 1] = 1; }
+        else y.rk(b)[l + 1] = k;
       }
       __syncthreads();
-      if (last) {
-        if (tid == 0) { y.rk(b)[l] = chi; y.rk(b)[l + 1] = 1; }
-        __syncthreads();
-        break;
-      }
-      // Y (cols x rows) ~= L Rk ; T ~= Rk^H L^H
-      const int k = la::svd_trunc_rows(Y, cols, rows, delta2, chicap, X, Z, S, J, Lm, Rm, sh);
-      merge_flags(sh, &code_sh);
-      // output core l = Rk^H : (rows x k) as [chi][u][k]
-      for (int e = tid; e < rows * k; e += CM_WG) {
-        const int i = e % k, row = e / k;
-        cstore<T>::st(Yout, (int64_t)row * k + i, cconj(Rm[i + (int64_t)k * row]));
-      }
-      // next carry C[k][w1][r1] = L^H  (L is cols x k, ld cols)
-      for (int e = tid; e < k * cols; e += CM_WG) {
-        const int col = e % cols, i = e / cols;
-        C[(int64_t)i * cols + col] = cconj(Lm[col + (int64_t)cols * i]);
-      }
-      if (tid == 0) y.rk(b)[l + 1] = k;
-      __syncthreads();
+      if (last) break;
       chi = k;
     }
     if (tid == 0 && status) status[b] = code_sh;
@@ -181,7 +232,7 @@ __global__ __launch_bounds__(CM_WG) void k_zipup(TTView w, TTView x, TTView y, d
 }
 
 extern "C" size_t cm_zip_slab_bytes(int cap) {
-  size_t parts[7];
+  size_t parts[3];
   return zip_slab_bytes(cap, parts);
 }
 
@@ -204,7 +255,7 @@ extern "C" cm_status cm_sfft_apply(const cm_tt_batch *w_by_n, const cm_tt_batch 
   const int slots = cm_slots_for(batch);
   const size_t slab = cm_zip_slab_bytes(cap_rank);
   const int64_t mc = (int64_t)zip_mat_cap(cap_rank);
-  const size_t lds = sizeof(double2) * 2 * 64 * 64;
+  const size_t lds = ZLDS;
   hipStream_t s = (hipStream_t)stream;
   TTView vw = tt_view(w_by_n), vx = tt_view(x), vy = tt_view(y);
   CM_HIP_CHECK(cm_allow_lds(k_zipup<float2>, lds));
@@ -216,5 +267,6 @@ extern "C" cm_status cm_sfft_apply(const cm_tt_batch *w_by_n, const cm_tt_batch 
     hipLaunchKernelGGL(k_zipup<double2>, dim3(slots), dim3(CM_WG), lds, s, vw, vx, vy, tol, cap_rank, batch, status,
                        (char *)ws, slab, mc);
   CM_LAUNCH_CHECK();
+  y->flags = CM_TT_LEFT_ORTHO;
   return CM_OK;
 }
