@@ -172,12 +172,15 @@ cm_status cm_tt_round(cm_tt_batch *t, double tol, int cap_rank, double *err_out,
 cm_status cm_readout_prices(const cm_tt_batch *y, const cm_problem *prob, const int64_t *strike_idx,
                             int nk, double *prices, int32_t *status, void *stream);
 
-/* Dense Carr–Madan baseline: evaluates x (Eq. x) on all M = 2^n points inside the first
- * FFT pass, applies the minus-sign DFT with a Stockham FFT in the storage precision, and
- * applies the readout scalars in the last pass. Every problem must have prob[b].n == n
- * (n <= 30). If strike_idx is NULL, prices is [batch][M]; otherwise strike_idx is device
- * int64 [batch][nk] and prices is [batch][nk] (gathered). prices holds float for CM_C64 and
- * double for CM_C128. status: device [batch] (may be NULL).
+/* Dense Carr–Madan baseline (Section 2.1): evaluates x (Eq. x) inside the first FFT pass,
+ * applies the minus-sign DFT of Eq. dft with a Stockham FFT in the storage precision, and
+ * applies the readout scalars of Eq. discretization_dft in the last pass. x_j is set to
+ * exactly zero where |psi| lies below 1e-16 (CM_C64) or 1e-32 (CM_C128) times |psi(0)|, a
+ * per-problem cut-off found once by scanning |psi| outward. Every problem must have
+ * prob[b].n == n (n <= 30, batch <= 65535). If strike_idx is NULL, prices is [batch][M];
+ * otherwise strike_idx is device int64 [batch][nk] and prices is [batch][nk] (gathered).
+ * prices holds float for CM_C64 and double for CM_C128. status: device [batch] (may be
+ * NULL); a problem that fails its checks gets its code there and NaN prices.
  * Workspace: cm_workspace_bytes(CM_OP_FFT_PRICE, batch, n, 0, dtype). */
 cm_status cm_fft_price(const cm_problem *prob, int batch, int n, int dtype, const int64_t *strike_idx,
                        int nk, void *prices, int32_t *status, void *ws, size_t ws_bytes, void *stream);

@@ -158,6 +158,34 @@ def test_paper_grid_statevector_pin_through_gpu():
     assert e < 1e-13
 
 
+def test_dense_fft_fp64_batched_multi_instance_launch():
+    """Four instances in one launch (n = 20, two passes): every instance against the oracle's
+    direct DFT on strikes strided over 0.5 <= K/S0 <= 1.5."""
+    probs = W.heston_batch(4, seed=11, n=20)
+    got, st = cm.dense_prices(probs, cm.CM_C128)
+    assert np.all(st.cpu().numpy() == cm.CM_OK)
+    got = got.cpu().numpy()
+    for b, p in enumerate(probs):
+        u = W.window_strided(p, 256)
+        ref = O.prices_direct(p, u)
+        assert np.abs(got[b, u] - ref).max() / p.S0 < FP64_TOL
+
+
+def test_dense_fft_failed_problem_is_nan():
+    """A problem that fails its checks gets its status code and NaN prices; its neighbours in
+    the batch are unaffected."""
+    good = W.bs_simpson_n12()
+    bad = good.replace(params=(-0.2,))
+    got, st = cm.dense_prices([good, bad, good], cm.CM_C128)
+    st = st.cpu().numpy()
+    got = got.cpu().numpy()
+    assert list(st) == [cm.CM_OK, cm.CM_E_INVALID, cm.CM_OK]
+    assert np.isnan(got[1]).all()
+    ref = O.prices_dense(good)
+    for b in (0, 2):
+        assert np.all(np.abs(got[b] - ref) <= FP64_TOL * good.S0 + 1e-12 * np.abs(ref))
+
+
 # ------------------------------------------------------------------ complex64 paths
 
 def test_heston_n24_c64_sfft_and_dense_vs_oracle():
@@ -176,6 +204,21 @@ def test_heston_n24_c64_sfft_and_dense_vs_oracle():
     e_dense = np.abs(dense.cpu().numpy()[0] - ref).max() / p.S0
     say("errors sfft", e_sfft, "dense", e_dense)
     assert e_sfft < C64_TOL and e_dense < C64_TOL
+
+
+def test_dense_c64_heston_batch_n24_support_cut():
+    """Eight seeded Heston draws at n = 24 through the complex64 dense path (integrand cut to
+    its numerical support, maturities down to the box's shortest): sampled strikes over
+    0.5 <= K/S0 <= 1.5 against the FP64 oracle."""
+    probs = W.heston_batch(8, seed=5, n=24)
+    got, st = cm.dense_prices(probs, cm.CM_C64)
+    assert np.all(st.cpu().numpy() == cm.CM_OK)
+    for b, p in enumerate(probs):
+        u = W.window_strided(p, 128)
+        ref = O.prices_direct(p, u)
+        e = np.abs(got[b, torch.from_numpy(u).cuda()].double().cpu().numpy() - ref).max() / p.S0
+        say("dense c64 n24 instance", b, "T", round(p.T, 3), "err", e)
+        assert e < C64_TOL
 
 
 def test_batched_heston_ragged_c64():
