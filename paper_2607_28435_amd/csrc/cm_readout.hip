@@ -2,9 +2,13 @@
 //
 // Output core l carries log-strike bit 2^l (the bit reversal of Section 3.2 is absorbed
 // in the index map), so y_u = Y_0[0, u_0, :] Y_1[:, u_1, :] ... Y_{n-1}[:, u_{n-1}, 0].
-// A lane group of width RW (a power of two >= the bond cap) holds one strike's vector;
-// each lane owns one bond component and the vector is contracted from the right, core by
-// core, through LDS. The price is
+// k_readout: one lane per strike. The instance's cores are staged once per workgroup into
+// LDS (when they fit), and each lane contracts its strike's vector from the right, core by
+// core, in registers sized by a compile-time bound on the instance's largest bond; loops
+// stop at the actual bond dimensions, which are uniform over the workgroup.
+// k_readout_groups (bonds above that bound): a lane group of width RW (a power of two >=
+// the bond cap) holds one strike's vector, one bond component per lane, through LDS.
+// The price is
 //   C(k_u) = Re[ exp(-alpha k_u)/(s pi) * exp(-i v0 k_u) * sqrt(M) * y_u ],
 // with exp(-i v0 k_u) = exp(-i v0 k0) (-1)^u for the symmetric rule and 1 for Simpson.
 #include "cm_cf.h"
@@ -26,14 +30,159 @@ template <> struct rd<double2> {
 };
 }  // namespace
 
+// Per-instance readout scalars.
+struct ReadConst {
+  double k0, lam, alpha, sfac;   // sfac = sqrt(M) / (s pi)
+  double2 ro;                    // exp(-i v0 k0)
+  bool alt;                      // sign alternates with u (symmetric rule)
+};
+
+__device__ __forceinline__ ReadConst read_const(const cm_problem &pr, int n) {
+  ReadConst c;
+  const bool simpson = pr.quad == CM_QUAD_SIMPSON1;
+  c.k0 = k0_of(pr);
+  c.lam = 2.0 * M_PI / (ldexp(1.0, n) * pr.eta);
+  c.alpha = pr.alpha;
+  c.sfac = ldexp((n & 1) ? M_SQRT2 : 1.0, n >> 1) / ((simpson ? 1.0 : 2.0) * M_PI);
+  c.alt = !simpson;
+  c.ro = cmk(1.0, 0.0);
+  if (!simpson) {
+    double f;
+    if (k0_is_default(pr)) {
+      f = prod_cycles_frac(pr.eta, log(pr.S0), n - 1);
+      if (n == 1) { f += 0.5; f -= floor(f); }
+    } else {
+      f = prod_cycles_frac(pr.eta, pr.k0, n - 1);
+    }
+    c.ro = turn(f);
+  }
+  return c;
+}
+
+__device__ __forceinline__ double read_price(const ReadConst &c, int64_t u, double2 yu) {
+  const double k = c.k0 + c.lam * (double)u;
+  double2 ro = c.ro;
+  if (c.alt && (u & 1)) ro = cmk(-ro.x, -ro.y);
+  return exp(-c.alpha * k) * c.sfac * (ro.x * yu.x - ro.y * yu.y);
+}
+
+constexpr int RD_WG = 256;
+constexpr int RD_SPT = 4;                 // strikes per lane
+constexpr int RD_LDS = 48 * 1024;         // core staging arena (three workgroups per CU)
+
+// Contracts one strike: v <- Y_l[:, bit_l, :] v from l = n-1 down to 0; returns y_u.
+// Core l starts at base + off(l) and holds [rk[l]][2][rk[l+1]] values.
+template <typename T, int RM, class Off>
+__device__ __forceinline__ T contract_strike(const T *base, const Off &off, const int32_t *rk, int n, int64_t u) {
+  T v[RM], w[RM];
+#pragma unroll
+  for (int a = 0; a < RM; ++a) v[a] = T{0, 0};
+  v[0] = T{1, 0};
+  for (int l = n - 1; l >= 0; --l) {
+    const int ra = rk[l], rb = rk[l + 1];
+    const T *C = base + off(l) + (int)((u >> l) & 1) * rb;
+#pragma unroll
+    for (int a = 0; a < RM; ++a) {
+      if (a < ra) {
+        typename rd<T>::V acc = rd<T>::zero();
+        const T *row = C + a * 2 * rb;
+#pragma unroll
+        for (int q = 0; q < RM; ++q)
+          if (q < rb) rd<T>::fma_(acc, row[q], v[q]);
+        w[a] = acc;
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < RM; ++a) v[a] = w[a];
+  }
+  return v[0];
+}
+
+struct LdsOff {
+  const int32_t *o;
+  __device__ __forceinline__ int64_t operator()(int l) const { return o[l]; }
+};
+struct GlobalOff {
+  const TTView *y;
+  int b;
+  __device__ __forceinline__ int64_t operator()(int l) const { return y->coff(b, l); }
+};
+
+__device__ __forceinline__ int max_bond(const int32_t *rk, int n) {
+  int r = 1;
+  for (int l = 0; l <= n; ++l) r = rk[l] > r ? rk[l] : r;
+  return r;
+}
+
+template <typename T, int RM>
+__global__ __launch_bounds__(RD_WG) void k_readout(TTView y, const cm_problem *__restrict__ prob,
+                                                   const int64_t *__restrict__ strike_idx, int nk,
+                                                   double *__restrict__ prices, int32_t *__restrict__ status,
+                                                   int rm_lo) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  __shared__ int32_t s_off[CM_MAX_N + 1], s_rk[CM_MAX_N + 1];
+  __shared__ int s_ok;
+  const int b = blockIdx.y;
+  const int n = y.n[b];
+  const int32_t *rk = y.rk(b);
+  // this instantiation serves instances whose largest bond lies in (rm_lo, RM]
+  const int rmax = max_bond(rk, n);
+  if (rmax <= rm_lo || rmax > RM) return;
+  const T *gcores = (const T *)y.cores;
+  T *arena = (T *)lds_raw;
+  if (threadIdx.x == 0) {
+    int o = 0;
+    for (int l = 0; l < n; ++l) {
+      s_off[l] = o;
+      s_rk[l] = rk[l];
+      o += rk[l] * 2 * rk[l + 1];
+    }
+    s_rk[n] = rk[n];
+    s_off[n] = o;
+    s_ok = (size_t)o * sizeof(T) <= (size_t)RD_LDS;
+  }
+  __syncthreads();
+  const bool in_lds = s_ok != 0;
+  if (in_lds) {
+    for (int l = 0; l < n; ++l) {
+      const T *src = gcores + y.coff(b, l);
+      const int cnt = s_rk[l] * 2 * s_rk[l + 1];
+      for (int e = threadIdx.x; e < cnt; e += RD_WG) arena[s_off[l] + e] = src[e];
+    }
+  }
+  __syncthreads();
+  const cm_problem pr = prob[b];
+  const ReadConst rc = read_const(pr, n);
+  const int64_t M = (int64_t)1 << n;
+  const int s0 = blockIdx.x * RD_WG * RD_SPT;
+  for (int t = 0; t < RD_SPT; ++t) {
+    const int s = s0 + t * RD_WG + (int)threadIdx.x;
+    if (s >= nk) break;
+    const int64_t u = strike_idx[(int64_t)b * nk + s];
+    double price;
+    if (u < 0 || u >= M || pr.n != n) {
+      price = NAN;
+      set_status(status, b, CM_E_INVALID);
+    } else {
+      T yu;
+      if (in_lds) yu = contract_strike<T, RM>(arena, LdsOff{s_off}, s_rk, n, u);
+      else yu = contract_strike<T, RM>(gcores, GlobalOff{&y, b}, s_rk, n, u);
+      price = read_price(rc, u, rd<T>::to(yu));
+    }
+    prices[(int64_t)b * nk + s] = price;
+  }
+}
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_readout(TTView y, const cm_problem *__restrict__ prob,
+__global__ __launch_bounds__(256) void k_readout_groups(TTView y, const cm_problem *__restrict__ prob,
                                                  const int64_t *__restrict__ strike_idx, int nk,
-                                                 double *__restrict__ prices, int32_t *__restrict__ status, int RW) {
+                                                 double *__restrict__ prices, int32_t *__restrict__ status, int RW,
+                                                 int rm_lo) {
   extern __shared__ unsigned char lds_raw[];
   T *buf = (T *)lds_raw;  // [2][256]
   const int tid = threadIdx.x;
   const int b = blockIdx.y;
+  if (max_bond(y.rk(b), y.n[b]) <= rm_lo) return;
   const int spw = 256 / RW;
   const int sl = tid / RW, lane = tid % RW;
   const int s = blockIdx.x * spw + sl;
@@ -70,25 +219,7 @@ __global__ __launch_bounds__(256) void k_readout(TTView y, const cm_problem *__r
       price = NAN;
       set_status(status, b, CM_E_INVALID);
     } else {
-      const bool simpson = pr.quad == CM_QUAD_SIMPSON1;
-      const double k0 = k0_of(pr);
-      const double lam = 2.0 * M_PI / (ldexp(1.0, n) * pr.eta);
-      const double k = k0 + lam * (double)u;
-      const double sqM = ldexp((n & 1) ? M_SQRT2 : 1.0, n >> 1);
-      const double sc = exp(-pr.alpha * k) / ((simpson ? 1.0 : 2.0) * M_PI) * sqM;
-      double2 ro = cmk(1.0, 0.0);
-      if (!simpson) {
-        double f;
-        if (k0_is_default(pr)) {
-          f = prod_cycles_frac(pr.eta, log(pr.S0), n - 1);
-          if (n == 1) { f += 0.5; f -= floor(f); }
-        } else {
-          f = prod_cycles_frac(pr.eta, pr.k0, n - 1);
-        }
-        ro = turn(f);
-        if (u & 1) ro = cmk(-ro.x, -ro.y);
-      }
-      price = sc * (ro.x * yu.x - ro.y * yu.y);
+      price = read_price(read_const(pr, n), u, yu);
     }
     prices[(int64_t)b * nk + s] = price;
   }
@@ -102,19 +233,50 @@ extern "C" cm_status cm_readout_prices(const cm_tt_batch *y, const cm_problem *p
   if (y->cap_rank < 1 || y->cap_rank > 256) return CM_E_INVALID;
   if (y->batch == 0 || nk == 0) return CM_OK;
   if (y->batch > 65535) return CM_E_UNSUPPORTED;
-  int RW = 1;
-  while (RW < y->cap_rank) RW <<= 1;
-  if (RW > 256) return CM_E_UNSUPPORTED;
-  const int spw = 256 / RW;
-  dim3 grid((unsigned)((nk + spw - 1) / spw), (unsigned)y->batch);
   hipStream_t s = (hipStream_t)stream;
   TTView v = tt_view(y);
-  if (y->dtype == CM_C64)
-    hipLaunchKernelGGL(k_readout<float2>, grid, dim3(256), 2 * 256 * sizeof(float2), s, v, prob, strike_idx, nk,
-                       prices, status, RW);
-  else
-    hipLaunchKernelGGL(k_readout<double2>, grid, dim3(256), 2 * 256 * sizeof(double2), s, v, prob, strike_idx, nk,
-                       prices, status, RW);
+  const dim3 grid((unsigned)((nk + RD_WG * RD_SPT - 1) / (RD_WG * RD_SPT)), (unsigned)y->batch);
+  const int cap = y->cap_rank;
+  // one-lane-per-strike kernels by bound on the largest bond; the lane-group kernel takes
+  // the rest
+  int fast_max;
+  if (y->dtype == CM_C64) {
+    CM_HIP_CHECK(cm_allow_lds(k_readout<float2, 8>, RD_LDS));
+    CM_HIP_CHECK(cm_allow_lds(k_readout<float2, 16>, RD_LDS));
+    CM_HIP_CHECK(cm_allow_lds(k_readout<float2, 32>, RD_LDS));
+    hipLaunchKernelGGL((k_readout<float2, 8>), grid, dim3(RD_WG), RD_LDS, s, v, prob, strike_idx, nk, prices, status,
+                       0);
+    if (cap > 8)
+      hipLaunchKernelGGL((k_readout<float2, 16>), grid, dim3(RD_WG), RD_LDS, s, v, prob, strike_idx, nk, prices,
+                         status, 8);
+    if (cap > 16)
+      hipLaunchKernelGGL((k_readout<float2, 32>), grid, dim3(RD_WG), RD_LDS, s, v, prob, strike_idx, nk, prices,
+                         status, 16);
+    fast_max = 32;
+  } else {
+    CM_HIP_CHECK(cm_allow_lds(k_readout<double2, 8>, RD_LDS));
+    CM_HIP_CHECK(cm_allow_lds(k_readout<double2, 16>, RD_LDS));
+    hipLaunchKernelGGL((k_readout<double2, 8>), grid, dim3(RD_WG), RD_LDS, s, v, prob, strike_idx, nk, prices,
+                       status, 0);
+    if (cap > 8)
+      hipLaunchKernelGGL((k_readout<double2, 16>), grid, dim3(RD_WG), RD_LDS, s, v, prob, strike_idx, nk, prices,
+                         status, 8);
+    fast_max = 16;
+  }
+  CM_LAUNCH_CHECK();
+  if (cap > fast_max) {
+    int RW = 1;
+    while (RW < cap) RW <<= 1;
+    if (RW > 256) return CM_E_UNSUPPORTED;
+    const int spw = 256 / RW;
+    dim3 g2((unsigned)((nk + spw - 1) / spw), (unsigned)y->batch);
+    if (y->dtype == CM_C64)
+      hipLaunchKernelGGL(k_readout_groups<float2>, g2, dim3(256), 2 * 256 * sizeof(float2), s, v, prob, strike_idx,
+                         nk, prices, status, RW, fast_max);
+    else
+      hipLaunchKernelGGL(k_readout_groups<double2>, g2, dim3(256), 2 * 256 * sizeof(double2), s, v, prob,
+                         strike_idx, nk, prices, status, RW, fast_max);
+  }
   CM_LAUNCH_CHECK();
   return CM_OK;
 }
