@@ -13,7 +13,7 @@ extern "C" size_t cm_fft_ws_bytes(int batch, int n, int dtype, int gather);
 // Workgroups kept resident by the batched sweep kernels (each processes trains
 // blockIdx.x, blockIdx.x + slots, ...). Four per compute unit of a 256-CU device.
 extern "C" int cm_slots_for(int batch) {
-  const int max_slots = 1024;
+  const int max_slots = 2048;
   return batch < max_slots ? batch : max_slots;
 }
 

@@ -8,7 +8,12 @@
 
 #include "../../include/cm.h"
 
-#define CM_WG 256  // threads per workgroup of the sweep kernels
+// Threads per workgroup of the sweep kernels. A source file may define it before including
+// this header: each .hip file is compiled to its own device code object, so the
+// factorisation routines are instantiated per file with that file's workgroup size.
+#ifndef CM_WG
+#define CM_WG 256
+#endif
 
 // ------------------------------------------------------------------ complex helpers
 __host__ __device__ __forceinline__ double2 cmk(double re, double im) { return make_double2(re, im); }

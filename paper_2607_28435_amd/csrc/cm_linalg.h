@@ -144,11 +144,11 @@ __device__ __forceinline__ void qr_apply_q(const double2 *Y, int lda, int m, int
   }
 }
 
-// One-sided Jacobi on the columns of S (s x s, column-major, ld s, in LDS), accumulating
-// the rotations in J (s x s, LDS). On return the columns of S are mutually orthogonal,
-// S_in J = S_out, and sh.sig2[i] / sh.perm[i] list squared column norms in descending
-// order. Sets sh.noconv if the sweep limit was reached, sh.nonfinite on NaN/Inf.
-__device__ __forceinline__ void jacobi_onesided(double2 *S, double2 *J, int s, Sh &sh) {
+// One-sided Jacobi on the s columns of S (m x s, column-major, ld m, in LDS; s <= 64),
+// accumulating the rotations in J (s x s, LDS). On return the columns of S are mutually
+// orthogonal, S_in J = S_out, and sh.sig2[i] / sh.perm[i] list squared column norms in
+// descending order. Sets sh.noconv if the sweep limit was reached, sh.nonfinite on NaN/Inf.
+__device__ __forceinline__ void jacobi_onesided(double2 *S, double2 *J, int m, int s, Sh &sh) {
   const int tid = threadIdx.x;
   for (int e = tid; e < s * s; e += CM_WG) J[e] = cmk((e % s) == (e / s) ? 1.0 : 0.0, 0.0);
   if (tid == 0) { sh.noconv = 0; sh.nonfinite = 0; }
@@ -164,7 +164,7 @@ __device__ __forceinline__ void jacobi_onesided(double2 *S, double2 *J, int s, S
   double amax_part = 0.0;
   if (tid < s) {
     double a = 0.0;
-    for (int i = 0; i < s; ++i) a += cabs2(S[i + s * tid]);
+    for (int i = 0; i < m; ++i) a += cabs2(S[i + m * tid]);
     amax_part = a;
   }
   __syncthreads();
@@ -194,8 +194,8 @@ __device__ __forceinline__ void jacobi_onesided(double2 *S, double2 *J, int s, S
       }
       double a = 0.0, b = 0.0, gr = 0.0, gi = 0.0;
       if (p >= 0) {
-        for (int i = lane; i < s; i += G) {
-          double2 xp = S[i + s * p], xq = S[i + s * q];
+        for (int i = lane; i < m; i += G) {
+          double2 xp = S[i + m * p], xq = S[i + m * q];
           a += cabs2(xp); b += cabs2(xq);
           gr += xp.x * xq.x + xp.y * xq.y;
           gi += xp.x * xq.y - xp.y * xq.x;
@@ -215,10 +215,12 @@ __device__ __forceinline__ void jacobi_onesided(double2 *S, double2 *J, int s, S
             const double2 e = cmk(gr / ag, gi / ag);
             const double2 se = cscale(e, sn);          // s e
             const double2 sce = cscale(cconj(e), sn);  // s conj(e)
+            for (int i = lane; i < m; i += G) {
+              double2 xp = S[i + m * p], xq = S[i + m * q];
+              S[i + m * p] = csub(cscale(xp, c), cmul(sce, xq));
+              S[i + m * q] = cadd(cmul(se, xp), cscale(xq, c));
+            }
             for (int i = lane; i < s; i += G) {
-              double2 xp = S[i + s * p], xq = S[i + s * q];
-              S[i + s * p] = csub(cscale(xp, c), cmul(sce, xq));
-              S[i + s * q] = cadd(cmul(se, xp), cscale(xq, c));
               double2 vp = J[i + s * p], vq = J[i + s * q];
               J[i + s * p] = csub(cscale(vp, c), cmul(sce, vq));
               J[i + s * q] = cadd(cmul(se, vp), cscale(vq, c));
@@ -237,7 +239,7 @@ __device__ __forceinline__ void jacobi_onesided(double2 *S, double2 *J, int s, S
   // squared column norms and descending order
   if (tid < s) {
     double a = 0.0;
-    for (int i = 0; i < s; ++i) a += cabs2(S[i + s * tid]);
+    for (int i = 0; i < m; ++i) a += cabs2(S[i + m * tid]);
     if (!(a == a) || isinf(a)) { sh.nonfinite = 1; a = 0.0; }
     sh.sig2[tid] = a;
   }
@@ -277,81 +279,6 @@ __device__ __forceinline__ void choose_rank_t0(Sh &sh, int s, double delta2, int
     sh.rankcap = rc;
   }
   __syncthreads();
-}
-
-// Truncated factorisation Y ~= L * Rk of Y (a x b, column-major in global scratch, ld a;
-// destroyed), where Rk (k x b) has orthonormal rows (the top-k right singular vectors)
-// and L = Y Rk^H (a x k). The kept rank k follows choose_rank_t0(delta2, cap).
-//   X : global scratch of at least a*b complex (used when a < b)
-//   Z : global scratch of at least max(a,b)*min(a,b) complex
-//   S, J : LDS, s*s complex each, s = min(a,b) <= 64
-//   L (ld a) and R (ld k) : global outputs.
-// Returns k (uniform).
-__device__ __forceinline__ int svd_trunc_rows(double2 *Y, int a, int b, double delta2, int cap,
-                              double2 *X, double2 *Z, double2 *S, double2 *J,
-                              double2 *L, double2 *R, Sh &sh) {
-  const int tid = threadIdx.x;
-  if (a >= b) {
-    const int s = b;
-    qr_householder(Y, a, a, s, s, sh);
-    for (int e = tid; e < s * s; e += CM_WG) {
-      const int i = e % s, j = e / s;
-      S[e] = (i <= j) ? Y[i + (int64_t)a * j] : cmk(0.0, 0.0);
-    }
-    __syncthreads();
-    jacobi_onesided(S, J, s, sh);
-    choose_rank_t0(sh, s, delta2, cap);
-    const int k = sh.k;
-    // Rk[i, c] = conj(J[c, perm[i]])
-    for (int e = tid; e < k * b; e += CM_WG) {
-      const int i = e % k, c = e / k;
-      R[i + (int64_t)k * c] = cconj(J[c + s * sh.perm[i]]);
-    }
-    // L = Q [W_k; 0]
-    for (int e = tid; e < a * k; e += CM_WG) {
-      const int i = e % a, j = e / a;
-      Z[e] = (i < s) ? S[i + s * sh.perm[j]] : cmk(0.0, 0.0);
-    }
-    __syncthreads();
-    qr_apply_q(Y, a, a, s, sh, Z, a, k);
-    for (int e = tid; e < a * k; e += CM_WG) L[e] = Z[e];
-    __syncthreads();
-    return k;
-  } else {
-    const int s = a;
-    // X = Y^H (b x a)
-    for (int e = tid; e < a * b; e += CM_WG) {
-      const int i = e % b, j = e / b;   // X[i, j] = conj(Y[j, i])
-      X[e] = cconj(Y[j + (int64_t)a * i]);
-    }
-    __syncthreads();
-    qr_householder(X, b, b, s, s, sh);
-    // S = R^H (a x a)
-    for (int e = tid; e < s * s; e += CM_WG) {
-      const int i = e % s, j = e / s;
-      S[e] = (j <= i) ? cconj(X[j + (int64_t)b * i]) : cmk(0.0, 0.0);
-    }
-    __syncthreads();
-    jacobi_onesided(S, J, s, sh);
-    choose_rank_t0(sh, s, delta2, cap);
-    const int k = sh.k;
-    for (int e = tid; e < a * k; e += CM_WG) {
-      const int i = e % a, j = e / a;
-      L[e] = S[i + s * sh.perm[j]];
-    }
-    for (int e = tid; e < b * k; e += CM_WG) {
-      const int i = e % b, j = e / b;
-      Z[e] = (i < s) ? J[i + s * sh.perm[j]] : cmk(0.0, 0.0);
-    }
-    __syncthreads();
-    qr_apply_q(X, b, b, s, sh, Z, b, k);
-    for (int e = tid; e < k * b; e += CM_WG) {
-      const int i = e % k, c = e / k;
-      R[i + (int64_t)k * c] = cconj(Z[c + (int64_t)b * i]);
-    }
-    __syncthreads();
-    return k;
-  }
 }
 
 // Thin QR: Y (m x p, ld m, destroyed) = Q Rr with Q (m x kq, orthonormal columns) and
@@ -519,6 +446,58 @@ __device__ __forceinline__ int cpqr_trunc(double2 *T, int m, int p, double delta
   }
   __syncthreads();
   qr_apply_q(T, m, m, k, sh, Qk, m, k);
+  return k;
+}
+
+// Truncated factorisation Y ~= L * Rk of Y (a x b, column-major, ld a; destroyed), where
+// Rk (k x b) has orthonormal rows (the top-k right singular vectors) and L = Y Rk^H (a x k),
+// a <= 64. Column-pivoted QR of X = Y^H first drops a tail of squared norm <= delta2/2 and
+// leaves X ~= Q B (Q: b x kc orthonormal, B: kc x a); one-sided Jacobi on the kc columns of
+// B^H (ordered by decreasing norm by the pivoting, which speeds convergence) then yields its
+// SVD, truncated with the rest of the budget. The kept rank k is the smallest whose total
+// dropped squared norm is <= delta2, clipped to cap (sh.rankcap is set if that loses more).
+//   X : scratch of at least a*b complex;  Z : scratch of at least a*b complex
+//   S, J : LDS, at least a*min(a,b) and min(a,b)^2 complex
+//   L (ld a) and R (ld k) : outputs.
+// Returns k (uniform); sh.err2 holds the dropped squared norm.
+__device__ __forceinline__ int svd_trunc_rows(double2 *Y, int a, int b, double delta2, int cap,
+                                              double2 *X, double2 *Z, double2 *S, double2 *J,
+                                              double2 *L, double2 *R, Sh &sh) {
+  const int tid = threadIdx.x;
+  for (int e = tid; e < a * b; e += CM_WG) {
+    const int i = e % b, j = e / b;   // X[i, j] = conj(Y[j, i])
+    X[e] = cconj(Y[j + (int64_t)a * i]);
+  }
+  __syncthreads();
+  // X P = Q R, truncated: Q -> Z (b x kc), B = R[:kc] P^T -> Y (kc x a, ld kc)
+  const int kc = cpqr_trunc(X, b, a, 0.5 * delta2, 64, Z, Y, sh.sig2, sh.perm, sh);
+  __syncthreads();
+  const double err_c = sh.err2;
+  // S = B^H (a x kc, ld a)
+  for (int e = tid; e < a * kc; e += CM_WG) {
+    const int i = e % a, j = e / a;
+    S[e] = cconj(Y[j + (int64_t)kc * i]);
+  }
+  __syncthreads();
+  jacobi_onesided(S, J, a, kc, sh);
+  const double rest = delta2 - err_c;
+  choose_rank_t0(sh, kc, rest > 0.0 ? rest : 0.0, cap);
+  const int k = sh.k;
+  // L = (B^H J)[:, perm[:k]];  Rk^H = Q J[:, perm[:k]]
+  for (int e = tid; e < a * k; e += CM_WG) {
+    const int i = e % a, j = e / a;
+    L[e] = S[i + (int64_t)a * sh.perm[j]];
+  }
+  for (int e = tid; e < k * b; e += CM_WG) {
+    const int i = e % k, c = e / k;
+    const double2 *jc = J + (int64_t)kc * sh.perm[i];
+    double2 acc = cmk(0.0, 0.0);
+    for (int t = 0; t < kc; ++t) cfma(acc, Z[c + (int64_t)b * t], jc[t]);
+    R[i + (int64_t)k * c] = cconj(acc);
+  }
+  __syncthreads();
+  if (tid == 0) sh.err2 += err_c;
+  __syncthreads();
   return k;
 }
 

@@ -19,6 +19,8 @@
 // then rounded to `tol` by the shared FP64 sweep. This replaces the TT-cross of the paper
 // (Section 3.3) with a deterministic construction whose cost is O(#leaves * P) evaluations
 // of h plus O(n P^3) assembly, independent of the grid size 2^n.
+// One wavefront per problem (see cm_round.hip).
+#define CM_WG 64
 #include "cm_cf.h"
 #include "cm_tt.h"
 
@@ -29,7 +31,7 @@ constexpr int QNC = 64;         // max candidate intervals per depth
 constexpr int QI = QNC / 2;     // max split intervals per depth
 constexpr int QNPT = 2 * QP - 1;
 constexpr int PRE_CAP = QI + QP + 1;   // bond bound before rounding (<= 64)
-constexpr int QLDS = 76 * 1024;        // LDS arena per workgroup (two workgroups per CU)
+constexpr int QLDS = 38 * 1024;        // LDS arena per workgroup (four workgroups per CU)
 
 struct TreeDepth {
   int n_int;                 // split intervals at this depth

@@ -1,10 +1,13 @@
 // cm_tt_round: in-place TT rounding (the recompression of Section 3.1, after Oseledets
 // 2011) of every train in a batch, one workgroup per train, FP64 factorisations.
+// One wavefront per train: the factorisations are chains of small dependent steps, so
+// barriers over a single wave and more trains per CU beat wider workgroups.
+#define CM_WG 64
 #include "cm_tt.h"
 
 namespace {
 __host__ __device__ inline size_t al256r(size_t x) { return (x + 255) & ~(size_t)255; }
-constexpr int RLDS = 76 * 1024;  // LDS arena per workgroup (two workgroups per CU)
+constexpr int RLDS = 38 * 1024;  // LDS arena per workgroup (four workgroups per CU)
 __host__ __device__ inline size_t round_slab_bytes(int n_max, int d, int cap) {
   const size_t core_cap = (size_t)cap * d * cap;
   return al256r(sizeof(double2) * core_cap * n_max) + al256r(sizeof(double2) * core_cap * 6) +
