@@ -39,7 +39,7 @@ extern "C" {
 
 typedef enum {
   CM_OK = 0,
-  CM_E_INVALID = 1,      /* bad argument, or a workspace smaller than cm_workspace_bytes */
+  CM_E_INVALID = 1,      /* bad argument, or a workspace smaller than the op needs */
   CM_E_MOMENT = 2,       /* damping moment E[S_T^(alpha+1)] infinite (Eq. damping_moment_condition) */
   CM_E_RANKCAP = 3,      /* a bond hit cap_rank while the truncation error exceeded tol; result still written */
   CM_E_NOCONV = 4,       /* an iteration (Jacobi sweeps, QTT refinement) did not converge */
@@ -113,7 +113,12 @@ int64_t cm_tt_layout(int n, int d_out, int d_in, int cap_rank, int64_t *off);
 
 /* Host helper. Bytes of device workspace the operation needs for `batch` instances of
  * chain length at most n_max and bond dimensions at most cap_rank (0 on bad arguments).
- * For CM_OP_FFT_PRICE, n_max is the grid exponent and cap_rank is ignored. */
+ * For CM_OP_FFT_PRICE, n_max is the grid exponent and cap_rank is ignored.
+ * Sweep ops (CM_OP_BUILD_QTT, CM_OP_SFFT_APPLY, CM_OP_TT_ROUND) run persistent workgroups,
+ * one per workspace slab of cm_workspace_bytes(op, 1, n_max, cap_rank, dtype) bytes, each
+ * looping over instances b, b + slots, ...: the default size gives min(batch, 2048) slots;
+ * any workspace of s >= 1 slabs is accepted and runs min(s, batch) slots, which is how a
+ * caller (the autotuner of the Python layer) picks the launch width. */
 size_t cm_workspace_bytes(int op, int batch, int n_max, int cap_rank, int dtype);
 
 /* Builds the tensor-train operator of Q_n: the minus-sign unitary DFT of Eq. dft without

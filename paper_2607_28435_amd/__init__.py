@@ -226,6 +226,15 @@ class Workspace:
 
 # ------------------------------------------------------------------ the C ABI entry points
 
+def _sweep_ws_bytes(op: int, batch: int, n_max: int, cap_rank: int, dtype: int, slots: Optional[int]) -> int:
+    """Workspace bytes for a sweep op: the library's default, or exactly `slots` slabs (the
+    library runs one persistent workgroup per slab)."""
+    if slots is None:
+        return cm_workspace_bytes(op, batch, n_max, cap_rank, dtype)
+    slab = cm_workspace_bytes(op, 1, n_max, cap_rank, dtype)
+    return slab * max(1, min(int(slots), batch))
+
+
 def cm_qft_mpo(n: int, tol: float, cap_rank: int, w: TTBatch, slot: int, ws: Workspace, stream=None) -> int:
     need = cm_workspace_bytes(CM_OP_QFT_MPO, 1, n, cap_rank, w.dtype)
     buf = ws.get(need)
@@ -234,27 +243,28 @@ def cm_qft_mpo(n: int, tol: float, cap_rank: int, w: TTBatch, slot: int, ws: Wor
 
 
 def cm_build_qtt(prob_dev, batch: int, tol: float, cap_rank: int, x: TTBatch, status, ws: Workspace,
-                 stream=None) -> int:
-    need = cm_workspace_bytes(CM_OP_BUILD_QTT, batch, x.struct.n_max, cap_rank, x.dtype)
+                 stream=None, slots: Optional[int] = None) -> int:
+    need = _sweep_ws_bytes(CM_OP_BUILD_QTT, batch, x.struct.n_max, cap_rank, x.dtype, slots)
     buf = ws.get(need)
     code = lib().cm_build_qtt(_ptr(prob_dev), batch, tol, cap_rank, C.byref(x.struct), _ptr(status), _ptr(buf),
-                              buf.numel(), _stream_ptr(stream))
+                              need, _stream_ptr(stream))
     return _check(code, "cm_build_qtt")
 
 
 def cm_sfft_apply(w_by_n: TTBatch, x: TTBatch, tol: float, cap_rank: int, y: TTBatch, status, ws: Workspace,
-                  stream=None) -> int:
-    need = cm_workspace_bytes(CM_OP_SFFT_APPLY, x.batch, x.struct.n_max, cap_rank, x.dtype)
+                  stream=None, slots: Optional[int] = None) -> int:
+    need = _sweep_ws_bytes(CM_OP_SFFT_APPLY, x.batch, x.struct.n_max, cap_rank, x.dtype, slots)
     buf = ws.get(need)
     code = lib().cm_sfft_apply(C.byref(w_by_n.struct), C.byref(x.struct), tol, cap_rank, C.byref(y.struct),
-                               _ptr(status), _ptr(buf), buf.numel(), _stream_ptr(stream))
+                               _ptr(status), _ptr(buf), need, _stream_ptr(stream))
     return _check(code, "cm_sfft_apply")
 
 
-def cm_tt_round(t: TTBatch, tol: float, cap_rank: int, err_out, status, ws: Workspace, stream=None) -> int:
-    need = cm_workspace_bytes(CM_OP_TT_ROUND, t.batch, t.struct.n_max, t.cap_rank, t.dtype)
+def cm_tt_round(t: TTBatch, tol: float, cap_rank: int, err_out, status, ws: Workspace, stream=None,
+                slots: Optional[int] = None) -> int:
+    need = _sweep_ws_bytes(CM_OP_TT_ROUND, t.batch, t.struct.n_max, t.cap_rank, t.dtype, slots)
     buf = ws.get(need)
-    code = lib().cm_tt_round(C.byref(t.struct), tol, cap_rank, _ptr(err_out), _ptr(status), _ptr(buf), buf.numel(),
+    code = lib().cm_tt_round(C.byref(t.struct), tol, cap_rank, _ptr(err_out), _ptr(status), _ptr(buf), need,
                              _stream_ptr(stream))
     return _check(code, "cm_tt_round")
 
@@ -274,4 +284,4 @@ def cm_fft_price(prob_dev, batch: int, n: int, dtype: int, strike_idx, nk: int, 
     return _check(code, "cm_fft_price")
 
 
-from .pipeline import MpoCache, SfftPricer, dense_prices  # noqa: E402
+from .pipeline import MpoCache, SfftPricer, autotune_slots, dense_prices  # noqa: E402

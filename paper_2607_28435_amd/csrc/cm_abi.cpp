@@ -65,6 +65,16 @@ extern "C" size_t cm_workspace_bytes(int op, int batch, int n_max, int cap_rank,
   }
 }
 
+// Persistent workgroups for a sweep op: one per workspace slab, at most one per instance.
+extern "C" int cm_slots_for_ws(int op, int batch, int n_max, int cap_rank, int dtype, size_t ws_bytes) {
+  const size_t slab = cm_workspace_bytes(op, 1, n_max, cap_rank, dtype);
+  if (slab == 0 || batch < 1) return 0;
+  size_t s = ws_bytes / slab;
+  if (s > (size_t)batch) s = (size_t)batch;
+  if (s > 65535) s = 65535;
+  return (int)s;
+}
+
 extern "C" const char *cm_status_str(cm_status s) {
   switch (s) {
     case CM_OK: return "ok";

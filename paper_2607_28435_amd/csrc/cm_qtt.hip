@@ -376,7 +376,7 @@ extern "C" size_t cm_qtt_slab_bytes(int n_max, int cap) {
   return qtt_slab_bytes(n_max, cap, parts);
 }
 
-extern "C" int cm_slots_for(int batch);
+extern "C" int cm_slots_for_ws(int op, int batch, int n_max, int cap_rank, int dtype, size_t ws_bytes);
 
 extern "C" cm_status cm_build_qtt(const cm_problem *prob, int batch, double tol, int cap_rank,
                                   cm_tt_batch *x, int32_t *status, void *ws, size_t ws_bytes,
@@ -386,9 +386,9 @@ extern "C" cm_status cm_build_qtt(const cm_problem *prob, int batch, double tol,
   if (x->d_out != 2 || x->d_in != 1 || x->batch < batch || x->n_max < 1 || x->n_max > CM_MAX_N) return CM_E_INVALID;
   if (cap_rank > x->cap_rank) return CM_E_INVALID;
   if (x->dtype != CM_C64 && x->dtype != CM_C128) return CM_E_INVALID;
-  const size_t need = cm_workspace_bytes(CM_OP_BUILD_QTT, batch, x->n_max, cap_rank, x->dtype);
-  if (!ws || ws_bytes < need) return CM_E_INVALID;
-  const int slots = cm_slots_for(batch);
+  // one workgroup per workspace slab (cm_workspace_bytes gives the default count)
+  const int slots = cm_slots_for_ws(CM_OP_BUILD_QTT, batch, x->n_max, cap_rank, x->dtype, ws ? ws_bytes : 0);
+  if (slots < 1) return CM_E_INVALID;
   const size_t slab = cm_qtt_slab_bytes(x->n_max, cap_rank);
   const size_t lds = QLDS;
   static_assert(sizeof(double2) * QNC * QNPT <= QLDS, "tree values must fit the LDS arena");

@@ -63,7 +63,7 @@ __global__ __launch_bounds__(CM_WG) void k_tt_round(TTView t, int batch, double 
 }
 
 extern "C" size_t cm_round_slab_bytes(int n_max, int d, int cap) { return round_slab_bytes(n_max, d, cap); }
-extern "C" int cm_slots_for(int batch);
+extern "C" int cm_slots_for_ws(int op, int batch, int n_max, int cap_rank, int dtype, size_t ws_bytes);
 
 extern "C" cm_status cm_tt_round(cm_tt_batch *t, double tol, int cap_rank, double *err_out, int32_t *status,
                                  void *ws, size_t ws_bytes, void *stream) {
@@ -73,10 +73,10 @@ extern "C" cm_status cm_tt_round(cm_tt_batch *t, double tol, int cap_rank, doubl
   if (t->d_out < 1 || t->d_in < 1 || t->d_out * t->d_in > 4) return CM_E_INVALID;
   if (t->cap_rank < 1 || t->cap_rank > 64) return CM_E_UNSUPPORTED;
   if (t->batch == 0) return CM_OK;
-  const size_t need = cm_workspace_bytes(CM_OP_TT_ROUND, t->batch, t->n_max, t->cap_rank, t->dtype);
-  if (!ws || ws_bytes < need) return CM_E_INVALID;
+  // one workgroup per workspace slab (cm_workspace_bytes gives the default count)
+  const int slots = cm_slots_for_ws(CM_OP_TT_ROUND, t->batch, t->n_max, t->cap_rank, t->dtype, ws ? ws_bytes : 0);
+  if (slots < 1) return CM_E_INVALID;
   const int d = t->d_out * t->d_in;
-  const int slots = cm_slots_for(t->batch);
   const size_t slab = round_slab_bytes(t->n_max, d, t->cap_rank);
   const size_t lds = RLDS;
   TTView v = tt_view(t);

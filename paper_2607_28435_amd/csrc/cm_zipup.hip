@@ -236,7 +236,7 @@ extern "C" size_t cm_zip_slab_bytes(int cap) {
   return zip_slab_bytes(cap, parts);
 }
 
-extern "C" int cm_slots_for(int batch);
+extern "C" int cm_slots_for_ws(int op, int batch, int n_max, int cap_rank, int dtype, size_t ws_bytes);
 
 extern "C" cm_status cm_sfft_apply(const cm_tt_batch *w_by_n, const cm_tt_batch *x, double tol, int cap_rank,
                                    cm_tt_batch *y, int32_t *status, void *ws, size_t ws_bytes, void *stream) {
@@ -250,9 +250,9 @@ extern "C" cm_status cm_sfft_apply(const cm_tt_batch *w_by_n, const cm_tt_batch 
   if (w_by_n->batch <= x->n_max || x->cap_rank > cap_rank || cap_rank > y->cap_rank) return CM_E_INVALID;
   if (w_by_n->rank_max > ZW) return CM_E_UNSUPPORTED;
   const int batch = x->batch;
-  const size_t need = cm_workspace_bytes(CM_OP_SFFT_APPLY, batch, x->n_max, cap_rank, x->dtype);
-  if (!ws || ws_bytes < need) return CM_E_INVALID;
-  const int slots = cm_slots_for(batch);
+  // one workgroup per workspace slab (cm_workspace_bytes gives the default count)
+  const int slots = cm_slots_for_ws(CM_OP_SFFT_APPLY, batch, x->n_max, cap_rank, x->dtype, ws ? ws_bytes : 0);
+  if (slots < 1) return CM_E_INVALID;
   const size_t slab = cm_zip_slab_bytes(cap_rank);
   const int64_t mc = (int64_t)zip_mat_cap(cap_rank);
   const size_t lds = ZLDS;

@@ -32,6 +32,9 @@ class MpoCache:
         self.ns = ns
 
 
+_SWEEP_OPS = ("build", "apply", "round")
+
+
 class SfftPricer:
     """Batched SFFT pricing of a fixed list of problems on one stream.
 
@@ -39,17 +42,33 @@ class SfftPricer:
     build_tol : QTT construction tolerance (default tol/10)
     mpo_tol   : operator rounding tolerance (default tol/10)
     cap       : bond capacity of x and y (zip-up bonds are limited to min(cap, 32))
+    slots     : persistent workgroups per sweep op ({"build": s, "apply": s, "round": s});
+                None entries take the library default (see `autotune_slots`)
+
+    Ragged batches are processed longest chain first (the persistent workgroups take
+    instances b, b + slots, ..., so descending cost balances them); `run` and `statuses`
+    return everything in the caller's order. `capture` records the whole chain as one HIP
+    graph for replay.
     """
 
     def __init__(self, problems: Sequence, dtype: int = CM_C64, tol: float = 1e-8, cap: int = 32,
                  build_tol: Optional[float] = None, mpo_tol: Optional[float] = None, mpo: Optional[MpoCache] = None,
-                 device="cuda", stream=None):
+                 device="cuda", stream=None, slots: Optional[Dict[str, Optional[int]]] = None):
         torch = _torch()
-        self.problems = list(problems)
-        self.batch = len(self.problems)
+        problems = list(problems)
+        self.batch = len(problems)
+        ns_in = [p.n for p in problems]
+        if len(set(ns_in)) > 1:
+            # longest chain first; stable among equal n
+            self.order = sorted(range(self.batch), key=lambda i: -ns_in[i])
+        else:
+            self.order = list(range(self.batch))
+        self.identity = self.order == list(range(self.batch))
+        self.problems = [problems[i] for i in self.order]
         self.dtype, self.tol, self.cap = dtype, tol, cap
         self.build_tol = tol / 10 if build_tol is None else build_tol
         ns = [p.n for p in self.problems]
+        self.device = device
         self.prob = pack_problems(self.problems, device)
         self.x = TTBatch(ns, 2, 1, cap, dtype, device)
         self.y = TTBatch(ns, 2, 1, cap, dtype, device)
@@ -60,27 +79,155 @@ class SfftPricer:
         self.round_err = torch.zeros(self.batch, dtype=torch.float64, device=device)
         self.ws = Workspace(device)
         self.stream = stream
+        self.slots = {k: None for k in _SWEEP_OPS}
+        if slots:
+            self.slots.update(slots)
+        self._perm = None if self.identity else torch.tensor(self.order, dtype=torch.int64, device=device)
+        self._graph = None
 
+    # -- stages (all on internal, cost-ordered rows)
     def build(self):
-        cm_build_qtt(self.prob, self.batch, self.build_tol, self.cap, self.x, self.st_build, self.ws, self.stream)
+        cm_build_qtt(self.prob, self.batch, self.build_tol, self.cap, self.x, self.st_build, self.ws, self.stream,
+                     slots=self.slots["build"])
 
-    def core(self, strikes, prices):
-        """The online part: SFFT apply, rounding and readout (x must be built)."""
-        cm_sfft_apply(self.mpo.w, self.x, self.tol, self.cap, self.y, self.st_apply, self.ws, self.stream)
-        cm_tt_round(self.y, self.tol, self.cap, self.round_err, self.st_round, self.ws, self.stream)
-        cm_readout_prices(self.y, self.prob, strikes, strikes.shape[-1], prices, self.st_read, self.stream)
+    def apply(self):
+        cm_sfft_apply(self.mpo.w, self.x, self.tol, self.cap, self.y, self.st_apply, self.ws, self.stream,
+                      slots=self.slots["apply"])
+
+    def round(self):
+        cm_tt_round(self.y, self.tol, self.cap, self.round_err, self.st_round, self.ws, self.stream,
+                    slots=self.slots["round"])
+
+    def read(self, strikes_int, prices_int):
+        self.st_read.zero_()
+        cm_readout_prices(self.y, self.prob, strikes_int, strikes_int.shape[-1], prices_int, self.st_read,
+                          self.stream)
+
+    def core(self, strikes_int, prices_int):
+        """The online part: SFFT apply, rounding and readout (x must be built); rows in
+        internal order."""
+        self.apply()
+        self.round()
+        self.read(strikes_int, prices_int)
+
+    # -- caller-order interface
+    def to_internal(self, rows):
+        return rows if self.identity else rows.index_select(0, self._perm)
 
     def run(self, strikes, prices=None):
-        """strikes: device int64 [batch, nk]; returns device float64 [batch, nk]."""
+        """strikes: device int64 [batch, nk] (caller's order); returns device float64
+        [batch, nk] in the caller's order."""
         torch = _torch()
-        if prices is None:
-            prices = torch.empty(strikes.shape, dtype=torch.float64, device=strikes.device)
+        s_int = self.to_internal(strikes)
+        p_int = torch.empty(s_int.shape, dtype=torch.float64, device=strikes.device)
         self.build()
-        self.core(strikes, prices)
+        self.core(s_int, p_int)
+        if self.identity:
+            if prices is None:
+                return p_int
+            prices.copy_(p_int)
+            return prices
+        if prices is None:
+            prices = torch.empty_like(p_int)
+        prices.index_copy_(0, self._perm, p_int)
         return prices
 
     def statuses(self) -> Dict[str, np.ndarray]:
-        return {k: getattr(self, "st_" + k).cpu().numpy() for k in ("build", "apply", "round", "read")}
+        out = {}
+        for k in ("build", "apply", "round", "read"):
+            v = getattr(self, "st_" + k).cpu().numpy()
+            if not self.identity:
+                w = np.empty_like(v)
+                w[np.asarray(self.order)] = v
+                v = w
+            out[k] = v
+        return out
+
+    # -- HIP graph of the whole chain
+    def capture(self, strikes):
+        """Records build -> apply -> round -> readout (plus the caller-order permutations) as
+        one HIP graph. Runs the chain once eagerly first so that every buffer exists; the
+        graph then owns its input copy (`graph_strikes`) and output (`graph_prices`)."""
+        torch = _torch()
+        self.graph_strikes = strikes.clone()
+        self.graph_prices = self.run(self.graph_strikes)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.run(self.graph_strikes, self.graph_prices)
+        self._graph = g
+        return g
+
+    def replay(self):
+        if self._graph is None:
+            raise RuntimeError("capture() first")
+        self._graph.replay()
+        return self.graph_prices
+
+
+def autotune_slots(pricer: SfftPricer, strikes, candidates: Sequence[int] = (512, 1024, 2048, 4096), reps: int = 2,
+                   cache_path: Optional[str] = None) -> Dict[str, int]:
+    """Picks the persistent-workgroup count of each sweep op by timing the candidates on the
+    pricer's own batch (HIP events, best of `reps`), stores the choice in pricer.slots and,
+    if cache_path is given, in a JSON table keyed by device, dtype, cap, batch and the
+    chain-length histogram (read back on the next call instead of re-timing)."""
+    import json
+    import os
+    torch = _torch()
+    key = "|".join([torch.cuda.get_device_name(), str(pricer.dtype), str(pricer.cap), str(pricer.batch),
+                    ",".join(f"{n}:{c}" for n, c in sorted(_hist(p.n for p in pricer.problems).items()))])
+    table = {}
+    if cache_path and os.path.exists(cache_path):
+        with open(cache_path) as f:
+            table = json.load(f)
+        if key in table:
+            pricer.slots.update({k: int(v) for k, v in table[key].items()})
+            return dict(pricer.slots)
+    cands = sorted(set(min(int(c), pricer.batch) for c in candidates))
+    s_int = pricer.to_internal(strikes)
+    p_int = torch.empty(s_int.shape, dtype=torch.float64, device=strikes.device)
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    pricer.build()
+    pricer.core(s_int, p_int)
+    torch.cuda.synchronize()
+    best = {}
+    for op in _SWEEP_OPS:
+        res = {}
+        for c in cands:
+            pricer.slots[op] = c
+            t = []
+            for _ in range(reps):
+                if op == "build":
+                    t.append(timed(pricer.build))
+                elif op == "apply":
+                    t.append(timed(pricer.apply))
+                else:
+                    pricer.apply()   # rounding works in place: start from a fresh zip-up output
+                    t.append(timed(pricer.round))
+            res[c] = min(t)
+        best[op] = min(res, key=res.get)
+        pricer.slots[op] = best[op]
+    if cache_path:
+        table[key] = best
+        with open(cache_path, "w") as f:
+            json.dump(table, f, indent=1, sort_keys=True)
+    return best
+
+
+def _hist(values) -> Dict[int, int]:
+    h: Dict[int, int] = {}
+    for v in values:
+        h[int(v)] = h.get(int(v), 0) + 1
+    return h
 
 
 def dense_prices(problems: Sequence, dtype: int = CM_C64, strikes=None, device="cuda", stream=None, ws=None):

@@ -63,3 +63,17 @@ def test_status_strings():
         assert cm.cm_status_str(code)
     assert "moment" in cm.cm_status_str(cm.CM_E_MOMENT)
     assert cm.cm_version().startswith("cm-sfft")
+
+
+def test_sweep_workspace_is_per_slot():
+    """Sweep ops run one persistent workgroup per workspace slab: the default size is
+    min(batch, 2048) slabs and an explicit slot count asks for exactly that many."""
+    from paper_2607_28435_amd import _sweep_ws_bytes
+    for op in (cm.CM_OP_BUILD_QTT, cm.CM_OP_SFFT_APPLY, cm.CM_OP_TT_ROUND):
+        slab = cm.cm_workspace_bytes(op, 1, 24, 32, cm.CM_C64)
+        assert slab > 0
+        assert cm.cm_workspace_bytes(op, 100, 24, 32, cm.CM_C64) == 100 * slab
+        assert cm.cm_workspace_bytes(op, 5000, 24, 32, cm.CM_C64) == 2048 * slab
+        assert _sweep_ws_bytes(op, 100, 24, 32, cm.CM_C64, 7) == 7 * slab
+        assert _sweep_ws_bytes(op, 5, 24, 32, cm.CM_C64, 7) == 5 * slab
+        assert _sweep_ws_bytes(op, 100, 24, 32, cm.CM_C64, None) == 100 * slab
