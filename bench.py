@@ -6,10 +6,12 @@ T~U[0.1,2]), S0=100, r=0.03, alpha=1.5, Simpson weights, n forced to 24,
 eta = 40/2^12; complex64 contraction with FP64 factorisation, tolerance 1e-8.
 One step = the whole SFFT chain for the batch: QTT construction, SFFT apply (zip-up),
 TT rounding and readout of 4096 near-money prices per instance (the Q_n operator is built
-once and cached). A strike grid = one instance's priced M-point log-strike grid: the rounded
-output train, from which every grid price is readable, plus its 4096 read-out prices.
+once and cached), replayed as one captured HIP graph. A strike grid = one instance's priced
+M-point log-strike grid: the rounded output train, from which every grid price is readable,
+plus its 4096 read-out prices. Per-stage times come from HIP events on eager steps.
 The dense Stockham path (all 2^24 prices per instance written to HBM) is timed on the
-same problems for comparison.
+same problems for comparison, and the same draws with uneven n ~ U{16..28} (slot counts
+autotuned, longest chain first) give the ragged-batch figure.
 
 Prints one JSON line.
 """
@@ -44,27 +46,29 @@ def parse():
     ap.add_argument("--dense-instances", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--no-ragged", action="store_true")
     return ap.parse_args()
 
 
 def zipup_flops(xr, wr, yr_zip, n):
-    """Algorithmic FP operations of one zip-up (per instance), from the bond dimensions.
-    Per site: the contraction chi*w*2*r*r' + chi*2*w*2*w'*r' complex MACs (8 real flops each);
-    the pivoted Householder QR of the (2chi) x (w'r') matrix stopped at rank k,
+    """Algorithmic FP operations of one zip-up (per instance), from the bond dimensions:
+    (FP32 flops, FP64 flops). Per site: the complex64 contraction
+    chi*w*2*r*r' + chi*2*w*2*w'*r' complex MACs (8 real flops each); the FP64 pivoted
+    Householder QR of the (2chi) x (w'r') matrix stopped at rank k,
     sum_{i<k} 16 (m-i)(p-i) (reflector application) plus 8 (m-i)(p-i) (norm refresh);
     and forming Q_k, sum_{i<k} 16 (m-i) k."""
-    fl = 0.0
+    f32 = f64 = 0.0
     chi = 1
     for l in range(n):
         w0, w1, r0, r1 = wr[l], wr[l + 1], xr[l], xr[l + 1]
-        fl += 8.0 * (chi * w0 * 2 * r0 * r1 + chi * 2 * w0 * 2 * w1 * r1)
+        f32 += 8.0 * (chi * w0 * 2 * r0 * r1 + chi * 2 * w0 * 2 * w1 * r1)
         if l < n - 1:
             m, p = 2 * chi, w1 * r1
             k = yr_zip[l + 1]
             for i in range(k):
-                fl += 24.0 * (m - i) * (p - i) + 16.0 * (m - i) * k
+                f64 += 24.0 * (m - i) * (p - i) + 16.0 * (m - i) * k
             chi = k
-    return fl
+    return f32, f64
 
 
 def cpu_baseline(problem, budget_s=20.0):
@@ -83,6 +87,29 @@ def cpu_baseline(problem, budget_s=20.0):
     return {"value": done / dt, "unit": "strike grids/s", "cores": threads, "kind": "oracle",
             "sample": f"{done} dense Heston grid(s) at n={problem.n} priced by the numpy FP64 oracle "
                       f"(psi on all 2^{problem.n} points + FFT + readout), {dt:.1f} s"}
+
+
+def ragged_run(cm, torch, batch, nk, steps):
+    """The same parameter draws with n ~ U{16..28}: slot counts autotuned per sweep op,
+    longest chain first, whole chain captured as one HIP graph."""
+    probs = W.heston_batch(batch, seed=20261203, n_range=(16, 28))
+    ns = sorted(set(p.n for p in probs))
+    strikes = torch.from_numpy(np.stack([W.near_money(p, nk) for p in probs])).cuda()
+    mpo = cm.MpoCache(ns, 1e-9, 32, cm.CM_C64)
+    pr = cm.SfftPricer(probs, cm.CM_C64, tol=1e-8, cap=32, mpo=mpo)
+    slots = cm.autotune_slots(pr, strikes, candidates=(512, 1024, 2048, 4096), reps=1)
+    pr.capture(strikes)
+    pr.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        pr.replay()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    st = pr.statuses()
+    return {"grids_per_s": batch / dt, "ms_per_step": dt * 1e3, "slots": slots,
+            "status_errors": {k: int((v != 0).sum()) for k, v in st.items()},
+            "n_hist": {int(n): sum(1 for p in probs if p.n == n) for n in ns}}
 
 
 def main():
@@ -118,30 +145,39 @@ def main():
         if timed:
             ev["build"][1].record(stream)
             ev["apply"][0].record(stream)
-        cm.cm_sfft_apply(pr.mpo.w, pr.x, pr.tol, pr.cap, pr.y, pr.st_apply, pr.ws)
+        pr.apply()
         if timed:
             ev["apply"][1].record(stream)
             ev["round"][0].record(stream)
-        cm.cm_tt_round(pr.y, pr.tol, pr.cap, pr.round_err, pr.st_round, pr.ws)
+        pr.round()
         if timed:
             ev["round"][1].record(stream)
             ev["read"][0].record(stream)
-        cm.cm_readout_prices(pr.y, pr.prob, strikes, nk, prices, pr.st_read)
+        pr.read(strikes, prices)
         if timed:
             ev["read"][1].record(stream)
 
     for _ in range(args.warmup):
         step(False)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
+    # per-stage times on eager steps
     for _ in range(args.steps):
         step(True)
         torch.cuda.synchronize()
         for k in ev:
             acc[k] += ev[k][0].elapsed_time(ev[k][1])
+    # the timed region: the whole chain as one HIP graph, replayed
+    pr.capture(strikes)
+    for _ in range(max(1, args.warmup)):
+        pr.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        pr.replay()
     torch.cuda.synchronize()
     sfft_s = (time.perf_counter() - t0) / args.steps
     sfft_gps = args.batch / sfft_s
+    prices = pr.graph_prices
     stat = pr.statuses()
     bad = {k: int((v != 0).sum()) for k, v in stat.items()}
 
@@ -150,12 +186,23 @@ def main():
     yr = pr.y.ranks.cpu().numpy()
     wr = mpo.w.ranks[args.n].cpu().numpy()
     # zip-up output ranks before rounding: rerun apply once (not timed) to read them
-    cm.cm_sfft_apply(pr.mpo.w, pr.x, pr.tol, pr.cap, pr.y, pr.st_apply, pr.ws)
+    pr.apply()
     torch.cuda.synchronize()
     yz = pr.y.ranks.cpu().numpy()
-    flops = sum(zipup_flops(xr[b], wr, yz[b], args.n) for b in range(args.batch))
+    f32 = f64 = 0.0
+    for b in range(args.batch):
+        a32, a64 = zipup_flops(xr[b], wr, yz[b], args.n)
+        f32 += a32
+        f64 += a64
     apply_ms = acc["apply"] / args.steps
-    achieved_tf = flops / (apply_ms * 1e-3) / 1e12
+    apply_s = apply_ms * 1e-3
+    # fraction of the mixed FP32/FP64 vector roof: sum_i (flops_i / peak_i) / time
+    frac = (f32 / (FP32_VECTOR_TFLOPS * 1e12) + f64 / (FP64_VECTOR_TFLOPS * 1e12)) / apply_s
+    achieved_tf = frac * FP64_VECTOR_TFLOPS
+
+    ragged = None
+    if not args.no_ragged:
+        ragged = ragged_run(cm, torch, args.batch, nk, args.steps)
 
     # dense baseline on a subset of the same problems (all 2^n prices per instance)
     nd = min(args.dense_instances, args.batch)
@@ -218,13 +265,16 @@ def main():
         "max_abs_err_over_S0": max_err,
         "dense_max_abs_err_over_S0": dense_err,
         "stage_ms": {k: acc[k] / args.steps for k in acc},
+        "eager_ms_per_step": sum(acc.values()) / args.steps,
+        "ragged": ragged,
         "mpo_build_s": mpo_s,
         "status_errors": bad,
         "ranks": {"x_max": int(xr[:, :args.n + 1].max()), "y_max": int(yr[:, :args.n + 1].max()),
                   "w_max": int(wr[:args.n + 1].max())},
         "roofline": {"kernel": "k_zipup (cm_sfft_apply)", "bound": "alu", "achieved": achieved_tf,
-                     "peak": FP64_VECTOR_TFLOPS, "unit": "TFLOP/s", "frac": achieved_tf / FP64_VECTOR_TFLOPS,
-                     "traffic": None},
+                     "peak": FP64_VECTOR_TFLOPS, "unit": "TFLOP/s", "frac": frac, "traffic": None,
+                     "note": "achieved = FP64-equivalent rate: (FP32 flops/157.3T + FP64 flops/78.6T)/time x 78.6T",
+                     "flops_fp32": f32, "flops_fp64": f64},
         "dense_roofline": {"kernel": "k_fft_first + k_fft_next", "bound": "hbm", "achieved": dense_gbs,
                            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dense_gbs / HBM_PEAK_GBS},
     }
