@@ -140,6 +140,32 @@ def heston_batch(count: int, seed: int = 20261203, n: Optional[int] = None,
     return out
 
 
+# Surrogate domain: the batched Heston box plus the log-moneyness k = ln(K/S0).
+SURROGATE_K = (-0.5, 0.5)
+SURROGATE_KEYS = ("kappa", "theta", "sigma_v", "rho", "v0", "T", "k")
+
+
+def surrogate_box(enlarge: float = 0.0) -> Tuple[np.ndarray, np.ndarray]:
+    """(lo, hi) of the seven surrogate inputs; `enlarge` widens every interval by that
+    fraction of its width (half on each side), clipped to where the model stays defined
+    (positive rates and volatilities, |rho| < 1, T > 0)."""
+    lo = np.array([HESTON_BOX[k][0] for k in SURROGATE_KEYS[:6]] + [SURROGATE_K[0]], dtype=np.float64)
+    hi = np.array([HESTON_BOX[k][1] for k in SURROGATE_KEYS[:6]] + [SURROGATE_K[1]], dtype=np.float64)
+    w = (hi - lo) * enlarge / 2
+    lo, hi = lo - w, hi + w
+    floor = np.array([0.05, 0.001, 0.02, -0.98, 0.001, 0.02, -np.inf])
+    ceil = np.array([np.inf, np.inf, np.inf, 0.98, np.inf, np.inf, np.inf])
+    return np.maximum(lo, floor), np.minimum(hi, ceil)
+
+
+def surrogate_queries(count: int, seed: int, enlarge: float = 0.0) -> np.ndarray:
+    """[count, 7] float64 query points (kappa, theta, sigma_v, rho, v0, T, k) uniform in the
+    (possibly enlarged) surrogate box, from a Philox stream."""
+    lo, hi = surrogate_box(enlarge)
+    u = _rng(seed).random((count, 7))
+    return lo + (hi - lo) * u
+
+
 def bs_batch(count: int, seed: int = 7, n: int = 12, quad: str = "simpson1") -> List[Problem]:
     """Seeded Black–Scholes instances (sigma in [0.1, 0.5], T in [0.25, 2], r in [0, 0.06])."""
     g = _rng(seed)

@@ -190,6 +190,70 @@ cm_status cm_readout_prices(const cm_tt_batch *y, const cm_problem *prob, const 
 cm_status cm_fft_price(const cm_problem *prob, int batch, int n, int dtype, const int64_t *strike_idx,
                        int nk, void *prices, int32_t *status, void *ws, size_t ws_bytes, void *stream);
 
+/* ------------------------------------------------------------------ pricing surrogate
+ * A project addition (the paper has no learned component): a multilayer perceptron
+ * mapping (kappa, theta, sigma_v, rho, v0, T, k) -- the Heston parameters, the maturity and
+ * the log-moneyness k = ln(K/S0) -- to C/S0, trained on SFFT prices by the kernels below
+ * and gated so that queries outside its training domain go back to the SFFT path.
+ *   xn = (x - shift) * scale;  a1 = silu(W1 xn + b1)  (7 -> 256);
+ *   a_l = silu(W_l a_{l-1} + b_l) for l = 2, 3, 4 (256 -> 256);  y = W5 a4 + b5  (256 -> 1);
+ *   silu(z) = z / (1 + e^-z).
+ * The three 256 x 256 layers run on BF16 MFMA with FP32 accumulation: their weights are the
+ * BF16 copies in w_bf16, and each activation operand is split into two BF16 parts
+ * (hi + lo) so that its rounding stays near FP32; the 7 -> 256 and 256 -> 1 layers, the
+ * loss, and Adam run in FP32.
+ * Parameter vector (FP32, CM_MLP_NPARAMS values, row-major, output index first):
+ *   W1 [256][7] @0, b1 [256] @1792, W2 [256][256] @2048, b2 @67584, W3 @67840, b3 @133376,
+ *   W4 @133632, b4 @199168, W5 [1][256] @199424, b5 @199680. */
+#define CM_MLP_NIN 7
+#define CM_MLP_WIDTH 256
+#define CM_MLP_NPARAMS 199681
+
+typedef struct {
+  float *params;       /* device [CM_MLP_NPARAMS] FP32 master parameters */
+  uint16_t *w_bf16;    /* device [3][256][256] BF16 bit patterns of W2, W3, W4 */
+  float shift[7];      /* host values: input normalisation xn = (x - shift) * scale */
+  float scale[7];
+} cm_mlp;
+
+/* Bytes of saved pre-activations (Z1..Z4, FP32) that cm_mlp_forward writes for a batch of
+ * B rows when asked to, and cm_mlp_backward reads. */
+size_t cm_mlp_act_bytes(int B);
+
+/* Refreshes net->w_bf16 from the FP32 master weights (round to nearest even). */
+cm_status cm_mlp_sync_bf16(const cm_mlp *net, void *stream);
+
+/* y[b] = network(x[b]) for b < B. x: device float [B][7] raw inputs; y: device float [B].
+ * acts: device buffer of acts_bytes bytes. With acts_bytes >= cm_mlp_act_bytes(B) the
+ * pre-activations Z1..Z4 are kept there for cm_mlp_backward; with at least half of that
+ * (inference) two of them are ping-ponged; less is CM_E_INVALID. */
+cm_status cm_mlp_forward(const cm_mlp *net, const float *x, int B, float *y, float *acts, size_t acts_bytes,
+                         void *stream);
+
+/* grad = sum_b dy[b] * d y[b] / d params, overwriting grad (device float [CM_MLP_NPARAMS]).
+ * acts: what cm_mlp_forward saved for the same x. ws: device workspace of
+ * cm_mlp_act_bytes(B) / 2 bytes. Column sums over the batch use float atomics, so the
+ * summation order (and the last bits) may vary between runs. */
+cm_status cm_mlp_backward(const cm_mlp *net, const float *x, const float *acts, const float *dy, int B, float *grad,
+                          void *ws, size_t ws_bytes, void *stream);
+
+/* Mean squared error: dy[b] = 2 (y[b] - t[b]) / B and *loss += mean((y - t)^2) (device
+ * scalar, accumulated with float atomics; the caller zeroes it). */
+cm_status cm_mlp_mse(const float *y, const float *t, int B, float *dy, float *loss, void *stream);
+
+/* One Adam step (Kingma & Ba 2015, bias-corrected) on every parameter: m, v are device
+ * float [CM_MLP_NPARAMS] moment buffers (zero before step 1), step >= 1. Also refreshes
+ * w_bf16. */
+cm_status cm_adam_step(const cm_mlp *net, const float *grad, float *m, float *v, int step, float lr, float beta1,
+                       float beta2, float eps, void *stream);
+
+/* Surrogate gate. accept[b] = 1 if every raw input x[b][i] lies in [lo[i], hi[i]] (host
+ * arrays of 7: the training box) and the predicted y[b] = C/S0 violates the static
+ * no-arbitrage bounds max(0, 1 - e^{k - r T}) <= C/S0 <= 1 by at most res_tol; else 0
+ * (the caller prices those queries with the SFFT path). */
+cm_status cm_surrogate_gate(const float *x, const float *y, int B, const float *lo, const float *hi, float r,
+                            float res_tol, int32_t *accept, void *stream);
+
 /* Short English text for a status code (static storage). */
 const char *cm_status_str(cm_status s);
 

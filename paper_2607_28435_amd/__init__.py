@@ -50,6 +50,12 @@ class CmTTBatch(C.Structure):
     ]
 
 
+class CmMlp(C.Structure):
+    _fields_ = [("params", C.c_void_p), ("w_bf16", C.c_void_p), ("shift", C.c_float * 7), ("scale", C.c_float * 7)]
+
+
+CM_MLP_NIN, CM_MLP_WIDTH, CM_MLP_NPARAMS = 7, 256, 199681
+
 _lib = None
 
 
@@ -73,6 +79,14 @@ def lib() -> C.CDLL:
         "cm_tt_round": (C.c_int, [pb, f64, C.c_int, vp, vp, vp, sz, vp]),
         "cm_readout_prices": (C.c_int, [pb, vp, vp, C.c_int, vp, vp, vp]),
         "cm_fft_price": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, vp, C.c_int, vp, vp, vp, sz, vp]),
+        "cm_mlp_act_bytes": (sz, [C.c_int]),
+        "cm_mlp_sync_bf16": (C.c_int, [C.POINTER(CmMlp), vp]),
+        "cm_mlp_forward": (C.c_int, [C.POINTER(CmMlp), vp, C.c_int, vp, vp, sz, vp]),
+        "cm_mlp_backward": (C.c_int, [C.POINTER(CmMlp), vp, vp, vp, C.c_int, vp, vp, sz, vp]),
+        "cm_mlp_mse": (C.c_int, [vp, vp, C.c_int, vp, vp, vp]),
+        "cm_adam_step": (C.c_int, [C.POINTER(CmMlp), vp, vp, vp, C.c_int, C.c_float, C.c_float, C.c_float,
+                                   C.c_float, vp]),
+        "cm_surrogate_gate": (C.c_int, [vp, vp, C.c_int, vp, vp, C.c_float, C.c_float, vp, vp]),
         "cm_status_str": (C.c_char_p, [C.c_int]),
         "cm_version": (C.c_char_p, []),
     }
@@ -86,7 +100,9 @@ def lib() -> C.CDLL:
 
 def exported_symbols() -> List[str]:
     return ["cm_tt_layout", "cm_workspace_bytes", "cm_qft_mpo", "cm_build_qtt", "cm_sfft_apply",
-            "cm_tt_round", "cm_readout_prices", "cm_fft_price", "cm_status_str", "cm_version"]
+            "cm_tt_round", "cm_readout_prices", "cm_fft_price", "cm_mlp_act_bytes", "cm_mlp_sync_bf16",
+            "cm_mlp_forward", "cm_mlp_backward", "cm_mlp_mse", "cm_adam_step", "cm_surrogate_gate",
+            "cm_status_str", "cm_version"]
 
 
 class CmError(RuntimeError):
@@ -153,6 +169,44 @@ def pack_problems(problems: Sequence, device="cuda"):
         a[i]["p"] = pp
     t = torch.from_numpy(a.view(np.uint8).copy())
     return t.to(device)
+
+
+class ProblemArrays:
+    """A batch of problems held as numpy arrays (one entry per problem), for batches too
+    large to describe problem by problem. Fields follow cm_problem; `model`/`quad` are
+    strings shared by the whole batch, `p` is [count, 5]."""
+
+    def __init__(self, model: str, quad: str, n, S0, r, q, T, alpha, eta, p, k0=None):
+        count = len(np.atleast_1d(T))
+        full = lambda v, dt=np.float64: np.broadcast_to(np.asarray(v, dtype=dt), (count,)).copy()
+        self.model, self.quad = model, quad
+        self.n = full(n, np.int32)
+        self.S0, self.r, self.q, self.T = full(S0), full(r), full(q), full(T)
+        self.alpha, self.eta = full(alpha), full(eta)
+        self.k0 = full(math.nan if k0 is None else k0)
+        pp = np.zeros((count, 5))
+        pa = np.asarray(p, dtype=np.float64)
+        pp[:, :pa.shape[1]] = pa
+        self.p = pp
+
+    def __len__(self):
+        return len(self.T)
+
+    def take(self, idx) -> "ProblemArrays":
+        idx = np.asarray(idx)
+        return ProblemArrays(self.model, self.quad, self.n[idx], self.S0[idx], self.r[idx], self.q[idx],
+                             self.T[idx], self.alpha[idx], self.eta[idx], self.p[idx], self.k0[idx])
+
+    def pack(self, device="cuda"):
+        torch = _torch()
+        a = np.zeros(len(self), dtype=PROBLEM_DTYPE)
+        a["model"] = _MODEL[self.model]
+        a["quad"] = _QUAD[self.quad]
+        a["n"] = self.n
+        a["S0"], a["r"], a["q"], a["T"] = self.S0, self.r, self.q, self.T
+        a["alpha"], a["eta"], a["k0"] = self.alpha, self.eta, self.k0
+        a["p"] = self.p
+        return torch.from_numpy(a.view(np.uint8).copy()).to(device)
 
 
 class TTBatch:
@@ -284,4 +338,48 @@ def cm_fft_price(prob_dev, batch: int, n: int, dtype: int, strike_idx, nk: int, 
     return _check(code, "cm_fft_price")
 
 
+# ------------------------------------------------------------------ surrogate network
+
+def cm_mlp_act_bytes(B: int) -> int:
+    return int(lib().cm_mlp_act_bytes(int(B)))
+
+
+def cm_mlp_sync_bf16(net: CmMlp, stream=None) -> int:
+    return _check(lib().cm_mlp_sync_bf16(C.byref(net), _stream_ptr(stream)), "cm_mlp_sync_bf16")
+
+
+def cm_mlp_forward(net: CmMlp, x, B: int, y, acts, acts_bytes: int, stream=None) -> int:
+    code = lib().cm_mlp_forward(C.byref(net), _ptr(x), int(B), _ptr(y), _ptr(acts), int(acts_bytes),
+                                _stream_ptr(stream))
+    return _check(code, "cm_mlp_forward")
+
+
+def cm_mlp_backward(net: CmMlp, x, acts, dy, B: int, grad, ws, ws_bytes: int, stream=None) -> int:
+    code = lib().cm_mlp_backward(C.byref(net), _ptr(x), _ptr(acts), _ptr(dy), int(B), _ptr(grad), _ptr(ws),
+                                 int(ws_bytes), _stream_ptr(stream))
+    return _check(code, "cm_mlp_backward")
+
+
+def cm_mlp_mse(y, t, B: int, dy, loss, stream=None) -> int:
+    return _check(lib().cm_mlp_mse(_ptr(y), _ptr(t), int(B), _ptr(dy), _ptr(loss), _stream_ptr(stream)),
+                  "cm_mlp_mse")
+
+
+def cm_adam_step(net: CmMlp, grad, m, v, step: int, lr: float, beta1: float = 0.9, beta2: float = 0.999,
+                 eps: float = 1e-8, stream=None) -> int:
+    code = lib().cm_adam_step(C.byref(net), _ptr(grad), _ptr(m), _ptr(v), int(step), float(lr), float(beta1),
+                              float(beta2), float(eps), _stream_ptr(stream))
+    return _check(code, "cm_adam_step")
+
+
+def cm_surrogate_gate(x, y, B: int, lo: Sequence[float], hi: Sequence[float], r: float, res_tol: float, accept,
+                      stream=None) -> int:
+    lo_a = (C.c_float * 7)(*[float(v) for v in lo])
+    hi_a = (C.c_float * 7)(*[float(v) for v in hi])
+    code = lib().cm_surrogate_gate(_ptr(x), _ptr(y), int(B), C.cast(lo_a, C.c_void_p), C.cast(hi_a, C.c_void_p),
+                                   float(r), float(res_tol), _ptr(accept), _stream_ptr(stream))
+    return _check(code, "cm_surrogate_gate")
+
+
 from .pipeline import MpoCache, SfftPricer, autotune_slots, dense_prices  # noqa: E402
+from .surrogate import MlpNet, Surrogate  # noqa: E402

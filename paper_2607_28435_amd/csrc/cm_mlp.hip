@@ -1,0 +1,520 @@
+// Pricing surrogate network (a project addition; the paper has no learned component):
+// forward, backward, MSE, Adam and the gate. Layer equations and the parameter layout are
+// in cm.h.
+//
+// The 256 x 256 layers are GEMMs on BF16 MFMA (v_mfma_f32_32x32x16_bf16) with FP32
+// accumulation: a 256-thread workgroup computes a 64 x 64 tile of C as four 32 x 32 wave
+// tiles, staging 32-deep K slices of both operands in LDS as BF16. An operand that comes
+// from FP32 activations can be split into hi + lo BF16 parts (two MFMAs per step), so its
+// rounding error is ~2^-16 instead of 2^-8. Operand lane layout (32x32x16): lane l holds
+// A[l % 32][8 (l / 32) + i] and B[8 (l / 32) + i][l % 32], i < 8; accumulator v of lane l is
+// C[8 (v / 4) + 4 (l / 32) + v % 4][l % 32].
+#include "cm_internal.h"
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int NW = CM_MLP_WIDTH;
+constexpr int NIN = CM_MLP_NIN;
+constexpr int OFF_W1 = 0, OFF_B1 = 1792, OFF_W5 = 199424, OFF_B5 = 199680;
+__host__ __device__ constexpr int off_w(int l) { return l == 2 ? 2048 : l == 3 ? 67840 : 133632; }
+__host__ __device__ constexpr int off_b(int l) { return l == 2 ? 67584 : l == 3 ? 133376 : 199168; }
+static_assert(OFF_B5 + 1 == CM_MLP_NPARAMS, "parameter layout");
+
+__device__ __forceinline__ float silu_f(float z) { return z / (1.0f + expf(-z)); }
+__device__ __forceinline__ float silu_grad_f(float z) {
+  const float s = 1.0f / (1.0f + expf(-z));
+  return s * (1.0f + z * (1.0f - s));
+}
+
+// float -> bf16 bits, round to nearest even (NaN stays NaN)
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// ------------------------------------------------------------------ GEMM
+constexpr int GT = 64;        // tile edge
+constexpr int KC = 32;        // K slice staged per step
+constexpr int KP = KC + 8;    // LDS row pitch (bf16 elements): 80 bytes, 16-byte aligned rows
+
+enum { A_ROWMAJOR = 0, A_COLMAJOR = 1 };        // A[m lda + k] or A[k lda + m]  (FP32)
+enum { B_F32_KN = 0, B_BF16_NK = 1, B_BF16_KN = 2 };  // B[k ldb + n] fp32, B[n ldb + k] bf16, B[k ldb + n] bf16
+enum { F_NONE = 0, F_SILU = 1 };
+enum { E_BIAS_STORE = 0, E_DSILU_STORE = 1, E_ATOMIC_ADD = 2 };
+
+struct GemmArgs {
+  const float *A;
+  int lda;
+  const void *B;
+  int ldb;
+  int M, N, K, kspan;   // kspan: K range per blockIdx.z
+  float *C;
+  int ldc;
+  const float *bias;    // E_BIAS_STORE
+  const float *Z;       // E_DSILU_STORE: multiply by silu'(Z[m ldc + n])
+};
+
+template <int AL, int AF, bool ASPLIT, int BK, int BF, int EPI>
+__global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
+  __shared__ __align__(16) uint16_t As[2][GT][KP];
+  __shared__ __align__(16) uint16_t Bs[GT][KP];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int n0 = blockIdx.x * GT, m0 = blockIdx.y * GT;
+  const int kbeg = blockIdx.z * g.kspan;
+  const int kend = min(g.K, kbeg + g.kspan);
+  f32x16 acc;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
+  for (int k0 = kbeg; k0 < kend; k0 += KC) {
+    // ---- stage A (64 x 32)
+    if (AL == A_ROWMAJOR) {
+      const int m = tid >> 2, k8 = (tid & 3) * 8;
+      const int gm = m0 + m;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int gk = k0 + k8 + i;
+        float v = (gm < g.M && gk < kend) ? g.A[(int64_t)gm * g.lda + gk] : 0.0f;
+        if (AF == F_SILU) v = silu_f(v);
+        const uint16_t hi = f2bf(v);
+        As[0][m][k8 + i] = hi;
+        if (ASPLIT) As[1][m][k8 + i] = f2bf(v - bf2f(hi));
+      }
+    } else {
+      const int k = tid >> 3, m8 = (tid & 7) * 8;
+      const int gk = k0 + k;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int gm = m0 + m8 + i;
+        float v = (gm < g.M && gk < kend) ? g.A[(int64_t)gk * g.lda + gm] : 0.0f;
+        if (AF == F_SILU) v = silu_f(v);
+        const uint16_t hi = f2bf(v);
+        As[0][m8 + i][k] = hi;
+        if (ASPLIT) As[1][m8 + i][k] = f2bf(v - bf2f(hi));
+      }
+    }
+    // ---- stage B (32 x 64) as Bs[n][k]
+    if (BK == B_BF16_NK) {
+      const int n = tid >> 2, k8 = (tid & 3) * 8;
+      const int gn = n0 + n;
+      const uint16_t *Bb = (const uint16_t *)g.B;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int gk = k0 + k8 + i;
+        Bs[n][k8 + i] = (gn < g.N && gk < kend) ? Bb[(int64_t)gn * g.ldb + gk] : (uint16_t)0;
+      }
+    } else {
+      const int k = tid >> 3, n8 = (tid & 7) * 8;
+      const int gk = k0 + k;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int gn = n0 + n8 + i;
+        uint16_t h = 0;
+        if (gn < g.N && gk < kend) {
+          if (BK == B_BF16_KN) {
+            h = ((const uint16_t *)g.B)[(int64_t)gk * g.ldb + gn];
+          } else {
+            float v = ((const float *)g.B)[(int64_t)gk * g.ldb + gn];
+            if (BF == F_SILU) v = silu_f(v);
+            h = f2bf(v);
+          }
+        }
+        Bs[n8 + i][k] = h;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += 16) {
+      const int kq = kk + 8 * (lane >> 5);
+      const s16x8 bv = *(const s16x8 *)&Bs[wn * 32 + (lane & 31)][kq];
+      const s16x8 av = *(const s16x8 *)&As[0][wm * 32 + (lane & 31)][kq];
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av), __builtin_bit_cast(bf16x8, bv),
+                                                    acc, 0, 0, 0);
+      if (ASPLIT) {
+        const s16x8 al = *(const s16x8 *)&As[1][wm * 32 + (lane & 31)][kq];
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, al),
+                                                      __builtin_bit_cast(bf16x8, bv), acc, 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  // ---- epilogue
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int m = m0 + wm * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+    const int n = n0 + wn * 32 + (lane & 31);
+    if (m < g.M && n < g.N) {
+      float* c = g.C + (int64_t)m * g.ldc + n;
+      if (EPI == E_BIAS_STORE) *c = acc[v] + g.bias[n];
+      else if (EPI == E_DSILU_STORE) *c = acc[v] * silu_grad_f(g.Z[(int64_t)m * g.ldc + n]);
+      else atomicAdd(c, acc[v]);
+    }
+  }
+}
+
+// Weight-stationary layer for the batch dimension: C[M x 256] = epi(op(A) W'), with the
+// whole 256 x 256 BF16 weight matrix held in LDS (Ws[n][k], 132 KB) for the workgroup's
+// lifetime and the workgroup looping over 32-row tiles of A. Each wave computes 32 rows x 64
+// columns (two 32 x 32 accumulators); it reads its A operand straight from global memory
+// (FP32, split into hi + lo BF16 in registers; the four waves read the same rows, which
+// the L1 serves).
+//   W_NK: W' = W^T, Ws[n][k] = W[n][k]   (forward: z = a W^T + b)
+//   W_KN: W' = W,   Ws[n][k] = W[k][n]   (backward data: delta W)
+enum { W_NK = 0, W_KN = 1 };
+constexpr int WSP = NW + 8;   // LDS row pitch of Ws (bf16): 528 bytes, 16-byte aligned
+
+template <int WL, int AF, int EPI>
+__global__ __launch_bounds__(256) void k_gemm_ws(const float *__restrict__ A, const uint16_t *__restrict__ W, int M,
+                                                 float *__restrict__ C, const float *__restrict__ bias,
+                                                 const float *__restrict__ Z) {
+  extern __shared__ __align__(16) uint16_t Ws[];   // [NW][WSP]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (WL == W_NK) {
+    for (int e = tid; e < NW * NW / 8; e += 256) {
+      const int n = e / (NW / 8), k8 = (e % (NW / 8)) * 8;
+      *(uint4 *)&Ws[n * WSP + k8] = *(const uint4 *)&W[n * NW + k8];
+    }
+  } else {
+    for (int e = tid; e < NW * NW; e += 256) {
+      const int k = e / NW, n = e % NW;
+      Ws[n * WSP + k] = W[e];
+    }
+  }
+  __syncthreads();
+  const int ntiles = (M + 31) / 32;
+  const int col0 = wave * 64;
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int row = t * 32 + (lane & 31);
+    const bool rok = row < M;
+    f32x16 acc0, acc1;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) { acc0[v] = 0.0f; acc1[v] = 0.0f; }
+    const float *arow = A + (int64_t)(rok ? row : 0) * NW;
+#pragma unroll 4
+    for (int kk = 0; kk < NW; kk += 16) {
+      const int kq = kk + 8 * (lane >> 5);
+      float a[8];
+      if (rok) {
+        const float4 x0 = *(const float4 *)&arow[kq], x1 = *(const float4 *)&arow[kq + 4];
+        a[0] = x0.x; a[1] = x0.y; a[2] = x0.z; a[3] = x0.w; a[4] = x1.x; a[5] = x1.y; a[6] = x1.z; a[7] = x1.w;
+      } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) a[i] = 0.0f;
+      }
+      s16x8 ah, al;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const float v = (AF == F_SILU) ? silu_f(a[i]) : a[i];
+        const uint16_t h = f2bf(v);
+        ah[i] = (short)h;
+        al[i] = (short)f2bf(v - bf2f(h));
+      }
+      const s16x8 b0 = *(const s16x8 *)&Ws[(col0 + (lane & 31)) * WSP + kq];
+      const s16x8 b1 = *(const s16x8 *)&Ws[(col0 + 32 + (lane & 31)) * WSP + kq];
+      const bf16x8 AH = __builtin_bit_cast(bf16x8, ah), AL = __builtin_bit_cast(bf16x8, al);
+      acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(AH, __builtin_bit_cast(bf16x8, b0), acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(AH, __builtin_bit_cast(bf16x8, b1), acc1, 0, 0, 0);
+      acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(AL, __builtin_bit_cast(bf16x8, b0), acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(AL, __builtin_bit_cast(bf16x8, b1), acc1, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int m = t * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+      if (m < M) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int n = col0 + 32 * h + (lane & 31);
+          const float val = h ? acc1[v] : acc0[v];
+          float *c = C + (int64_t)m * NW + n;
+          if (EPI == E_BIAS_STORE) *c = val + bias[n];
+          else *c = val * silu_grad_f(Z[(int64_t)m * NW + n]);
+        }
+      }
+    }
+  }
+}
+constexpr size_t WS_LDS = sizeof(uint16_t) * NW * WSP;
+
+// ------------------------------------------------------------------ small layers
+// Z1[b][n] = b1[n] + sum_i W1[n][i] xn[b][i]
+__global__ void k_mlp_in(const float *__restrict__ x, int B, const float *__restrict__ p, cm_mlp net,
+                         float *__restrict__ Z1) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= (int64_t)B * NW) return;
+  const int b = (int)(e / NW), n = (int)(e % NW);
+  float acc = p[OFF_B1 + n];
+#pragma unroll
+  for (int i = 0; i < NIN; ++i) acc += p[OFF_W1 + n * NIN + i] * ((x[(int64_t)b * NIN + i] - net.shift[i]) * net.scale[i]);
+  Z1[e] = acc;
+}
+
+// y[b] = b5 + sum_n W5[n] silu(Z4[b][n]); one wavefront per row
+__global__ void k_mlp_out(const float *__restrict__ Z4, int B, const float *__restrict__ p, float *__restrict__ y) {
+  const int b = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (b >= B) return;
+  float acc = 0.0f;
+  for (int n = lane; n < NW; n += 64) acc += p[OFF_W5 + n] * silu_f(Z4[(int64_t)b * NW + n]);
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if (lane == 0) y[b] = acc + p[OFF_B5];
+}
+
+// delta4[b][n] = dy[b] W5[n] silu'(Z4[b][n])
+__global__ void k_out_back(const float *__restrict__ Z4, const float *__restrict__ dy, int B,
+                           const float *__restrict__ p, float *__restrict__ d4) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= (int64_t)B * NW) return;
+  const int b = (int)(e / NW), n = (int)(e % NW);
+  d4[e] = dy[b] * p[OFF_W5 + n] * silu_grad_f(Z4[e]);
+}
+
+// out[n] += sum_{b in chunk} w[b] f(X[b][n])  (w = NULL: weight 1); blockDim = 256 (one
+// thread per column), blockIdx.x = row chunk
+template <int F>
+__global__ void k_colsum(const float *__restrict__ X, const float *__restrict__ w, int B, int rows_per,
+                         float *__restrict__ out) {
+  const int n = threadIdx.x;
+  const int b0 = blockIdx.x * rows_per, b1 = min(B, b0 + rows_per);
+  float acc = 0.0f;
+  for (int b = b0; b < b1; ++b) {
+    float v = X[(int64_t)b * NW + n];
+    if (F == F_SILU) v = silu_f(v);
+    acc += (w ? w[b] : 1.0f) * v;
+  }
+  atomicAdd(out + n, acc);
+}
+
+// gb5 += sum_b dy[b]
+__global__ void k_sum(const float *__restrict__ v, int B, float *__restrict__ out) {
+  float acc = 0.0f;
+  for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < B; b += gridDim.x * blockDim.x) acc += v[b];
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) atomicAdd(out, acc);
+}
+
+// gW1[n][i] += sum_b d1[b][n] xn[b][i], gb1[n] += sum_b d1[b][n]
+__global__ void k_in_back(const float *__restrict__ d1, const float *__restrict__ x, int B, int rows_per, cm_mlp net,
+                          float *__restrict__ grad) {
+  const int n = threadIdx.x;
+  const int b0 = blockIdx.x * rows_per, b1 = min(B, b0 + rows_per);
+  float gw[NIN], gb = 0.0f;
+#pragma unroll
+  for (int i = 0; i < NIN; ++i) gw[i] = 0.0f;
+  for (int b = b0; b < b1; ++b) {
+    const float d = d1[(int64_t)b * NW + n];
+    gb += d;
+#pragma unroll
+    for (int i = 0; i < NIN; ++i) gw[i] += d * ((x[(int64_t)b * NIN + i] - net.shift[i]) * net.scale[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < NIN; ++i) atomicAdd(grad + OFF_W1 + n * NIN + i, gw[i]);
+  atomicAdd(grad + OFF_B1 + n, gb);
+}
+
+__global__ void k_fill(float *__restrict__ a, int64_t n, float v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    a[i] = v;
+}
+
+__global__ void k_mse(const float *__restrict__ y, const float *__restrict__ t, int B, float *__restrict__ dy,
+                      float *__restrict__ loss) {
+  float acc = 0.0f;
+  const float inv = 1.0f / (float)B;
+  for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < B; b += gridDim.x * blockDim.x) {
+    const float r = y[b] - t[b];
+    dy[b] = 2.0f * r * inv;
+    acc += r * r * inv;
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if ((threadIdx.x & 63) == 0 && loss) atomicAdd(loss, acc);
+}
+
+// BF16 copies of W2..W4 live contiguously in w_bf16: layer l's copy at (l - 2) * 65536
+__device__ __forceinline__ int bf16_slot(int i) {
+  for (int l = 2; l <= 4; ++l)
+    if (i >= off_w(l) && i < off_w(l) + NW * NW) return (l - 2) * NW * NW + (i - off_w(l));
+  return -1;
+}
+
+__global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m, float *__restrict__ v,
+                       int n, float lr, float b1, float b2, float eps, float bc1, float bc2,
+                       uint16_t *__restrict__ wbf) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float pi = p[i] - lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+    p[i] = pi;
+    const int s = bf16_slot(i);
+    if (s >= 0) wbf[s] = f2bf(pi);
+  }
+}
+
+__global__ void k_sync_bf16(const float *__restrict__ p, uint16_t *__restrict__ wbf) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < 3 * NW * NW; e += gridDim.x * blockDim.x) {
+    const int l = 2 + e / (NW * NW), i = e % (NW * NW);
+    wbf[e] = f2bf(p[off_w(l) + i]);
+  }
+}
+
+struct GateBox {
+  float lo[NIN], hi[NIN];
+};
+
+__global__ void k_gate(const float *__restrict__ x, const float *__restrict__ y, int B, GateBox box, float r,
+                       float tol, int32_t *__restrict__ accept) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  bool ok = true;
+#pragma unroll
+  for (int i = 0; i < NIN; ++i) {
+    const float xi = x[(int64_t)b * NIN + i];
+    ok = ok && (xi >= box.lo[i]) && (xi <= box.hi[i]);
+  }
+  const float T = x[(int64_t)b * NIN + 5], k = x[(int64_t)b * NIN + 6];
+  const float lower = fmaxf(0.0f, 1.0f - expf(k - r * T));
+  const float yb = y[b];
+  const float res = fmaxf(fmaxf(lower - yb, yb - 1.0f), 0.0f);
+  accept[b] = (ok && res <= tol && yb == yb) ? 1 : 0;
+}
+
+inline unsigned grid_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+extern "C" size_t cm_mlp_act_bytes(int B) { return B > 0 ? (size_t)4 * B * NW * sizeof(float) : 0; }
+
+static bool net_ok(const cm_mlp *net) { return net && net->params && net->w_bf16; }
+
+extern "C" cm_status cm_mlp_sync_bf16(const cm_mlp *net, void *stream) {
+  if (!net_ok(net)) return CM_E_INVALID;
+  hipLaunchKernelGGL(k_sync_bf16, dim3(256), dim3(256), 0, (hipStream_t)stream, net->params, net->w_bf16);
+  CM_LAUNCH_CHECK();
+  return CM_OK;
+}
+
+// persistent workgroups for the weight-stationary layers: one per CU (132 KB of LDS each)
+static int ws_grid(int M) {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+      cus = n;
+    else
+      cus = 256;
+  }
+  const int tiles = (M + 31) / 32;
+  return tiles < cus ? tiles : cus;
+}
+
+extern "C" cm_status cm_mlp_forward(const cm_mlp *net, const float *x, int B, float *y, float *acts,
+                                    size_t acts_bytes, void *stream) {
+  if (!net_ok(net) || !x || !y || !acts || B < 0) return CM_E_INVALID;
+  if (B == 0) return CM_OK;
+  if ((int64_t)B * NW > INT32_MAX) return CM_E_UNSUPPORTED;
+  const bool keep = acts_bytes >= cm_mlp_act_bytes(B);
+  if (!keep && acts_bytes < cm_mlp_act_bytes(B) / 2) return CM_E_INVALID;
+  hipStream_t s = (hipStream_t)stream;
+  float *Z[4];
+  for (int l = 0; l < 4; ++l) Z[l] = acts + (int64_t)(keep ? l : (l & 1)) * B * NW;
+  CM_HIP_CHECK(cm_allow_lds(k_gemm_ws<W_NK, F_SILU, E_BIAS_STORE>, WS_LDS));
+  hipLaunchKernelGGL(k_mlp_in, dim3(grid_for((int64_t)B * NW, 256)), dim3(256), 0, s, x, B, net->params, *net, Z[0]);
+  CM_LAUNCH_CHECK();
+  for (int l = 2; l <= 4; ++l) {
+    hipLaunchKernelGGL((k_gemm_ws<W_NK, F_SILU, E_BIAS_STORE>), dim3(ws_grid(B)), dim3(256), WS_LDS, s, Z[l - 2],
+                       net->w_bf16 + (int64_t)(l - 2) * NW * NW, B, Z[l - 1], net->params + off_b(l),
+                       (const float *)nullptr);
+    CM_LAUNCH_CHECK();
+  }
+  hipLaunchKernelGGL(k_mlp_out, dim3(grid_for(B, 4)), dim3(256), 0, s, Z[3], B, net->params, y);
+  CM_LAUNCH_CHECK();
+  return CM_OK;
+}
+
+extern "C" cm_status cm_mlp_backward(const cm_mlp *net, const float *x, const float *acts, const float *dy, int B,
+                                     float *grad, void *ws, size_t ws_bytes, void *stream) {
+  if (!net_ok(net) || !x || !acts || !dy || !grad || B < 0) return CM_E_INVALID;
+  if (B == 0) return CM_OK;
+  if (!ws || ws_bytes < cm_mlp_act_bytes(B) / 2) return CM_E_INVALID;
+  hipStream_t s = (hipStream_t)stream;
+  const float *Z[4];
+  for (int l = 0; l < 4; ++l) Z[l] = acts + (int64_t)l * B * NW;
+  float *D[2] = {(float *)ws, (float *)ws + (int64_t)B * NW};
+  const float *p = net->params;
+  CM_HIP_CHECK(cm_allow_lds(k_gemm_ws<W_KN, F_NONE, E_DSILU_STORE>, WS_LDS));
+  hipLaunchKernelGGL(k_fill, dim3(256), dim3(256), 0, s, grad, (int64_t)CM_MLP_NPARAMS, 0.0f);
+  hipLaunchKernelGGL(k_out_back, dim3(grid_for((int64_t)B * NW, 256)), dim3(256), 0, s, Z[3], dy, B, p, D[0]);
+  const int rows_per = 64;
+  const unsigned chunks = grid_for(B, rows_per);
+  hipLaunchKernelGGL(k_colsum<F_SILU>, dim3(chunks), dim3(NW), 0, s, Z[3], dy, B, rows_per, grad + OFF_W5);
+  hipLaunchKernelGGL(k_sum, dim3(64), dim3(256), 0, s, dy, B, grad + OFF_B5);
+  CM_LAUNCH_CHECK();
+  // split-K over the batch for the weight gradients: about 256 rows per workgroup
+  const int kspan = 256;
+  const unsigned ksplit = grid_for(B, kspan);
+  int cur = 0;
+  for (int l = 4; l >= 2; --l) {
+    const float *dl = D[cur];
+    {  // gW_l[m][n] += sum_b delta_l[b][m] silu(Z_{l-1}[b][n])
+      GemmArgs g{};
+      g.A = dl; g.lda = NW;
+      g.B = Z[l - 2]; g.ldb = NW;
+      g.M = NW; g.N = NW; g.K = B; g.kspan = kspan;
+      g.C = grad + off_w(l); g.ldc = NW;
+      hipLaunchKernelGGL((k_gemm<A_COLMAJOR, F_NONE, true, B_F32_KN, F_SILU, E_ATOMIC_ADD>),
+                         dim3(NW / GT, NW / GT, ksplit), dim3(256), 0, s, g);
+    }
+    hipLaunchKernelGGL(k_colsum<F_NONE>, dim3(chunks), dim3(NW), 0, s, dl, (const float *)nullptr, B, rows_per,
+                       grad + off_b(l));
+    // delta_{l-1}[b][n] = (sum_k delta_l[b][k] W_l[k][n]) silu'(Z_{l-1}[b][n])
+    hipLaunchKernelGGL((k_gemm_ws<W_KN, F_NONE, E_DSILU_STORE>), dim3(ws_grid(B)), dim3(256), WS_LDS, s, dl,
+                       net->w_bf16 + (int64_t)(l - 2) * NW * NW, B, D[cur ^ 1], (const float *)nullptr, Z[l - 2]);
+    CM_LAUNCH_CHECK();
+    cur ^= 1;
+  }
+  hipLaunchKernelGGL(k_in_back, dim3(chunks), dim3(NW), 0, s, D[cur], x, B, rows_per, *net, grad);
+  CM_LAUNCH_CHECK();
+  return CM_OK;
+}
+
+extern "C" cm_status cm_mlp_mse(const float *y, const float *t, int B, float *dy, float *loss, void *stream) {
+  if (!y || !t || !dy || B < 0) return CM_E_INVALID;
+  if (B == 0) return CM_OK;
+  hipLaunchKernelGGL(k_mse, dim3(grid_for(B, 256) < 1024 ? grid_for(B, 256) : 1024), dim3(256), 0,
+                     (hipStream_t)stream, y, t, B, dy, loss);
+  CM_LAUNCH_CHECK();
+  return CM_OK;
+}
+
+extern "C" cm_status cm_adam_step(const cm_mlp *net, const float *grad, float *m, float *v, int step, float lr,
+                                  float beta1, float beta2, float eps, void *stream) {
+  if (!net_ok(net) || !grad || !m || !v || step < 1) return CM_E_INVALID;
+  if (!(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f && eps > 0.0f)) return CM_E_INVALID;
+  const float bc1 = 1.0f - powf(beta1, (float)step), bc2 = 1.0f - powf(beta2, (float)step);
+  hipLaunchKernelGGL(k_adam, dim3(grid_for(CM_MLP_NPARAMS, 256)), dim3(256), 0, (hipStream_t)stream, net->params,
+                     grad, m, v, (int)CM_MLP_NPARAMS, lr, beta1, beta2, eps, bc1, bc2, net->w_bf16);
+  CM_LAUNCH_CHECK();
+  return CM_OK;
+}
+
+extern "C" cm_status cm_surrogate_gate(const float *x, const float *y, int B, const float *lo, const float *hi,
+                                       float r, float res_tol, int32_t *accept, void *stream) {
+  if (!x || !y || !lo || !hi || !accept || B < 0) return CM_E_INVALID;
+  if (B == 0) return CM_OK;
+  GateBox box;
+  for (int i = 0; i < NIN; ++i) { box.lo[i] = lo[i]; box.hi[i] = hi[i]; }
+  hipLaunchKernelGGL(k_gate, dim3(grid_for(B, 256)), dim3(256), 0, (hipStream_t)stream, x, y, B, box, r, res_tol,
+                     accept);
+  CM_LAUNCH_CHECK();
+  return CM_OK;
+}

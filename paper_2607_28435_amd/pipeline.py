@@ -6,8 +6,8 @@ from typing import Dict, Iterable, Optional, Sequence
 
 import numpy as np
 
-from . import (CM_C64, CM_C128, TTBatch, Workspace, cm_build_qtt, cm_fft_price, cm_qft_mpo, cm_readout_prices,
-               cm_sfft_apply, cm_tt_round, pack_problems)
+from . import (CM_C64, CM_C128, ProblemArrays, TTBatch, Workspace, cm_build_qtt, cm_fft_price, cm_qft_mpo,
+               cm_readout_prices, cm_sfft_apply, cm_tt_round, pack_problems)
 
 
 def _torch():
@@ -55,21 +55,27 @@ class SfftPricer:
                  build_tol: Optional[float] = None, mpo_tol: Optional[float] = None, mpo: Optional[MpoCache] = None,
                  device="cuda", stream=None, slots: Optional[Dict[str, Optional[int]]] = None):
         torch = _torch()
-        problems = list(problems)
+        arrays = isinstance(problems, ProblemArrays)
+        if not arrays:
+            problems = list(problems)
         self.batch = len(problems)
-        ns_in = [p.n for p in problems]
+        ns_in = [int(v) for v in problems.n] if arrays else [p.n for p in problems]
         if len(set(ns_in)) > 1:
             # longest chain first; stable among equal n
             self.order = sorted(range(self.batch), key=lambda i: -ns_in[i])
         else:
             self.order = list(range(self.batch))
         self.identity = self.order == list(range(self.batch))
-        self.problems = [problems[i] for i in self.order]
+        if arrays:
+            self.problems = problems if self.identity else problems.take(self.order)
+        else:
+            self.problems = [problems[i] for i in self.order]
         self.dtype, self.tol, self.cap = dtype, tol, cap
         self.build_tol = tol / 10 if build_tol is None else build_tol
-        ns = [p.n for p in self.problems]
+        ns = [ns_in[i] for i in self.order]
+        self.ns = ns
         self.device = device
-        self.prob = pack_problems(self.problems, device)
+        self.prob = self.problems.pack(device) if arrays else pack_problems(self.problems, device)
         self.x = TTBatch(ns, 2, 1, cap, dtype, device)
         self.y = TTBatch(ns, 2, 1, cap, dtype, device)
         self.mpo = mpo if mpo is not None else MpoCache(ns, tol / 10 if mpo_tol is None else mpo_tol, cap, dtype,
@@ -175,7 +181,7 @@ def autotune_slots(pricer: SfftPricer, strikes, candidates: Sequence[int] = (512
     import os
     torch = _torch()
     key = "|".join([torch.cuda.get_device_name(), str(pricer.dtype), str(pricer.cap), str(pricer.batch),
-                    ",".join(f"{n}:{c}" for n, c in sorted(_hist(p.n for p in pricer.problems).items()))])
+                    ",".join(f"{n}:{c}" for n, c in sorted(_hist(pricer.ns).items()))])
     table = {}
     if cache_path and os.path.exists(cache_path):
         with open(cache_path) as f:
