@@ -247,12 +247,15 @@ cm_status cm_mlp_mse(const float *y, const float *t, int B, float *dy, float *lo
 cm_status cm_adam_step(const cm_mlp *net, const float *grad, float *m, float *v, int step, float lr, float beta1,
                        float beta2, float eps, void *stream);
 
-/* Surrogate gate. accept[b] = 1 if every raw input x[b][i] lies in [lo[i], hi[i]] (host
- * arrays of 7: the training box) and the predicted y[b] = C/S0 violates the static
- * no-arbitrage bounds max(0, 1 - e^{k - r T}) <= C/S0 <= 1 by at most res_tol; else 0
- * (the caller prices those queries with the SFFT path). */
-cm_status cm_surrogate_gate(const float *x, const float *y, int B, const float *lo, const float *hi, float r,
-                            float res_tol, int32_t *accept, void *stream);
+/* Surrogate decode and gate. The network output z[b] decodes to the price
+ * y[b] = C/S0 = e^{z[b]} - out_eps when out_eps > 0 (a network trained on log(C/S0 + out_eps))
+ * and y[b] = z[b] when out_eps == 0; y goes to price (device float [B], may be NULL).
+ * accept[b] = 1 if every raw input x[b][i] lies in [lo[i], hi[i]] (host arrays of 7: the
+ * trusted box) and y[b] violates the static no-arbitrage bounds
+ * max(0, 1 - e^{k - r T}) <= C/S0 <= 1 by at most res_tol; else 0 (the caller prices those
+ * queries with the SFFT path). */
+cm_status cm_surrogate_gate(const float *x, const float *z, int B, const float *lo, const float *hi, float r,
+                            float res_tol, float out_eps, float *price, int32_t *accept, void *stream);
 
 /* Short English text for a status code (static storage). */
 const char *cm_status_str(cm_status s);

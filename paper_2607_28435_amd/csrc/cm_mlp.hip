@@ -370,8 +370,8 @@ struct GateBox {
   float lo[NIN], hi[NIN];
 };
 
-__global__ void k_gate(const float *__restrict__ x, const float *__restrict__ y, int B, GateBox box, float r,
-                       float tol, int32_t *__restrict__ accept) {
+__global__ void k_gate(const float *__restrict__ x, const float *__restrict__ z, int B, GateBox box, float r,
+                       float tol, float out_eps, float *__restrict__ price, int32_t *__restrict__ accept) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= B) return;
   bool ok = true;
@@ -382,8 +382,9 @@ __global__ void k_gate(const float *__restrict__ x, const float *__restrict__ y,
   }
   const float T = x[(int64_t)b * NIN + 5], k = x[(int64_t)b * NIN + 6];
   const float lower = fmaxf(0.0f, 1.0f - expf(k - r * T));
-  const float yb = y[b];
+  const float yb = out_eps > 0.0f ? expf(z[b]) - out_eps : z[b];
   const float res = fmaxf(fmaxf(lower - yb, yb - 1.0f), 0.0f);
+  if (price) price[b] = yb;
   accept[b] = (ok && res <= tol && yb == yb) ? 1 : 0;
 }
 
@@ -507,14 +508,15 @@ extern "C" cm_status cm_adam_step(const cm_mlp *net, const float *grad, float *m
   return CM_OK;
 }
 
-extern "C" cm_status cm_surrogate_gate(const float *x, const float *y, int B, const float *lo, const float *hi,
-                                       float r, float res_tol, int32_t *accept, void *stream) {
-  if (!x || !y || !lo || !hi || !accept || B < 0) return CM_E_INVALID;
+extern "C" cm_status cm_surrogate_gate(const float *x, const float *z, int B, const float *lo, const float *hi,
+                                       float r, float res_tol, float out_eps, float *price, int32_t *accept,
+                                       void *stream) {
+  if (!x || !z || !lo || !hi || !accept || B < 0 || !(out_eps >= 0.0f)) return CM_E_INVALID;
   if (B == 0) return CM_OK;
   GateBox box;
   for (int i = 0; i < NIN; ++i) { box.lo[i] = lo[i]; box.hi[i] = hi[i]; }
-  hipLaunchKernelGGL(k_gate, dim3(grid_for(B, 256)), dim3(256), 0, (hipStream_t)stream, x, y, B, box, r, res_tol,
-                     accept);
+  hipLaunchKernelGGL(k_gate, dim3(grid_for(B, 256)), dim3(256), 0, (hipStream_t)stream, x, z, B, box, r, res_tol,
+                     out_eps, price, accept);
   CM_LAUNCH_CHECK();
   return CM_OK;
 }

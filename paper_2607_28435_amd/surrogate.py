@@ -114,21 +114,50 @@ def heston_arrays(params6: np.ndarray, n: int, S0: float, r: float, alpha: float
     return ProblemArrays("heston", "simpson1", n, S0, r, 0.0, p[:, 5], alpha, eta_for(n), p[:, :5], k0=k0)
 
 
-class Surrogate:
-    """Gated surrogate over the box [lo, hi] of (kappa, theta, sigma_v, rho, v0, T, k), k =
-    ln(K/S0), for S0 and r fixed; SFFT prices (Simpson rule, n-point grids, alpha damping,
-    complex64 contraction, tolerance tol) train and judge it and price what the gate
-    rejects."""
+# Where the Heston model stays defined (kappa, theta, sigma_v, rho, v0, T, k): the floors and
+# ceilings a widened training box is clipped to.
+_FLOOR = np.array([0.05, 0.001, 0.02, -0.98, 0.001, 0.02, -np.inf])
+_CEIL = np.array([np.inf, np.inf, np.inf, 0.98, np.inf, np.inf, np.inf])
 
-    def __init__(self, lo, hi, S0: float = 100.0, r: float = 0.03, n: int = 16, alpha: float = 1.5,
-                 tol: float = 1e-8, res_tol: float = 1e-3, seed: int = 0, device="cuda"):
+
+def widen(lo, hi, frac: float) -> Tuple[np.ndarray, np.ndarray]:
+    """The box [lo, hi] with every interval widened by `frac` of its width (half on each
+    side), clipped to where the model is defined."""
+    lo = np.asarray(lo, dtype=np.float64)
+    hi = np.asarray(hi, dtype=np.float64)
+    w = (hi - lo) * frac / 2
+    return np.maximum(lo - w, _FLOOR), np.minimum(hi + w, _CEIL)
+
+
+class Surrogate:
+    """Gated surrogate over the trusted box [lo, hi] of (kappa, theta, sigma_v, rho, v0, T, k),
+    k = ln(K/S0), for S0 and r fixed; SFFT prices (Simpson rule, n-point grids, alpha
+    damping, complex64 contraction, tolerance tol) train and judge it and price what the
+    gate rejects.
+
+    The network is trained on a box `train_lo`/`train_hi` wider than the trusted one (by
+    default 20 % of each width, clipped where the model stops being defined), so that no
+    accepted query sits on the edge of the training data, and it predicts
+    z = log(C/S0 + out_eps), which spreads the small prices of out-of-the-money strikes;
+    the gate decodes C/S0 = e^z - out_eps."""
+
+    def __init__(self, lo, hi, train_widen: float = 0.2, S0: float = 100.0, r: float = 0.03, n: int = 16,
+                 alpha: float = 1.5, tol: float = 1e-8, res_tol: float = 1e-3, out_eps: float = 1e-2,
+                 seed: int = 0, device="cuda"):
         self.lo = np.asarray(lo, dtype=np.float64)
         self.hi = np.asarray(hi, dtype=np.float64)
+        self.train_lo, self.train_hi = widen(self.lo, self.hi, train_widen)
         self.S0, self.r, self.n, self.alpha, self.tol, self.res_tol = S0, r, n, alpha, tol, res_tol
+        self.out_eps = out_eps
         self.device = device
-        self.net = MlpNet(self.lo, self.hi, seed=seed, device=device)
+        self.net = MlpNet(self.train_lo, self.train_hi, seed=seed, device=device)
         self._mpo = None
         self.history = []
+
+    def encode(self, price_over_s0: np.ndarray) -> np.ndarray:
+        """Training target for C/S0 (the inverse of the gate's decoding)."""
+        c = np.asarray(price_over_s0, dtype=np.float64)
+        return np.log(np.maximum(c, 0.0) + self.out_eps) if self.out_eps > 0 else c
 
     # -- SFFT prices
     def _mpo_cache(self):
@@ -138,26 +167,39 @@ class Surrogate:
 
     def grid_prices(self, params6: np.ndarray, ks: np.ndarray, chunk: int = 8192) -> Tuple[np.ndarray, np.ndarray]:
         """Training data: each parameter row priced at its row of log-moneyness values
-        (snapped to the grid). Returns (X [rows*per, 7] with snapped k, C/S0 [rows*per])."""
+        (snapped to the grid). Rows whose SFFT reports an error (for instance a damping
+        moment that explodes before T) are dropped. Returns (X [rows*per, 7] with snapped k,
+        C/S0 [rows*per])."""
         torch = _torch()
         n, M = self.n, 2 ** self.n
         lam = 2 * math.pi / (M * eta_for(n))
+        params6 = np.asarray(params6, dtype=np.float64)
         u = np.rint(M / 2 + np.asarray(ks) / lam).astype(np.int64)
         k_snap = lam * (u - M / 2)
         out = np.empty(u.shape, dtype=np.float64)
+        good = np.ones(len(params6), dtype=bool)
         for c0 in range(0, len(params6), chunk):
             sl = slice(c0, min(len(params6), c0 + chunk))
             pa = heston_arrays(params6[sl], n, self.S0, self.r, self.alpha)
             pr = SfftPricer(pa, CM_C64, tol=self.tol, cap=32, mpo=self._mpo_cache(), device=self.device)
             got = pr.run(torch.from_numpy(u[sl]).to(self.device))
-            st = pr.statuses()
-            bad = sum(int((v != CM_OK).sum()) for v in st.values())
-            if bad:
-                raise RuntimeError(f"SFFT training prices: {bad} instance errors")
+            ok = np.ones(sl.stop - sl.start, dtype=bool)
+            for v in pr.statuses().values():
+                ok &= v == CM_OK
+            good[sl] = ok
             out[sl] = got.cpu().numpy() / self.S0
         per = u.shape[1]
-        X = np.concatenate([np.repeat(params6, per, axis=0), k_snap.reshape(-1, 1)], axis=1)
-        return X, out.reshape(-1)
+        X = np.concatenate([np.repeat(params6[good], per, axis=0), k_snap[good].reshape(-1, 1)], axis=1)
+        return X, out[good].reshape(-1)
+
+    def training_set(self, n_sets: int, per: int, seed: int) -> Tuple[np.ndarray, np.ndarray]:
+        """n_sets parameter draws uniform in the training box, each priced at `per` uniform
+        log-moneyness values (Philox streams seed and seed + 1)."""
+        g = np.random.Generator(np.random.Philox(seed))
+        lo, hi = self.train_lo, self.train_hi
+        sets = lo[:6] + (hi[:6] - lo[:6]) * g.random((n_sets, 6))
+        ks = np.random.Generator(np.random.Philox(seed + 1)).uniform(lo[6], hi[6], (n_sets, per))
+        return self.grid_prices(sets, ks)
 
     def query_prices(self, queries: np.ndarray, chunk: int = 16384) -> Tuple[np.ndarray, np.ndarray]:
         """SFFT price of each query (kappa, theta, sigma_v, rho, v0, T, k) at exactly its k: the
@@ -194,11 +236,12 @@ class Surrogate:
     def fit(self, X: np.ndarray, Y: np.ndarray, steps: int, batch: int = 8192, lr: float = 2e-3,
             lr_final: float = 2e-5, warmup: int = 200, log_every: int = 500, seed: int = 1,
             time_budget: Optional[float] = None) -> Dict[str, float]:
-        """Adam on the mean squared error of C/S0 with a warm-up and a cosine decay from lr to
-        lr_final; minibatches are slices of a fresh permutation each epoch."""
+        """Adam on the mean squared error of the encoded price (Y holds C/S0) with a warm-up
+        and a cosine decay from lr to lr_final; minibatches are slices of a fresh
+        permutation each epoch."""
         torch = _torch()
         Xd = torch.from_numpy(np.asarray(X, dtype=np.float32)).to(self.device)
-        Yd = torch.from_numpy(np.asarray(Y, dtype=np.float32)).to(self.device)
+        Yd = torch.from_numpy(self.encode(Y).astype(np.float32)).to(self.device)
         N = Xd.shape[0]
         gen = torch.Generator(device=self.device)
         gen.manual_seed(seed)
@@ -232,13 +275,16 @@ class Surrogate:
 
     # -- inference
     def predict(self, queries_dev):
-        """Network output and gate for device float32 queries [B, 7]: (C/S0 [B], accept [B])."""
+        """Decoded network price and gate for device float32 queries [B, 7]:
+        (C/S0 [B] float32, accept [B] int32)."""
         torch = _torch()
-        y = self.net.forward(queries_dev)
-        acc = torch.empty(queries_dev.shape[0], dtype=torch.int32, device=queries_dev.device)
-        cm_surrogate_gate(queries_dev, y, queries_dev.shape[0], self.lo.tolist(), self.hi.tolist(), self.r,
-                          self.res_tol, acc)
-        return y, acc
+        z = self.net.forward(queries_dev)
+        B = queries_dev.shape[0]
+        price = torch.empty(B, dtype=torch.float32, device=queries_dev.device)
+        acc = torch.empty(B, dtype=torch.int32, device=queries_dev.device)
+        cm_surrogate_gate(queries_dev, z, B, self.lo.tolist(), self.hi.tolist(), self.r, self.res_tol, acc,
+                          out_eps=self.out_eps, price=price)
+        return price, acc
 
     def price(self, queries: np.ndarray) -> Dict[str, np.ndarray]:
         """Gated prices C/S0 for host queries [B, 7]: the network where the gate accepts,
