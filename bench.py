@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--no-ragged", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--surrogate-steps", type=int, default=60000)
     return ap.parse_args()
 
 
@@ -110,6 +112,59 @@ def ragged_run(cm, torch, batch, nk, steps):
     return {"grids_per_s": batch / dt, "ms_per_step": dt * 1e3, "slots": slots,
             "status_errors": {k: int((v != 0).sum()) for k, v in st.items()},
             "n_hist": {int(n): sum(1 for p in probs if p.n == n) for n in ns}}
+
+
+BF16_DENSE_TFLOPS = 2500.0
+
+
+def surrogate_run(cm, torch, steps):
+    """Surrogate (config 5): train on 2^22 SFFT samples (2^16 parameter sets x 64 k, training
+    box 20 % wider than the trusted box), then 2^20 held-out queries (90 % in the trusted
+    box, 10 % from a box enlarged by 20 %): gated prices vs the SFFT judge, accept rate, and
+    network+gate throughput against batched SFFT pricing of the same queries."""
+    from paper_2607_28435_amd.surrogate import Surrogate
+    lo, hi = W.surrogate_box()
+    t0 = time.perf_counter()
+    s = Surrogate(lo, hi, seed=0)
+    X, Y = s.training_set(2 ** 16, 64, seed=1001)
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    info = s.fit(X, Y, steps=steps, batch=8192, lr=2e-3, log_every=max(1, steps // 20))
+    nq = 2 ** 20
+    q = np.concatenate([W.surrogate_queries(nq - nq // 10, 5001), W.surrogate_queries(nq // 10, 5002, enlarge=0.2)])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    judge, st = s.query_prices(q)
+    torch.cuda.synchronize()
+    sfft_s = time.perf_counter() - t0
+    res = s.price(q)
+    acc = res["accept"]
+    ok = acc & (st == 0)
+    err = np.abs(res["price"] - judge)
+    # network + gate throughput on all queries (device-resident inputs)
+    qd = torch.from_numpy(q.astype(np.float32)).cuda()
+    s.predict(qd)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 10
+    e0.record(stream)
+    for _ in range(reps):
+        s.predict(qd)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    net_s = e0.elapsed_time(e1) * 1e-3 / reps
+    flops = 2.0 * 199681 * nq          # algorithmic (one multiply-add per weight per query)
+    executed = flops + 2.0 * 3 * 65536 * nq   # the activation split runs the 256x256 layers twice
+    ach = flops / net_s / 1e12
+    return {"train_samples": int(len(Y)), "train_steps": info["steps"], "train_s": info["seconds"],
+            "data_gen_s": gen_s, "final_train_loss": info["final_loss"],
+            "eval_queries": nq, "accept_rate": float(acc.mean()), "in_box_accept_rate": float(acc[:nq - nq // 10].mean()),
+            "in_gate_max_abs_err_over_S0": float(err[ok].max()), "in_gate_p999_abs_err_over_S0":
+                float(np.quantile(err[ok], 0.999)), "judge_failures": int((st != 0).sum()),
+            "queries_per_s": nq / net_s, "sfft_queries_per_s": nq / sfft_s, "speedup_vs_sfft": sfft_s / net_s,
+            "roofline": {"kernel": "k_mlp_in + 3x k_gemm_ws + k_mlp_out + k_gate", "bound": "mfma",
+                         "achieved": ach, "peak": BF16_DENSE_TFLOPS, "unit": "TFLOP/s",
+                         "frac": ach / BF16_DENSE_TFLOPS, "executed_tflops": executed / net_s / 1e12}}
 
 
 def main():
@@ -203,6 +258,9 @@ def main():
     ragged = None
     if not args.no_ragged:
         ragged = ragged_run(cm, torch, args.batch, nk, args.steps)
+    surrogate = None
+    if not args.no_surrogate:
+        surrogate = surrogate_run(cm, torch, args.surrogate_steps)
 
     # dense baseline on a subset of the same problems (all 2^n prices per instance)
     nd = min(args.dense_instances, args.batch)
@@ -267,6 +325,7 @@ def main():
         "stage_ms": {k: acc[k] / args.steps for k in acc},
         "eager_ms_per_step": sum(acc.values()) / args.steps,
         "ragged": ragged,
+        "surrogate": surrogate,
         "mpo_build_s": mpo_s,
         "status_errors": bad,
         "ranks": {"x_max": int(xr[:, :args.n + 1].max()), "y_max": int(yr[:, :args.n + 1].max()),
