@@ -48,6 +48,10 @@ def parse():
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--no-ragged", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--no-graph", action="store_true", help="time eager steps instead of graph replays "
+                    "(for counter-collection runs)")
+    ap.add_argument("--copy-calibration", action="store_true", help="run one 1 GiB device copy first: the "
+                    "reference a traffic counter is scaled by")
     ap.add_argument("--surrogate-steps", type=int, default=60000)
     return ap.parse_args()
 
@@ -116,6 +120,36 @@ def ragged_run(cm, torch, batch, nk, steps):
 
 BF16_DENSE_TFLOPS = 2500.0
 
+# HBM bytes per dispatch from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs recorded in
+# profiles/traffic_pmc_heston4096_n24.md (fetch scaled by 2.0 and write by 1.0, the factors a
+# 1 GiB device copy gives). A figure is reported only while the kernel's sources hash to the
+# value they had when the counters were taken.
+ZIPUP_SOURCES = ["paper_2607_28435_amd/csrc/cm_zipup.hip", "paper_2607_28435_amd/csrc/cm_tt.h",
+                 "paper_2607_28435_amd/csrc/cm_linalg.h", "paper_2607_28435_amd/csrc/cm_internal.h", "include/cm.h"]
+FFT_SOURCES = ["paper_2607_28435_amd/csrc/cm_fft.hip", "paper_2607_28435_amd/csrc/cm_cf.h",
+               "paper_2607_28435_amd/csrc/cm_tt.h", "paper_2607_28435_amd/csrc/cm_linalg.h",
+               "paper_2607_28435_amd/csrc/cm_internal.h", "include/cm.h"]
+PROFILED_TRAFFIC = {
+    "k_zipup": {"sha": "a710431600e496cf", "bytes": (523237.2 * 2.0 + 3206053.0) * 1024,
+                "per": "launch (4096 instances, n=24)"},
+    "dense": {"sha": "832b27751174ac25", "bytes": ((142.2 + 65640.8) * 2.0 + 131072.0 + 65536.0) * 1024,
+              "per": "grid (k_fft_first + k_fft_next, n=24)"},
+}
+
+
+def _sources_sha(files):
+    import hashlib
+    m = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            m.update(fh.read())
+    return m.hexdigest()[:16]
+
+
+def profiled_traffic(name, files):
+    rec = PROFILED_TRAFFIC[name]
+    return rec["bytes"] if _sources_sha(files) == rec["sha"] else None
+
 
 def surrogate_run(cm, torch, steps):
     """Surrogate (config 5): train on 2^22 SFFT samples (2^16 parameter sets x 64 k, training
@@ -177,6 +211,12 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = "cuda"
+    if args.copy_calibration:
+        a = torch.ones(2 ** 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     stream = torch.cuda.current_stream()
     probs = W.heston_batch(args.batch, seed=20261203, n=args.n)
     nk = 4096
@@ -222,17 +262,23 @@ def main():
         for k in ev:
             acc[k] += ev[k][0].elapsed_time(ev[k][1])
     # the timed region: the whole chain as one HIP graph, replayed
-    pr.capture(strikes)
-    for _ in range(max(1, args.warmup)):
-        pr.replay()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        pr.replay()
-    torch.cuda.synchronize()
+    if args.no_graph:
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step(False)
+        torch.cuda.synchronize()
+    else:
+        pr.capture(strikes)
+        for _ in range(max(1, args.warmup)):
+            pr.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            pr.replay()
+        torch.cuda.synchronize()
+        prices = pr.graph_prices
     sfft_s = (time.perf_counter() - t0) / args.steps
     sfft_gps = args.batch / sfft_s
-    prices = pr.graph_prices
     stat = pr.statuses()
     bad = {k: int((v != 0).sum()) for k, v in stat.items()}
 
@@ -331,11 +377,15 @@ def main():
         "ranks": {"x_max": int(xr[:, :args.n + 1].max()), "y_max": int(yr[:, :args.n + 1].max()),
                   "w_max": int(wr[:args.n + 1].max())},
         "roofline": {"kernel": "k_zipup (cm_sfft_apply)", "bound": "alu", "achieved": achieved_tf,
-                     "peak": FP64_VECTOR_TFLOPS, "unit": "TFLOP/s", "frac": frac, "traffic": None,
+                     "peak": FP64_VECTOR_TFLOPS, "unit": "TFLOP/s", "frac": frac,
+                     "traffic": profiled_traffic("k_zipup", ZIPUP_SOURCES),
+                     "traffic_per": PROFILED_TRAFFIC["k_zipup"]["per"],
                      "note": "achieved = FP64-equivalent rate: (FP32 flops/157.3T + FP64 flops/78.6T)/time x 78.6T",
                      "flops_fp32": f32, "flops_fp64": f64},
         "dense_roofline": {"kernel": "k_fft_first + k_fft_next", "bound": "hbm", "achieved": dense_gbs,
-                           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dense_gbs / HBM_PEAK_GBS},
+                           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dense_gbs / HBM_PEAK_GBS,
+                           "algorithmic_bytes": dense_bytes, "traffic": profiled_traffic("dense", FFT_SOURCES),
+                           "traffic_per": PROFILED_TRAFFIC["dense"]["per"]},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(probs[0])
