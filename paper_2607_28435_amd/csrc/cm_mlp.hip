@@ -3,10 +3,12 @@
 // in cm.h.
 //
 // The 256 x 256 layers are GEMMs on BF16 MFMA (v_mfma_f32_32x32x16_bf16) with FP32
-// accumulation: a 256-thread workgroup computes a 64 x 64 tile of C as four 32 x 32 wave
-// tiles, staging 32-deep K slices of both operands in LDS as BF16. An operand that comes
-// from FP32 activations can be split into hi + lo BF16 parts (two MFMAs per step), so its
-// rounding error is ~2^-16 instead of 2^-8. Operand lane layout (32x32x16): lane l holds
+// accumulation. Forward and backward-data use k_gemm_ws (the weight matrix stays in LDS for
+// a persistent workgroup that streams 32-row tiles of activations); the weight gradients use
+// k_gemm (64 x 64 output tiles as four 32 x 32 wave tiles, 32-deep K slices of both operands
+// staged in LDS as BF16, split-K over the batch). An operand that comes from FP32
+// activations is split into hi + lo BF16 parts (two MFMAs per step), so its rounding error
+// is ~2^-16 instead of 2^-8. Operand lane layout (32x32x16): lane l holds
 // A[l % 32][8 (l / 32) + i] and B[8 (l / 32) + i][l % 32], i < 8; accumulator v of lane l is
 // C[8 (v / 4) + 4 (l / 32) + v % 4][l % 32].
 #include "cm_internal.h"
