@@ -308,6 +308,10 @@ __device__ __forceinline__ int qr_thin(double2 *Y, int m, int p, double2 *Qout, 
 // Outputs: Qk (m x k, ld m) with orthonormal columns; the k x p factor B = R[:k,:] P^T is
 // written to B (ld k). nrm (p doubles) and perm (p ints) are scratch. Returns k; sh.err2
 // holds the dropped squared norm. p <= 1024.
+// The remaining column norms nrm[c] (rows >= i at step i) are recomputed exactly from the
+// updated entries after every reflection, so the pivot column's norm gives the reflector's
+// beta without another reduction, and wave 0 forms the tail sum together with the pivot
+// search: five barriers per step.
 __device__ __forceinline__ int cpqr_trunc(double2 *T, int m, int p, double delta2, int cap, double2 *Qk,
                                           double2 *B, double *nrm, int *perm, Sh &sh) {
   const int tid = threadIdx.x;
@@ -327,39 +331,39 @@ __device__ __forceinline__ int cpqr_trunc(double2 *T, int m, int p, double delta
   __shared__ double tail_sh;
   __shared__ int piv_sh;
   __shared__ int k_sh;
+  if (tid == 0) { k_sh = 0; sh.rankcap = 0; sh.nonfinite = 0; tail_sh = 0.0; }
   __syncthreads();
-  {
-    double part = 0.0;
-    for (int c = tid; c < p; c += CM_WG) part += nrm[c];
-    const double t = wg_sum(part, sh.red);
-    if (tid == 0) { tail_sh = t; k_sh = 0; sh.rankcap = 0; sh.nonfinite = !(t == t) || isinf(t); }
-    __syncthreads();
-  }
   for (int i = 0; i < kmax; ++i) {
-    const double tail = tail_sh;
-    if (i >= 1 && tail <= delta2) break;
-    if (i == cap) {
-      if (tid == 0) sh.rankcap = 1;
-      break;
-    }
-    // pivot: argmax nrm[c], c >= i (wave 0)
+    // wave 0: tail = sum of the remaining norms, pivot = their argmax
     if (tid < 64) {
-      double best = -1.0;
+      double best = -1.0, sum = 0.0;
       int bi = i;
       for (int c = i + tid; c < p; c += 64) {
         const double v = nrm[c];
+        sum += v;
         if (v > best) { best = v; bi = c; }
       }
       for (int o = 32; o > 0; o >>= 1) {
         const double ob = __shfl_xor(best, o, 64);
         const int oi = __shfl_xor(bi, o, 64);
+        sum += __shfl_xor(sum, o, 64);
         if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
       }
-      if (tid == 0) piv_sh = bi;
+      if (tid == 0) { piv_sh = bi; tail_sh = sum; }
     }
     __syncthreads();
+    const double tail = tail_sh;
+    if (!(tail == tail) || isinf(tail)) {
+      if (tid == 0) sh.nonfinite = 1;
+      break;
+    }
+    if (i >= 1 && tail <= delta2) break;
+    if (i == cap) {
+      if (tid == 0) sh.rankcap = 1;
+      break;
+    }
     const int pv = piv_sh;
-    if (pv != i) {
+    if (pv != i) {   // uniform
       for (int r = tid; r < m; r += CM_WG) {
         const double2 t = T[r + (int64_t)m * i];
         T[r + (int64_t)m * i] = T[r + (int64_t)m * pv];
@@ -369,19 +373,17 @@ __device__ __forceinline__ int cpqr_trunc(double2 *T, int m, int p, double delta
         const double t = nrm[i]; nrm[i] = nrm[pv]; nrm[pv] = t;
         const int q = perm[i]; perm[i] = perm[pv]; perm[pv] = q;
       }
+      __syncthreads();
     }
-    __syncthreads();
-    // Householder reflector for T[i:m, i]
-    double part = 0.0;
-    for (int r = i + 1 + tid; r < m; r += CM_WG) part += cabs2(T[r + (int64_t)m * i]);
-    const double xn2 = wg_sum(part, sh.red);
+    // Householder reflector for T[i:m, i]; ||T[i:m, i]||^2 = nrm[i]
     if (tid == 0) {
       const double2 a = T[i + (int64_t)m * i];
-      if (xn2 == 0.0 && a.y == 0.0) {
+      const double norm2 = nrm[i];
+      if (!(norm2 > 0.0)) {
         sh.tau[i] = cmk(0.0, 0.0);
         sh.scal = cmk(0.0, 0.0);
       } else {
-        const double beta = -copysign(sqrt(a.x * a.x + a.y * a.y + xn2), a.x);
+        const double beta = -copysign(sqrt(norm2), a.x);
         sh.tau[i] = cmk((beta - a.x) / beta, -a.y / beta);
         sh.scal = cdiv(cmk(1.0, 0.0), csub(a, cmk(beta, 0.0)));
         T[i + (int64_t)m * i] = cmk(beta, 0.0);
@@ -398,7 +400,6 @@ __device__ __forceinline__ int cpqr_trunc(double2 *T, int m, int p, double delta
     }
     // apply H^H to trailing columns; refresh their norms below row i
     const int ncols = p - i - 1;
-    double tpart = 0.0;
     if (ncols > 0) {
       const int G = group_for(ncols), groups = CM_WG / G, lane = tid % G;
       const double2 ctc = cconj(tc);
@@ -425,11 +426,10 @@ __device__ __forceinline__ int cpqr_trunc(double2 *T, int m, int p, double delta
           }
         }
         a = grp_sum(a, G);
-        if (ok && lane == 0) { nrm[j] = a; tpart += a; }
+        if (ok && lane == 0) nrm[j] = a;
       }
     }
-    const double t = wg_sum(tpart, sh.red);
-    if (tid == 0) tail_sh = t;
+    if (tid == 0 && i + 1 == kmax) tail_sh = 0.0;   // nothing remains below or beside
     __syncthreads();
   }
   const int k = k_sh;

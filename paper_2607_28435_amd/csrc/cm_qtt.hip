@@ -31,7 +31,9 @@ constexpr int QNC = 64;         // max candidate intervals per depth
 constexpr int QI = QNC / 2;     // max split intervals per depth
 constexpr int QNPT = 2 * QP - 1;
 constexpr int PRE_CAP = QI + QP + 1;   // bond bound before rounding (<= 64)
-constexpr int QLDS = 38 * 1024;        // LDS arena per workgroup (four workgroups per CU)
+// LDS arena per workgroup: small on purpose (see cm_round.hip); the tree phase's candidate
+// values then live in the slab as well.
+constexpr int QLDS = 8 * 1024;
 
 struct TreeDepth {
   int n_int;                 // split intervals at this depth
@@ -64,6 +66,7 @@ __host__ __device__ inline size_t qtt_slab_bytes(int n_max, int cap, size_t *par
   parts[4] = o; o += align256(sizeof(double2) * core_cap * n_max);  // rs.tt
   parts[5] = o; o += align256(sizeof(double2) * core_cap * 6);      // rs.Y..C
   parts[6] = o; o += align256(sizeof(double2) * 2 * 64 * 64);        // global Jacobi pair
+  parts[7] = o; o += align256(sizeof(double2) * QNC * QNPT);         // candidate values
   return o;
 }
 
@@ -126,12 +129,12 @@ __global__ __launch_bounds__(CM_WG) void k_build_qtt(const cm_problem *__restric
   __shared__ int8_t kind_sh[QNC];
   __shared__ double err_sh[QNC];
   const int tid = threadIdx.x;
-  // LDS arena: the tree phase keeps candidate values (vals[QNC][QNPT]) there; the rounding
-  // phase reuses it for its matrices
-  double2 *vals = (double2 *)lds_arena;
-  size_t parts[7];
+  // candidate values (vals[QNC][QNPT]) of the tree phase: in the LDS arena when it is large
+  // enough, else in the slab; the rounding phase reuses the arena for its matrices
+  size_t parts[8];
   qtt_slab_bytes(n_max, cap, parts);
   char *slab = ws + (size_t)blockIdx.x * slab_bytes;
+  double2 *vals = (sizeof(double2) * QNC * QNPT <= (size_t)QLDS) ? (double2 *)lds_arena : (double2 *)(slab + parts[7]);
   QttSlab W;
   W.tree = (TreeDepth *)(slab + parts[0]);
   W.pre = (double2 *)(slab + parts[1]);
@@ -372,7 +375,7 @@ __global__ __launch_bounds__(CM_WG) void k_build_qtt(const cm_problem *__restric
 
 // ------------------------------------------------------------------ host side
 extern "C" size_t cm_qtt_slab_bytes(int n_max, int cap) {
-  size_t parts[7];
+  size_t parts[8];
   return qtt_slab_bytes(n_max, cap, parts);
 }
 
@@ -391,7 +394,6 @@ extern "C" cm_status cm_build_qtt(const cm_problem *prob, int batch, double tol,
   if (slots < 1) return CM_E_INVALID;
   const size_t slab = cm_qtt_slab_bytes(x->n_max, cap_rank);
   const size_t lds = QLDS;
-  static_assert(sizeof(double2) * QNC * QNPT <= QLDS, "tree values must fit the LDS arena");
   TTView v = tt_view(x);
   hipStream_t s = (hipStream_t)stream;
   CM_HIP_CHECK(cm_allow_lds(k_build_qtt<float2>, lds));

@@ -19,7 +19,9 @@ namespace {
 
 constexpr int ZCHI = 32;          // zip-up bond limit
 constexpr int ZW = 24;            // largest operator bond supported by the workspace layout
-constexpr int ZLDS = 72 * 1024;   // LDS arena per workgroup (two workgroups per CU)
+// LDS arena per workgroup: sized so that four 256-thread workgroups share a CU (typical sites
+// fit; larger ones use the slab), which measured faster than two with a 72 KB arena.
+constexpr int ZLDS = 16 * 1024;
 
 __host__ __device__ inline size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
