@@ -118,7 +118,9 @@ __device__ __forceinline__ double v0mf_frac(const cm_problem &pr) {
 }
 
 template <typename OutT>
-__global__ __launch_bounds__(CM_WG) void k_build_qtt(const cm_problem *__restrict__ prob, int batch,
+// At most 256 VGPRs (two waves per SIMD): left alone the compiler takes 256 VGPRs plus AGPRs
+// and one wave per SIMD; two halve the build time despite a small spill.
+__global__ __launch_bounds__(CM_WG, 2) void k_build_qtt(const cm_problem *__restrict__ prob, int batch,
                                                      double tol, int cap, TTView x,
                                                      int32_t *__restrict__ status,
                                                      char *__restrict__ ws, size_t slab_bytes, int n_max) {
