@@ -19,9 +19,64 @@ __device__ __forceinline__ int pow2floor(int x) {
   return p;
 }
 
+// Cross-lane moves inside rows of 16 lanes (DPP, no LDS traffic): quad_perm [1,0,3,2] and
+// [2,3,0,1], row_half_mirror and row_mirror. In an aligned group of 2, 4, 8 or 16 lanes each
+// step pairs every lane with one holding the complementary partial result, so after
+// log2(G) steps every lane of the group holds the same (bit-identical) reduction.
+constexpr int DPP_XOR1 = 0xB1, DPP_XOR2 = 0x4E, DPP_HALF_MIRROR = 0x141, DPP_MIRROR = 0x140;
+
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = dpp_i<CTRL>(__double2loint(v)), hi = dpp_i<CTRL>(__double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over aligned groups of G lanes (G a power of two <= 64); every lane of the wave must
+// take part.
 __device__ __forceinline__ double grp_sum(double v, int G) {
-  for (int o = G >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
+  if (G >= 2) v += dpp_d<DPP_XOR1>(v);
+  if (G >= 4) v += dpp_d<DPP_XOR2>(v);
+  if (G >= 8) v += dpp_d<DPP_HALF_MIRROR>(v);
+  if (G >= 16) v += dpp_d<DPP_MIRROR>(v);
+  if (G >= 32) v += __shfl_xor(v, 16, 64);
+  if (G >= 64) v += __shfl_xor(v, 32, 64);
   return v;
+}
+
+// Maximum over the 64 lanes of a wave; every lane must take part.
+__device__ __forceinline__ double wave_max(double v) {
+  v = fmax(v, dpp_d<DPP_XOR1>(v));
+  v = fmax(v, dpp_d<DPP_XOR2>(v));
+  v = fmax(v, dpp_d<DPP_HALF_MIRROR>(v));
+  v = fmax(v, dpp_d<DPP_MIRROR>(v));
+  v = fmax(v, __shfl_xor(v, 16, 64));
+  return fmax(v, __shfl_xor(v, 32, 64));
+}
+
+// Over the 64 lanes of a wave: the largest `best` (ties to the smaller index `bi`) and the
+// sum of `sum`; every lane must take part and ends with the same result.
+template <int CTRL>
+__device__ __forceinline__ void argmax_sum_step(double &best, int &bi, double &sum) {
+  const double ob = dpp_d<CTRL>(best);
+  const int oi = dpp_i<CTRL>(bi);
+  sum += dpp_d<CTRL>(sum);
+  if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+}
+__device__ __forceinline__ void wave_argmax_sum(double &best, int &bi, double &sum) {
+  argmax_sum_step<DPP_XOR1>(best, bi, sum);
+  argmax_sum_step<DPP_XOR2>(best, bi, sum);
+  argmax_sum_step<DPP_HALF_MIRROR>(best, bi, sum);
+  argmax_sum_step<DPP_MIRROR>(best, bi, sum);
+  for (int o = 16; o <= 32; o <<= 1) {
+    const double ob = __shfl_xor(best, o, 64);
+    const int oi = __shfl_xor(bi, o, 64);
+    sum += __shfl_xor(sum, o, 64);
+    if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+  }
 }
 
 // Block-wide sum; `red` = LDS scratch of at least CM_WG/64 + 1 doubles. Includes syncs.
@@ -169,8 +224,7 @@ __device__ __forceinline__ void jacobi_onesided(double2 *S, double2 *J, int m, i
   }
   __syncthreads();
   {
-    double v = amax_part;
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    const double v = wave_max(amax_part);
     if ((tid & 63) == 0) sh.red[tid >> 6] = v;
   }
   __syncthreads();
@@ -343,12 +397,7 @@ __device__ __forceinline__ int cpqr_trunc(double2 *T, int m, int p, double delta
         sum += v;
         if (v > best) { best = v; bi = c; }
       }
-      for (int o = 32; o > 0; o >>= 1) {
-        const double ob = __shfl_xor(best, o, 64);
-        const int oi = __shfl_xor(bi, o, 64);
-        sum += __shfl_xor(sum, o, 64);
-        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-      }
+      wave_argmax_sum(best, bi, sum);
       if (tid == 0) { piv_sh = bi; tail_sh = sum; }
     }
     __syncthreads();

@@ -11,6 +11,8 @@
 // The price is
 //   C(k_u) = Re[ exp(-alpha k_u)/(s pi) * exp(-i v0 k_u) * sqrt(M) * y_u ],
 // with exp(-i v0 k_u) = exp(-i v0 k0) (-1)^u for the symmetric rule and 1 for Simpson.
+#include <climits>
+
 #include "cm_cf.h"
 #include "cm_tt.h"
 
@@ -69,6 +71,12 @@ __device__ __forceinline__ double read_price(const ReadConst &c, int64_t u, doub
 constexpr int RD_WG = 256;
 constexpr int RD_SPT = 4;                 // strikes per lane
 constexpr int RD_LDS = 48 * 1024;         // core staging arena (three workgroups per CU)
+// Prefix tree for strikes that share their high bits (a contiguous block of a workgroup's
+// 1024 strikes spans at most two values of u >> 10): y_u = Lo[u mod 32] . MR[u >> 10][(u >> 5)
+// mod 32], where Lo holds the 32 row vectors of cores 0..4, R[h] the right vectors of cores
+// 10..n-1 for high part h, and MR[h][m] = cores 5..9 at bits m applied to R[h]. Each strike
+// then costs r_5 multiply-adds instead of a contraction through all n cores.
+constexpr int TB_LO = 5, TB_H = 10, TB_K = 2;
 
 // Contracts one strike: v <- Y_l[:, bit_l, :] v from l = n-1 down to 0; returns y_u.
 // Core l starts at base + off(l) and holds [rk[l]][2][rk[l+1]] values.
@@ -96,6 +104,55 @@ __device__ __forceinline__ T contract_strike(const T *base, const Off &off, cons
     for (int a = 0; a < RM; ++a) v[a] = w[a];
   }
   return v[0];
+}
+
+// v <- Y_l[:, bit_l(u), :] v for l = l_hi down to l_lo; v is indexed by bond l_hi + 1 on
+// entry and by bond l_lo on exit (entries past the bond dimension are left undefined).
+template <typename T, int RM, class Off>
+__device__ __forceinline__ void contract_right(const T *base, const Off &off, const int32_t *rk, int l_hi, int l_lo,
+                                               int64_t u, T *v) {
+  T w[RM];
+  for (int l = l_hi; l >= l_lo; --l) {
+    const int ra = rk[l], rb = rk[l + 1];
+    const T *C = base + off(l) + (int)((u >> l) & 1) * rb;
+#pragma unroll
+    for (int a = 0; a < RM; ++a) {
+      if (a < ra) {
+        typename rd<T>::V acc = rd<T>::zero();
+        const T *row = C + a * 2 * rb;
+#pragma unroll
+        for (int q = 0; q < RM; ++q)
+          if (q < rb) rd<T>::fma_(acc, row[q], v[q]);
+        w[a] = acc;
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < RM; ++a) v[a] = w[a];
+  }
+}
+
+// Row vector v <- v Y_l[:, bit_l(u), :] for l = l_lo up to l_hi; v is indexed by bond l_lo on
+// entry and by bond l_hi + 1 on exit.
+template <typename T, int RM, class Off>
+__device__ __forceinline__ void contract_left(const T *base, const Off &off, const int32_t *rk, int l_lo, int l_hi,
+                                              int64_t u, T *v) {
+  T w[RM];
+  for (int l = l_lo; l <= l_hi; ++l) {
+    const int ra = rk[l], rb = rk[l + 1];
+    const T *C = base + off(l) + (int)((u >> l) & 1) * rb;
+#pragma unroll
+    for (int c = 0; c < RM; ++c) {
+      if (c < rb) {
+        typename rd<T>::V acc = rd<T>::zero();
+#pragma unroll
+        for (int a = 0; a < RM; ++a)
+          if (a < ra) rd<T>::fma_(acc, C[a * 2 * rb + c], v[a]);
+        w[c] = acc;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < RM; ++c) v[c] = w[c];
+  }
 }
 
 struct LdsOff {
@@ -155,10 +212,85 @@ __global__ __launch_bounds__(RD_WG) void k_readout(TTView y, const cm_problem *_
   const ReadConst rc = read_const(pr, n);
   const int64_t M = (int64_t)1 << n;
   const int s0 = blockIdx.x * RD_WG * RD_SPT;
+  // this workgroup's strikes; the range of their high parts decides the prefix tree
+  __shared__ long long s_hmin, s_hmax;
+  __shared__ int s_bad;
+  if (threadIdx.x == 0) { s_hmin = LLONG_MAX; s_hmax = -1; s_bad = 0; }
+  __syncthreads();
+  int64_t uu[RD_SPT];
+#pragma unroll
+  for (int t = 0; t < RD_SPT; ++t) {
+    const int s = s0 + t * RD_WG + (int)threadIdx.x;
+    uu[t] = -1;
+    if (s < nk) {
+      const int64_t u = strike_idx[(int64_t)b * nk + s];
+      uu[t] = u;
+      if (u < 0 || u >= M) atomicOr(&s_bad, 1);
+      else { atomicMin(&s_hmin, (long long)(u >> TB_H)); atomicMax(&s_hmax, (long long)(u >> TB_H)); }
+    }
+  }
+  __syncthreads();
+  const int r5 = (n > TB_H) ? s_rk[TB_LO] : 0, r10 = (n > TB_H) ? s_rk[TB_H] : 0;
+  const int tree_elems = TB_K * r10 + (32 + TB_K * 32) * r5;
+  const bool tree = in_lds && n > TB_H && pr.n == n && s_bad == 0 && s_hmax >= s_hmin &&
+                    s_hmax - s_hmin < TB_K && (size_t)(s_off[n] + tree_elems) * sizeof(T) <= (size_t)RD_LDS;
+  if (tree) {
+    const int64_t hmin = s_hmin;
+    const int nh = (int)(s_hmax - s_hmin) + 1;
+    T *R = arena + s_off[n];          // [TB_K][r10]
+    T *Lo = R + TB_K * r10;           // [32][r5]
+    T *MR = Lo + 32 * r5;             // [TB_K][32][r5]
+    const int tid = threadIdx.x;
+    if (tid < nh) {
+      T v[RM];
+#pragma unroll
+      for (int a = 0; a < RM; ++a) v[a] = T{0, 0};
+      v[0] = T{1, 0};
+      contract_right<T, RM>(arena, LdsOff{s_off}, s_rk, n - 1, TB_H, (hmin + tid) << TB_H, v);
+#pragma unroll
+      for (int a = 0; a < RM; ++a)
+        if (a < r10) R[tid * r10 + a] = v[a];
+    } else if (tid >= 64 && tid < 96) {
+      T v[RM];
+#pragma unroll
+      for (int a = 0; a < RM; ++a) v[a] = T{0, 0};
+      v[0] = T{1, 0};
+      contract_left<T, RM>(arena, LdsOff{s_off}, s_rk, 0, TB_LO - 1, tid - 64, v);
+#pragma unroll
+      for (int c = 0; c < RM; ++c)
+        if (c < r5) Lo[(tid - 64) * r5 + c] = v[c];
+    }
+    __syncthreads();
+    if (tid < 32 * nh) {
+      const int q = tid >> 5, m5 = tid & 31;
+      T v[RM];
+#pragma unroll
+      for (int a = 0; a < RM; ++a) v[a] = (a < r10) ? R[q * r10 + a] : T{0, 0};
+      contract_right<T, RM>(arena, LdsOff{s_off}, s_rk, TB_H - 1, TB_LO, ((hmin + q) << TB_H) | ((int64_t)m5 << TB_LO),
+                            v);
+#pragma unroll
+      for (int a = 0; a < RM; ++a)
+        if (a < r5) MR[(q * 32 + m5) * r5 + a] = v[a];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < RD_SPT; ++t) {
+      const int s = s0 + t * RD_WG + tid;
+      const int64_t u = uu[t];
+      if (s >= nk) break;
+      const T *lo = Lo + (int)(u & 31) * r5;
+      const T *mr = MR + (((int)((u >> TB_H) - hmin) * 32) + (int)((u >> TB_LO) & 31)) * r5;
+      typename rd<T>::V acc = rd<T>::zero();
+      for (int a = 0; a < r5; ++a) rd<T>::fma_(acc, lo[a], mr[a]);
+      prices[(int64_t)b * nk + s] = read_price(rc, u, rd<T>::to(acc));
+    }
+    return;
+  }
+#pragma unroll
   for (int t = 0; t < RD_SPT; ++t) {
     const int s = s0 + t * RD_WG + (int)threadIdx.x;
     if (s >= nk) break;
-    const int64_t u = strike_idx[(int64_t)b * nk + s];
+    const int64_t u = uu[t];
     double price;
     if (u < 0 || u >= M || pr.n != n) {
       price = NAN;
