@@ -69,14 +69,15 @@ __device__ __forceinline__ double read_price(const ReadConst &c, int64_t u, doub
 }
 
 constexpr int RD_WG = 256;
-constexpr int RD_SPT = 4;                 // strikes per lane
-constexpr int RD_LDS = 48 * 1024;         // core staging arena (three workgroups per CU)
+constexpr int RD_SPT = 16;                // strikes per lane
+constexpr int RD_LDS = 64 * 1024;         // core staging arena and prefix tree (two workgroups per CU)
 // Prefix tree for strikes that share their high bits (a contiguous block of a workgroup's
-// 1024 strikes spans at most two values of u >> 10): y_u = Lo[u mod 32] . MR[u >> 10][(u >> 5)
-// mod 32], where Lo holds the 32 row vectors of cores 0..4, R[h] the right vectors of cores
-// 10..n-1 for high part h, and MR[h][m] = cores 5..9 at bits m applied to R[h]. Each strike
+// 4096 strikes spans at most two values of u >> 12): y_u = Lo[u mod 32] . MR[u >> 12][(u >> 5)
+// mod 128], where Lo holds the 32 row vectors of cores 0..4, R[h] the right vectors of cores
+// 12..n-1 for high part h, and MR[h][m] = cores 5..11 at bits m applied to R[h]. Each strike
 // then costs r_5 multiply-adds instead of a contraction through all n cores.
-constexpr int TB_LO = 5, TB_H = 10, TB_K = 2;
+constexpr int TB_LO = 5, TB_H = 12, TB_K = 2;
+constexpr int TB_MID = 1 << (TB_H - TB_LO);
 
 // Contracts one strike: v <- Y_l[:, bit_l, :] v from l = n-1 down to 0; returns y_u.
 // Core l starts at base + off(l) and holds [rk[l]][2][rk[l+1]] values.
@@ -201,10 +202,26 @@ __global__ __launch_bounds__(RD_WG) void k_readout(TTView y, const cm_problem *_
   __syncthreads();
   const bool in_lds = s_ok != 0;
   if (in_lds) {
-    for (int l = 0; l < n; ++l) {
-      const T *src = gcores + y.coff(b, l);
-      const int cnt = s_rk[l] * 2 * s_rk[l + 1];
-      for (int e = threadIdx.x; e < cnt; e += RD_WG) arena[s_off[l] + e] = src[e];
+    // all cores as one flat range, four loads in flight per thread
+    constexpr int U = 4;
+    const int total = s_off[n];
+    int l = 0;
+    for (int e0 = threadIdx.x; e0 < total; e0 += RD_WG * U) {
+      T v[U];
+      int dst[U];
+#pragma unroll
+      for (int k = 0; k < U; ++k) {
+        const int e = e0 + k * RD_WG;
+        dst[k] = -1;
+        if (e < total) {
+          while (s_off[l + 1] <= e) ++l;
+          v[k] = gcores[y.coff(b, l) + (e - s_off[l])];
+          dst[k] = e;
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < U; ++k)
+        if (dst[k] >= 0) arena[dst[k]] = v[k];
     }
   }
   __syncthreads();
@@ -231,7 +248,7 @@ __global__ __launch_bounds__(RD_WG) void k_readout(TTView y, const cm_problem *_
   }
   __syncthreads();
   const int r5 = (n > TB_H) ? s_rk[TB_LO] : 0, r10 = (n > TB_H) ? s_rk[TB_H] : 0;
-  const int tree_elems = TB_K * r10 + (32 + TB_K * 32) * r5;
+  const int tree_elems = TB_K * r10 + (32 + TB_K * TB_MID) * r5;
   const bool tree = in_lds && n > TB_H && pr.n == n && s_bad == 0 && s_hmax >= s_hmin &&
                     s_hmax - s_hmin < TB_K && (size_t)(s_off[n] + tree_elems) * sizeof(T) <= (size_t)RD_LDS;
   if (tree) {
@@ -239,7 +256,7 @@ __global__ __launch_bounds__(RD_WG) void k_readout(TTView y, const cm_problem *_
     const int nh = (int)(s_hmax - s_hmin) + 1;
     T *R = arena + s_off[n];          // [TB_K][r10]
     T *Lo = R + TB_K * r10;           // [32][r5]
-    T *MR = Lo + 32 * r5;             // [TB_K][32][r5]
+    T *MR = Lo + 32 * r5;             // [TB_K][TB_MID][r5]
     const int tid = threadIdx.x;
     if (tid < nh) {
       T v[RM];
@@ -261,8 +278,8 @@ __global__ __launch_bounds__(RD_WG) void k_readout(TTView y, const cm_problem *_
         if (c < r5) Lo[(tid - 64) * r5 + c] = v[c];
     }
     __syncthreads();
-    if (tid < 32 * nh) {
-      const int q = tid >> 5, m5 = tid & 31;
+    for (int e = tid; e < TB_MID * nh; e += RD_WG) {
+      const int q = e / TB_MID, m5 = e % TB_MID;
       T v[RM];
 #pragma unroll
       for (int a = 0; a < RM; ++a) v[a] = (a < r10) ? R[q * r10 + a] : T{0, 0};
@@ -270,7 +287,7 @@ __global__ __launch_bounds__(RD_WG) void k_readout(TTView y, const cm_problem *_
                             v);
 #pragma unroll
       for (int a = 0; a < RM; ++a)
-        if (a < r5) MR[(q * 32 + m5) * r5 + a] = v[a];
+        if (a < r5) MR[(q * TB_MID + m5) * r5 + a] = v[a];
     }
     __syncthreads();
 #pragma unroll
@@ -279,7 +296,7 @@ __global__ __launch_bounds__(RD_WG) void k_readout(TTView y, const cm_problem *_
       const int64_t u = uu[t];
       if (s >= nk) break;
       const T *lo = Lo + (int)(u & 31) * r5;
-      const T *mr = MR + (((int)((u >> TB_H) - hmin) * 32) + (int)((u >> TB_LO) & 31)) * r5;
+      const T *mr = MR + (((int)((u >> TB_H) - hmin) * TB_MID) + (int)((u >> TB_LO) & (TB_MID - 1))) * r5;
       typename rd<T>::V acc = rd<T>::zero();
       for (int a = 0; a < r5; ++a) rd<T>::fma_(acc, lo[a], mr[a]);
       prices[(int64_t)b * nk + s] = read_price(rc, u, rd<T>::to(acc));

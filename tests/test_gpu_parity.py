@@ -111,6 +111,25 @@ def test_sfft_bs_n12_simpson_fp64():
     assert np.all(np.abs(got - ref)[big] <= 1e-6 * np.abs(ref)[big])
 
 
+def test_readout_tree_and_per_strike_paths_fp64():
+    """Readout of one FP64 SFFT train (BS rectangle rule, n = 16, tol 1e-10) through both
+    readout paths: a contiguous near-money block (prefix tree: the block spans at most two
+    values of u >> 12), the same block shuffled (still the tree), and a strided window (the
+    per-strike contraction). All against the oracle's direct DFT."""
+    p = W.bs_rect_n12().replace(n=16, eta=40.0 / 2 ** 8)
+    strided = W.window_strided(p, 4096)
+    near = W.near_money(p, len(strided))
+    shuffled = np.random.default_rng(1).permutation(near)
+    pr = cm.SfftPricer([p] * 3, cm.CM_C128, tol=1e-10, cap=32)
+    got = pr.run(_strikes_dev([near, shuffled, strided])).cpu().numpy()
+    st = pr.statuses()
+    assert all(np.all(v == cm.CM_OK) for v in st.values()), st
+    for row, u in zip(got, (near, shuffled, strided)):
+        ref = O.prices_direct(p, u)
+        assert np.abs(row - ref).max() / p.S0 < FP64_TOL
+    assert np.allclose(got[1][np.argsort(shuffled)], got[0], rtol=0, atol=1e-12 * p.S0)
+
+
 @pytest.mark.parametrize("quad", ["rect2", "simpson1"])
 def test_dense_fft_fp64_n12_all_strikes(quad):
     say("dense fp64", quad)
