@@ -11,17 +11,24 @@
 // right-canonical form the right environment is close to orthonormal, so this per-step
 // truncation is accurate; the following cm_tt_round makes the ranks optimal with SVDs.
 // The contraction runs in the storage precision (FP32 complex for CM_C64); the pivoted QR
-// runs in FP64. Per-site matrices live in LDS when they fit (the common case), otherwise in
-// the workgroup's global slab.
+// runs in FP64. Sites with 2 chi <= 48 and w' r' <= 128 (the bulk of a pricing chain) keep
+// T in registers for the whole factorisation, each column on a pair of lanes
+// (zip_site_pair); other sites stage their matrices in LDS when they fit, otherwise in the
+// workgroup's global slab.
 #include "cm_tt.h"
 
 namespace {
 
 constexpr int ZCHI = 32;          // zip-up bond limit
 constexpr int ZW = 24;            // largest operator bond supported by the workspace layout
-// LDS arena per workgroup: sized so that four 256-thread workgroups share a CU (typical sites
-// fit; larger ones use the slab), which measured faster than two with a 72 KB arena.
-constexpr int ZLDS = 16 * 1024;
+// LDS arena per workgroup. The pair-resident path holds half a column of T (up to 24 rows)
+// in 96 VGPRs per lane; the kernel is bounded to 168 VGPRs (three waves per SIMD, which
+// measured faster than two without spills or four with spills in the pivot loop), and the
+// FP32 arena lets three 256-thread workgroups share a CU while holding the staged carry and
+// D chunks of the largest sites of a 2^24-point chain, or the reflectors.
+template <typename T> constexpr int zlds_bytes();
+template <> constexpr int zlds_bytes<float2>() { return 40 * 1024; }
+template <> constexpr int zlds_bytes<double2>() { return 64 * 1024; }
 
 __host__ __device__ inline size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -150,10 +157,385 @@ __device__ __forceinline__ int zip_site(char *arena, const SiteDims &sd, const T
   return k;
 }
 
+// ---- pair-resident site -----------------------------------------------------------------
+// T (m x p, FP64) is held in registers for the whole pivoted QR. Column c lives on the lane
+// pair 2c, 2c + 1; at step i (j = i / 2 pair shifts done) lane g of the pair holds row
+// 2 (s + j) + g in register slot s. Both lanes move their slots down by one after every odd
+// step, so row i always sits in slot 0 of lane i % 2 and every register index is static;
+// the row finished at the even step before is then in slot 0 of lane 0 and takes no part
+// (its reflector entries are zero). A dot product is lane-local plus one DPP exchange
+// within the pair. A pivot step needs one workgroup barrier, at which each wave publishes
+// its best candidate column (norm, index, the sum of its columns' norms, its entry alpha in
+// row i and its rows from i on, with the Householder data it would give) and all waves
+// then take the same global choice. Column
+// norms are recomputed exactly from the updated entries at every step. Rows of
+// B = R P^T are emitted as they are finished, straight into the carry buffer in the
+// [k][w'][r'] order the next site reads. Q = H_0 ... H_{k-1} [I_k; 0] is then accumulated
+// barrier-free with eight lanes per column, from the reflectors kept in LDS.
+constexpr int PW = CM_WG / 64;    // waves per workgroup
+constexpr int MR = 48;            // rows: m = 2 chi <= 48
+constexpr int SM = MR / 2;        // register slots per lane
+constexpr int CP = CM_WG / 2;     // columns: p <= 128
+struct CandInfo {
+  double best, sum;
+  int idx, pad0;
+  double pad1;
+};
+static_assert(sizeof(CandInfo) == 32, "CandInfo layout");
+// LDS layout (bytes): candidate columns [2][PW][MR] (two buffers, by step parity; entry
+// 2 s + g is row 2 (s + j) + g), their CandInfo and Householder data [2][PW], taus, then a
+// region holding the
+// carry, the operator core, the input core and chunks of D during the contraction and the
+// reflectors V [k][MR] during the factorisation.
+constexpr size_t PL_CAND = 0;
+constexpr size_t PL_INFO = PL_CAND + 16 * 2 * PW * MR;
+constexpr size_t PL_HOUSE = PL_INFO + 32 * 2 * PW;       // House [2][PW]
+constexpr size_t PL_TAU = PL_HOUSE + 64 * 2 * PW;
+constexpr size_t PL_REGION = (PL_TAU + 16 * ZCHI + 255) & ~(size_t)255;
+
+template <typename T>
+__device__ __forceinline__ bool pair_site_fits(const SiteDims &s, int kcap, size_t lds_bytes) {
+  const int m = 2 * s.chi, p = s.w1 * s.r1;
+  if (m > MR || p > CP) return false;
+  // carry, operator core, input core and two 4-row chunks of D (storage precision)
+  const size_t dwa = sizeof(T) * ((size_t)s.chi * s.w0 * s.r0 + (size_t)s.w0 * 4 * s.w1 + (size_t)s.r0 * 2 * s.r1 +
+                                  (size_t)2 * 4 * s.w0 * 2 * s.r1);
+  int kmax = m < p ? m : p;
+  if (kcap < kmax) kmax = kcap;
+  const size_t v = (size_t)16 * MR * kmax;
+  return PL_REGION + (dwa > v ? dwa : v) <= lds_bytes;
+}
+
+// wave-uniform copies of values every lane already holds, and reads of one lane's value
+__device__ __forceinline__ int uni_i(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ double lane_d(double x, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), l),
+                          __builtin_amdgcn_readlane(__double2loint(x), l));
+}
+// sum over the lane pair (l, l ^ 1)
+__device__ __forceinline__ double pair_sum(double v) { return v + la::dpp_d<la::DPP_XOR1>(v); }
+
+// Over the 64 lanes of a wave: the largest `best` (ties to the smaller index) and the sum
+// of `sum`, returned wave-uniform. DPP inside rows of 16 lanes, then the four row results
+// combined in a fixed order.
+__device__ __forceinline__ void wave_argmax_sum_uni(double &best, int &bi, double &sum) {
+  la::argmax_sum_step<la::DPP_XOR1>(best, bi, sum);
+  la::argmax_sum_step<la::DPP_XOR2>(best, bi, sum);
+  la::argmax_sum_step<la::DPP_HALF_MIRROR>(best, bi, sum);
+  la::argmax_sum_step<la::DPP_MIRROR>(best, bi, sum);
+  double b = lane_d(best, 0), s = lane_d(sum, 0);
+  int ix = __builtin_amdgcn_readlane(bi, 0);
+#pragma unroll
+  for (int r = 1; r < 4; ++r) {
+    const double ob = lane_d(best, 16 * r);
+    const int oi = __builtin_amdgcn_readlane(bi, 16 * r);
+    s += lane_d(sum, 16 * r);
+    if (ob > b || (ob == b && oi < ix)) { b = ob; ix = oi; }
+  }
+  best = b; bi = ix; sum = s;
+}
+
+// Householder data of a pivot column with squared norm n2 (rows >= i) and entry alpha in row
+// i: beta = -sign(Re alpha) sqrt(n2), x_i = alpha - beta (so that v = x scal has v_i = 1),
+// tau = (beta - alpha) / beta and scal = 1 / (alpha - beta). The reciprocal square root and
+// the reciprocal come from the hardware approximations refined by two Newton steps each
+// (relative error a few ulp), which keeps the chain short.
+struct House {
+  double2 am, tau, scal;
+  double beta, pad;
+};
+static_assert(sizeof(House) == 64, "House layout");
+__device__ __forceinline__ double rcp_nr(double a) {
+  double y = __builtin_amdgcn_rcp(a);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) y = fma(y, fma(-a, y, 1.0), y);
+  return y;
+}
+__device__ __forceinline__ double rsq_nr(double a) {
+  double y = __builtin_amdgcn_rsq(a);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) y = fma(y, fma(-0.5 * a * y, y, 0.5), y);   // y (3 - a y^2) / 2
+  return y;
+}
+__device__ __forceinline__ House householder(double n2, double2 alpha) {
+  House H;
+  H.beta = 0.0;
+  H.pad = 0.0;
+  H.am = alpha;
+  H.tau = cmk(0.0, 0.0);
+  H.scal = cmk(0.0, 0.0);
+  if (n2 > 0.0) {
+    const double rs = rsq_nr(n2);
+    const double sg = alpha.x >= 0.0 ? 1.0 : -1.0;
+    H.beta = -sg * (n2 * rs);
+    const double ib = -sg * rs;   // 1 / beta
+    H.am.x = alpha.x - H.beta;
+    const double id = rcp_nr(cabs2(H.am));
+    H.tau = cmk(1.0 - alpha.x * ib, -alpha.y * ib);
+    H.scal = cmk(H.am.x * id, -H.am.y * id);
+  }
+  return H;
+}
+
+template <typename T>
+__device__ __forceinline__ int zip_site_pair(char *arena, const SiteDims &sd, const T *__restrict__ Wl,
+                                             const T *__restrict__ Al, double2 *C, T *Yout, double delta2,
+                                             int kcap, int *code) {
+  using A = acc_t<T>;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = uni_i(tid >> 6);   // wave index, known to the compiler as wave-uniform
+  const int chi = sd.chi, w0 = sd.w0, w1 = sd.w1, r0 = sd.r0, r1 = sd.r1;
+  const int m = 2 * chi, p = w1 * r1;
+  const int c = tid >> 1, g = tid & 1;   // this lane's column and its half of the rows
+  double2 *cand = (double2 *)(arena + PL_CAND);
+  CandInfo *info = (CandInfo *)(arena + PL_INFO);
+  House *hinf = (House *)(arena + PL_HOUSE);
+  double2 *taus = (double2 *)(arena + PL_TAU);
+  T *Cl = (T *)(arena + PL_REGION);
+  T *Wc = Cl + chi * w0 * r0;
+  T *Ac = Wc + w0 * 4 * w1;
+  T *Dch = Ac + r0 * 2 * r1;                       // two chunks of D[4][w0][2][r1]
+  double2 *V = (double2 *)(arena + PL_REGION);   // reuses the region once T is in registers
+  const int dchunk = 4 * w0 * 2 * r1;
+  // stage the carry (in the storage precision, which the contraction uses) and the cores;
+  // loads are issued in batches so that their latencies overlap
+  {
+    const int nc = chi * w0 * r0;
+    for (int e0 = tid; e0 < nc; e0 += 4 * CM_WG) {
+      double2 v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = e0 + u * CM_WG;
+        v[u] = e < nc ? C[e] : cmk(0.0, 0.0);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = e0 + u * CM_WG;
+        if (e < nc) Cl[e] = A::from(v[u]);
+      }
+    }
+  }
+  for (int e = tid; e < w0 * 4 * w1; e += CM_WG) Wc[e] = Wl[e];
+  for (int e = tid; e < r0 * 2 * r1; e += CM_WG) Ac[e] = Al[e];
+  // T[(ch, g)][(wp, rp)] = sum_{w0, j} D[ch][w0][j][rp] W[w0][g][j][wp] (row 2 ch + g, slot ch)
+  // with D[ch][w0][j][r1] = sum_r C[ch][w0][r] A[r][j][r1], both in the storage precision,
+  // four ch at a time; D chunks alternate between two buffers, one barrier per chunk
+  const bool cok = c < p;
+  double2 t[SM];
+#pragma unroll
+  for (int sl = 0; sl < SM; ++sl) t[sl] = cmk(0.0, 0.0);
+  {
+    const int wp = cok ? c / r1 : 0, rp = cok ? c - (c / r1) * r1 : 0;
+#pragma unroll
+    for (int ch0 = 0; ch0 < SM; ch0 += 4) {
+      if (ch0 < chi) {
+        T *Db = Dch + ((ch0 / 4) & 1) * dchunk;
+        __syncthreads();   // staging done (first chunk) / this buffer's previous readers done
+        for (int e = tid; e < dchunk; e += CM_WG) {
+          const int rpp = e % r1, j = (e / r1) & 1, ww = (e / (2 * r1)) % w0, cc = e / (2 * r1 * w0);
+          typename A::type acc = A::zero();
+          if (ch0 + cc < chi) {
+            const T *crow = Cl + ((ch0 + cc) * w0 + ww) * r0;
+            for (int r = 0; r < r0; ++r) A::fma_(acc, crow[r], Ac[(r * 2 + j) * r1 + rpp]);
+          }
+          Db[e] = acc;
+        }
+        __syncthreads();
+        typename A::type acc[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[e] = A::zero();
+        for (int ww = 0; ww < w0; ++ww)
+          for (int j = 0; j < 2; ++j) {
+            const T wvv = Wc[(ww * 4 + 2 * g + j) * w1 + wp];
+            const T *dd = Db + (ww * 2 + j) * r1 + rp;
+#pragma unroll
+            for (int cc = 0; cc < 4; ++cc) A::fma_(acc[cc], dd[cc * w0 * 2 * r1], wvv);
+          }
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (cok && ch0 + e < chi) t[ch0 + e] = A::to(acc[e]);
+      }
+    }
+  }
+  __syncthreads();   // the region now holds V
+  bool act = cok;    // still a candidate pivot column
+  double nrm;
+  {
+    double nz[2] = {0.0, 0.0};
+#pragma unroll
+    for (int sl = 0; sl < SM; ++sl) nz[sl & 1] += cabs2(t[sl]);
+    nrm = pair_sum(nz[0] + nz[1]);
+  }
+  const int kmax = m < p ? m : p;
+  const int hrows = (m + 1) >> 1;   // slots in use before any shift
+
+  // Pivot choice for step i: publishes this wave's candidate, waits for the other waves',
+  // and returns true when the factorisation stops at rank i (the same decision in every
+  // wave). The loop below exits only at its end, which keeps T in registers.
+  int pc = 0;
+  double beta = 0.0;
+  double2 am = cmk(0.0, 0.0), scal = cmk(0.0, 0.0), ctau = cmk(0.0, 0.0);
+  const double2 *X = cand;
+  auto select = [&](int i) -> bool {
+    const int b = i & 1, j = i >> 1;
+    double best = act ? nrm : -1.0, sum = (act && g == 0) ? nrm : 0.0;
+    int bi = act ? c : 0x7fffffff;
+    wave_argmax_sum_uni(best, bi, sum);
+    double2 *mine = cand + (b * PW + wv) * MR;
+    CandInfo *inf = info + b * PW + wv;
+    if (c == bi) {
+      // slot 0 is row 2 j + g: finished (zero), row i (x_i = alpha - beta) or the next row
+      const int r0w = 2 * j + g;
+      double2 v0 = t[0];
+      if (r0w < i) v0 = cmk(0.0, 0.0);
+      if (r0w == i) {
+        const House H = householder(best, t[0]);
+        v0 = H.am;
+        hinf[b * PW + wv] = H;
+        CandInfo ci;
+        ci.best = best; ci.sum = sum; ci.idx = bi; ci.pad0 = 0; ci.pad1 = 0.0;
+        *inf = ci;
+      }
+      mine[g] = v0;
+#pragma unroll
+      for (int sl = 1; sl < SM; ++sl) mine[2 * sl + g] = t[sl];
+    }
+    if (bi == 0x7fffffff && lane == 0) {   // no candidate left in this wave
+      CandInfo ci;
+      ci.best = -1.0; ci.sum = sum; ci.idx = bi; ci.pad0 = 0; ci.pad1 = 0.0;
+      *inf = ci;
+    }
+    __syncthreads();
+    double gbest = -1.0, tail = 0.0;
+    int gidx = 0x7fffffff, gw = 0;
+#pragma unroll
+    for (int q = 0; q < PW; ++q) {
+      const CandInfo ci = info[b * PW + q];
+      tail += ci.sum;
+      if (ci.best > gbest || (ci.best == gbest && ci.idx < gidx)) { gbest = ci.best; gidx = ci.idx; gw = q; }
+    }
+    if (!(tail == tail) || isinf(tail)) {
+      if (tid == 0 && *code == CM_OK) *code = CM_E_NONFINITE;
+      return true;
+    }
+    if (i >= kmax || (i >= 1 && tail <= delta2)) return true;
+    if (i == kcap) {
+      if (tid == 0 && *code == CM_OK) *code = CM_E_RANKCAP;
+      return true;
+    }
+    pc = gidx;
+    X = cand + (b * PW + gw) * MR;
+    const House H = hinf[b * PW + gw];
+    beta = H.beta;
+    am = H.am;
+    scal = H.scal;
+    ctau = cconj(H.tau);
+    if (tid == 0) taus[i] = H.tau;
+    return false;
+  };
+
+  int i = 0;
+  bool stop = select(0);
+  while (!stop) {
+    const int j = i >> 1;
+    const int live = hrows - j;   // slots holding rows >= i (and possibly one finished row)
+    const double2 *Xg = X + g;
+    // w_c = conj(tau) sum_r conj(v_r) T[r, c] with v = x scal, summed over the pair
+    double2 pz[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) pz[e] = cmk(0.0, 0.0);
+#pragma unroll
+    for (int q4 = 0; q4 < SM / 4; ++q4)
+      if (4 * q4 < live) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) ccfma(pz[e], Xg[2 * (4 * q4 + e)], t[4 * q4 + e]);
+      }
+    double2 pw = cadd(cadd(pz[0], pz[1]), cadd(pz[2], pz[3]));
+    pw.x = pair_sum(pw.x);
+    pw.y = pair_sum(pw.y);
+    const double2 ws = cmul(cscale(ctau, cabs2(scal)), pw);   // scal w_c
+    // row i of R, from slot 0 of lane i % 2
+    {
+      const double2 x0 = Xg[0];
+      double2 r0v = t[0];
+      r0v.x -= x0.x * ws.x - x0.y * ws.y;
+      r0v.y -= x0.x * ws.y + x0.y * ws.x;
+      if (cok && g == (i & 1)) C[(int64_t)i * p + c] = (c == pc) ? cmk(beta, 0.0) : (act ? r0v : cmk(0.0, 0.0));
+    }
+    // T <- H^H T; slot 0 holds row i (lane i % 2) or, after an even step, the row finished
+    // then (lane 0), neither of which counts towards the remaining norms
+    double nz[2] = {0.0, 0.0};
+    const bool skip0 = (i & 1) || g == 0;
+#pragma unroll
+    for (int q4 = 0; q4 < SM / 4; ++q4)
+      if (4 * q4 < live) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int sl = 4 * q4 + e;
+          const double2 x = Xg[2 * sl];
+          double2 y = t[sl];
+          y.x -= x.x * ws.x - x.y * ws.y;
+          y.y -= x.x * ws.y + x.y * ws.x;
+          t[sl] = y;
+          if (sl > 0 || !skip0) nz[e & 1] += cabs2(y);
+        }
+      }
+    // after an odd step both lanes move their slots down by one (every slot moves: a copy
+    // bounded by the live count would become a memmove that keeps T out of registers)
+    if (i & 1) {
+#pragma unroll
+      for (int sl = 0; sl + 1 < SM; ++sl) t[sl] = t[sl + 1];
+      t[SM - 1] = cmk(0.0, 0.0);
+    }
+    nrm = pair_sum(nz[0] + nz[1]);
+    if (c == pc) act = false;
+    // reflector i for the Q accumulation: V[i][r] = v_r (zero above row i and below row m)
+    if (tid < MR) {
+      double2 v = cmk(0.0, 0.0);
+      if (tid == i) v = cmk(1.0, 0.0);
+      else if (tid > i) v = cmul(X[tid - 2 * j], scal);
+      V[i * MR + tid] = v;
+    }
+    ++i;
+    stop = select(i);
+  }
+  const int k = i;
+  // Q = H_0 ... H_{k-1} [I_k; 0], barrier-free: column cq of Q on lanes 8 cq .. 8 cq + 7,
+  // lane h of the eight holding rows 8 s + h; the dot products are summed with DPP
+  {
+    const int cq = tid >> 3, h = tid & 7;
+    if (cq < k) {   // uniform over each group of eight lanes
+      double2 qv[MR / 8];
+#pragma unroll
+      for (int sl = 0; sl < MR / 8; ++sl) qv[sl] = cmk(8 * sl + h == cq ? 1.0 : 0.0, 0.0);
+      for (int jj = k - 1; jj >= 0; --jj) {
+        const double2 tj = taus[jj];
+        if (tj.x == 0.0 && tj.y == 0.0) continue;
+        const double2 *Vj = V + jj * MR + h;
+        double2 d = cmk(0.0, 0.0);
+#pragma unroll
+        for (int sl = 0; sl < MR / 8; ++sl)
+          if (8 * sl + 7 >= jj && 8 * sl < m) ccfma(d, Vj[8 * sl], qv[sl]);   // V[jj][r] = 0 for r < jj, r >= m
+        d.x = la::grp_sum(d.x, 8);
+        d.y = la::grp_sum(d.y, 8);
+        const double2 wq = cmul(tj, d);
+#pragma unroll
+        for (int sl = 0; sl < MR / 8; ++sl)
+          if (8 * sl + 7 >= jj && 8 * sl < m) qv[sl] = csub(qv[sl], cmul(Vj[8 * sl], wq));
+      }
+#pragma unroll
+      for (int sl = 0; sl < MR / 8; ++sl)
+        if (8 * sl + h < m) cstore<T>::st(Yout, (int64_t)(8 * sl + h) * k + cq, qv[sl]);
+    }
+  }
+  __syncthreads();   // the arena and the carry are reused by the next site
+  return k;
+}
+
 }  // namespace
 
 template <typename T>
-__global__ __launch_bounds__(CM_WG) void k_zipup(TTView w, TTView x, TTView y, double tol, int cap,
+__global__ __launch_bounds__(CM_WG, 3) void k_zipup(TTView w, TTView x, TTView y, double tol, int cap,
                                                  int batch, int32_t *__restrict__ status,
                                                  char *__restrict__ ws, size_t slab_bytes, int64_t mat_cap) {
   extern __shared__ __align__(16) char lds_arena[];
@@ -216,7 +598,9 @@ __global__ __launch_bounds__(CM_WG) void k_zipup(TTView w, TTView x, TTView y, d
       const T *Al = Xc + x.coff(b, l);
       T *Yout = Yc + y.coff(b, l);
       int k;
-      if (need <= (size_t)ZLDS)
+      if (!last && pair_site_fits<T>(sd, chicap, zlds_bytes<T>()))
+        k = zip_site_pair<T>(lds_arena, sd, Wl, Al, C, Yout, delta2, chicap, &code_sh);
+      else if (need <= (size_t)zlds_bytes<T>())
         k = zip_site<T>(lds_arena, sd, Wl, Al, C, D, Yout, last, delta2, chicap, sh, &code_sh);
       else
         k = zip_site<T>(garena, sd, Wl, Al, C, D, Yout, last, delta2, chicap, sh, &code_sh);
@@ -257,17 +641,16 @@ extern "C" cm_status cm_sfft_apply(const cm_tt_batch *w_by_n, const cm_tt_batch 
   if (slots < 1) return CM_E_INVALID;
   const size_t slab = cm_zip_slab_bytes(cap_rank);
   const int64_t mc = (int64_t)zip_mat_cap(cap_rank);
-  const size_t lds = ZLDS;
   hipStream_t s = (hipStream_t)stream;
   TTView vw = tt_view(w_by_n), vx = tt_view(x), vy = tt_view(y);
-  CM_HIP_CHECK(cm_allow_lds(k_zipup<float2>, lds));
-  CM_HIP_CHECK(cm_allow_lds(k_zipup<double2>, lds));
+  CM_HIP_CHECK(cm_allow_lds(k_zipup<float2>, zlds_bytes<float2>()));
+  CM_HIP_CHECK(cm_allow_lds(k_zipup<double2>, zlds_bytes<double2>()));
   if (x->dtype == CM_C64)
-    hipLaunchKernelGGL(k_zipup<float2>, dim3(slots), dim3(CM_WG), lds, s, vw, vx, vy, tol, cap_rank, batch, status,
-                       (char *)ws, slab, mc);
+    hipLaunchKernelGGL(k_zipup<float2>, dim3(slots), dim3(CM_WG), zlds_bytes<float2>(), s, vw, vx, vy, tol, cap_rank,
+                       batch, status, (char *)ws, slab, mc);
   else
-    hipLaunchKernelGGL(k_zipup<double2>, dim3(slots), dim3(CM_WG), lds, s, vw, vx, vy, tol, cap_rank, batch, status,
-                       (char *)ws, slab, mc);
+    hipLaunchKernelGGL(k_zipup<double2>, dim3(slots), dim3(CM_WG), zlds_bytes<double2>(), s, vw, vx, vy, tol,
+                       cap_rank, batch, status, (char *)ws, slab, mc);
   CM_LAUNCH_CHECK();
   y->flags = CM_TT_LEFT_ORTHO;
   return CM_OK;
