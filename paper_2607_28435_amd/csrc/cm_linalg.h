@@ -13,6 +13,21 @@
 
 namespace la {
 
+// 1/a and 1/sqrt(a) from the hardware approximations refined by two Newton steps each
+// (relative error a few ulp; a > 0 finite).
+__device__ __forceinline__ double rcp_nr(double a) {
+  double y = __builtin_amdgcn_rcp(a);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) y = fma(y, fma(-a, y, 1.0), y);
+  return y;
+}
+__device__ __forceinline__ double rsq_nr(double a) {
+  double y = __builtin_amdgcn_rsq(a);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) y = fma(y, fma(-0.5 * a * y, y, 0.5), y);   // y (3 - a y^2) / 2
+  return y;
+}
+
 __device__ __forceinline__ int pow2floor(int x) {
   int p = 1;
   while (p * 2 <= x) p *= 2;
@@ -260,13 +275,18 @@ __device__ __forceinline__ void jacobi_onesided(double2 *S, double2 *J, int m, i
         if (!(a == a) || !(b == b)) {
           if (lane == 0) sh.nonfinite = 1;
         } else if (a > null2 && b > null2) {
-          const double ag = sqrt(gr * gr + gi * gi);
-          if (ag > tol * sqrt(a) * sqrt(b)) {
-            const double zeta = (b - a) / (2.0 * ag);
-            const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-            const double c = 1.0 / sqrt(1.0 + t * t);
+          const double ag2 = gr * gr + gi * gi;
+          if (ag2 > (tol * tol) * a * b) {
+            // reciprocal square roots and reciprocals refined by Newton steps keep the
+            // dependent chain short (relative errors of a few ulp)
+            const double rag = rsq_nr(ag2);   // 1 / |g|
+            const double zeta = 0.5 * (b - a) * rag;
+            const double z2 = 1.0 + zeta * zeta;
+            const double sq = z2 * rsq_nr(z2);
+            const double t = (zeta >= 0.0 ? 1.0 : -1.0) * rcp_nr(fabs(zeta) + sq);
+            const double c = rsq_nr(1.0 + t * t);
             const double sn = c * t;
-            const double2 e = cmk(gr / ag, gi / ag);
+            const double2 e = cmk(gr * rag, gi * rag);
             const double2 se = cscale(e, sn);          // s e
             const double2 sce = cscale(cconj(e), sn);  // s conj(e)
             for (int i = lane; i < m; i += G) {
@@ -506,40 +526,51 @@ __device__ __forceinline__ int cpqr_trunc(double2 *T, int m, int p, double delta
 // SVD, truncated with the rest of the budget. The kept rank k is the smallest whose total
 // dropped squared norm is <= delta2, clipped to cap (sh.rankcap is set if that loses more).
 //   X : scratch of at least a*b complex;  Z : scratch of at least a*b complex
-//   S, J : LDS, at least a*min(a,b) and min(a,b)^2 complex
+//   S, J : at least a*min(a,b) and min(a,b)^2 complex
 //   L (ld a) and R (ld k) : outputs.
+//   lds, lds_elems : optional LDS scratch; X, and then the Jacobi pair, move there for this
+//   call when they fit (the factorisations are latency-bound chains of small steps).
 // Returns k (uniform); sh.err2 holds the dropped squared norm.
 __device__ __forceinline__ int svd_trunc_rows(double2 *Y, int a, int b, double delta2, int cap,
                                               double2 *X, double2 *Z, double2 *S, double2 *J,
-                                              double2 *L, double2 *R, Sh &sh) {
+                                              double2 *L, double2 *R, Sh &sh, double2 *lds = nullptr,
+                                              int lds_elems = 0) {
   const int tid = threadIdx.x;
+  const bool x_lds = lds != nullptr && a * b <= lds_elems;
+  double2 *Xw = x_lds ? lds : X;
   for (int e = tid; e < a * b; e += CM_WG) {
     const int i = e % b, j = e / b;   // X[i, j] = conj(Y[j, i])
-    X[e] = cconj(Y[j + (int64_t)a * i]);
+    Xw[e] = cconj(Y[j + (int64_t)a * i]);
   }
   __syncthreads();
   // X P = Q R, truncated: Q -> Z (b x kc), B = R[:kc] P^T -> Y (kc x a, ld kc)
-  const int kc = cpqr_trunc(X, b, a, 0.5 * delta2, 64, Z, Y, sh.sig2, sh.perm, sh);
+  int kc;
+  if (x_lds) kc = cpqr_trunc(lds, b, a, 0.5 * delta2, 64, Z, Y, sh.sig2, sh.perm, sh);
+  else kc = cpqr_trunc(X, b, a, 0.5 * delta2, 64, Z, Y, sh.sig2, sh.perm, sh);
   __syncthreads();
   const double err_c = sh.err2;
+  const bool sj_lds = lds != nullptr && a * kc + kc * kc <= lds_elems;
+  double2 *Sw = sj_lds ? lds : S;
+  double2 *Jw = sj_lds ? lds + a * kc : J;
   // S = B^H (a x kc, ld a)
   for (int e = tid; e < a * kc; e += CM_WG) {
     const int i = e % a, j = e / a;
-    S[e] = cconj(Y[j + (int64_t)kc * i]);
+    Sw[e] = cconj(Y[j + (int64_t)kc * i]);
   }
   __syncthreads();
-  jacobi_onesided(S, J, a, kc, sh);
+  if (sj_lds) jacobi_onesided(lds, lds + a * kc, a, kc, sh);
+  else jacobi_onesided(S, J, a, kc, sh);
   const double rest = delta2 - err_c;
   choose_rank_t0(sh, kc, rest > 0.0 ? rest : 0.0, cap);
   const int k = sh.k;
   // L = (B^H J)[:, perm[:k]];  Rk^H = Q J[:, perm[:k]]
   for (int e = tid; e < a * k; e += CM_WG) {
     const int i = e % a, j = e / a;
-    L[e] = S[i + (int64_t)a * sh.perm[j]];
+    L[e] = Sw[i + (int64_t)a * sh.perm[j]];
   }
   for (int e = tid; e < k * b; e += CM_WG) {
     const int i = e % k, c = e / k;
-    const double2 *jc = J + (int64_t)kc * sh.perm[i];
+    const double2 *jc = Jw + (int64_t)kc * sh.perm[i];
     double2 acc = cmk(0.0, 0.0);
     for (int t = 0; t < kc; ++t) cfma(acc, Z[c + (int64_t)b * t], jc[t]);
     R[i + (int64_t)k * c] = cconj(acc);

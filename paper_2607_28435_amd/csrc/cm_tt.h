@@ -82,7 +82,7 @@ template <typename OutT>
 __device__ __forceinline__ double round_train(int n, int d, const CoreSrc &src, double tol, int cap,
                               OutT *dst_cores, const int64_t *dst_off, int32_t *dst_ranks,
                               const RoundScratch &w, double2 *S, double2 *J, la::Sh &sh,
-                              int *code, bool skip_a = false) {
+                              int *code, bool skip_a = false, double2 *lds = nullptr, int lds_elems = 0) {
   const int tid = threadIdx.x;
   __shared__ int rk[CM_MAX_N + 1];
   __shared__ double norm2_sh;
@@ -163,7 +163,7 @@ __device__ __forceinline__ double round_train(int n, int d, const CoreSrc &src, 
       __syncthreads();
       break;
     }
-    const int k = la::svd_trunc_rows(w.Y, kl, b, delta2, cap, w.X, w.Z, S, J, w.L, w.R, sh);
+    const int k = la::svd_trunc_rows(w.Y, kl, b, delta2, cap, w.X, w.Z, S, J, w.L, w.R, sh, lds, lds_elems);
     merge_flags(sh, code);
     err2 += sh.err2;
     // core l = Rk (k x b, ld k) as [k][d][rpp]
@@ -184,7 +184,8 @@ __device__ __forceinline__ double round_train(int n, int d, const CoreSrc &src, 
 }
 
 // round_train with the hot matrices (Y, X, Z and the Jacobi pair) in the LDS arena when the
-// train's largest bond allows it, and in the global scratch otherwise.
+// train's largest bond allows it, and in the global scratch otherwise (then the pivoted QR
+// input and the Jacobi pair of each bond still move to the arena when they fit).
 template <typename OutT>
 __device__ __forceinline__ double round_train_auto(int n, int d, const CoreSrc &src, double tol, int cap,
                                                    OutT *dst_cores, const int64_t *dst_off, int32_t *dst_ranks,
@@ -210,5 +211,7 @@ __device__ __forceinline__ double round_train_auto(int n, int d, const CoreSrc &
     w.C = J + rmax * rmax;
     return round_train<OutT>(n, d, src, tol, cap, dst_cores, dst_off, dst_ranks, w, S, J, sh, code, skip_a);
   }
-  return round_train<OutT>(n, d, src, tol, cap, dst_cores, dst_off, dst_ranks, wg, wg.S, wg.J, sh, code, skip_a);
+  // matrices in global scratch; the SVD steps still use the arena for whatever fits per bond
+  return round_train<OutT>(n, d, src, tol, cap, dst_cores, dst_off, dst_ranks, wg, wg.S, wg.J, sh, code, skip_a,
+                           (double2 *)arena, (int)(arena_bytes / sizeof(double2)));
 }
