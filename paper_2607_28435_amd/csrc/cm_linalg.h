@@ -384,8 +384,9 @@ __device__ __forceinline__ int qr_thin(double2 *Y, int m, int p, double2 *Qout, 
 // holds the dropped squared norm. p <= 1024.
 // The remaining column norms nrm[c] (rows >= i at step i) are recomputed exactly from the
 // updated entries after every reflection, so the pivot column's norm gives the reflector's
-// beta without another reduction, and wave 0 forms the tail sum together with the pivot
-// search: five barriers per step.
+// beta without another reduction, wave 0 forms the tail sum together with the pivot search,
+// and every thread forms the reflector itself: three barriers per step (four when columns
+// are swapped).
 __device__ __forceinline__ int cpqr_trunc(double2 *T, int m, int p, double delta2, int cap, double2 *Qk,
                                           double2 *B, double *nrm, int *perm, Sh &sh) {
   const int tid = threadIdx.x;
@@ -444,29 +445,30 @@ __device__ __forceinline__ int cpqr_trunc(double2 *T, int m, int p, double delta
       }
       __syncthreads();
     }
-    // Householder reflector for T[i:m, i]; ||T[i:m, i]||^2 = nrm[i]
-    if (tid == 0) {
+    // Householder reflector for T[i:m, i]; ||T[i:m, i]||^2 = nrm[i]. Every thread forms it
+    // from the same inputs (reciprocal square root and reciprocal refined by Newton steps)
+    // and scales its share of the column; beta replaces T[i, i] after the barrier.
+    double2 tc = cmk(0.0, 0.0);
+    double beta = 0.0;
+    {
       const double2 a = T[i + (int64_t)m * i];
       const double norm2 = nrm[i];
-      if (!(norm2 > 0.0)) {
-        sh.tau[i] = cmk(0.0, 0.0);
-        sh.scal = cmk(0.0, 0.0);
-      } else {
-        const double beta = -copysign(sqrt(norm2), a.x);
-        sh.tau[i] = cmk((beta - a.x) / beta, -a.y / beta);
-        sh.scal = cdiv(cmk(1.0, 0.0), csub(a, cmk(beta, 0.0)));
-        T[i + (int64_t)m * i] = cmk(beta, 0.0);
+      if (norm2 > 0.0) {
+        const double rs = rsq_nr(norm2);
+        const double sg = a.x >= 0.0 ? 1.0 : -1.0;
+        beta = -sg * (norm2 * rs);
+        const double ib = -sg * rs;   // 1 / beta
+        const double2 am = cmk(a.x - beta, a.y);
+        const double id = rcp_nr(cabs2(am));
+        tc = cmk(1.0 - a.x * ib, -a.y * ib);
+        const double2 sc = cmk(am.x * id, -am.y * id);
+        for (int r = i + 1 + tid; r < m; r += CM_WG) T[r + (int64_t)m * i] = cmul(T[r + (int64_t)m * i], sc);
       }
-      k_sh = i + 1;
     }
+    if (tid == 0) { sh.tau[i] = tc; k_sh = i + 1; }
     __syncthreads();
-    const double2 tc = sh.tau[i];
     const bool refl = !(tc.x == 0.0 && tc.y == 0.0);
-    if (refl) {
-      const double2 sc = sh.scal;
-      for (int r = i + 1 + tid; r < m; r += CM_WG) T[r + (int64_t)m * i] = cmul(T[r + (int64_t)m * i], sc);
-      __syncthreads();
-    }
+    if (refl && tid == 0) T[i + (int64_t)m * i] = cmk(beta, 0.0);
     // apply H^H to trailing columns; refresh their norms below row i
     const int ncols = p - i - 1;
     if (ncols > 0) {
