@@ -130,9 +130,9 @@ FFT_SOURCES = ["paper_2607_28435_amd/csrc/cm_fft.hip", "paper_2607_28435_amd/csr
                "paper_2607_28435_amd/csrc/cm_tt.h", "paper_2607_28435_amd/csrc/cm_linalg.h",
                "paper_2607_28435_amd/csrc/cm_internal.h", "include/cm.h"]
 PROFILED_TRAFFIC = {
-    "k_zipup": {"sha": "a710431600e496cf", "bytes": (523237.2 * 2.0 + 3206053.0) * 1024,
+    "k_zipup": {"sha": "8884ced817093bd5", "bytes": (902532.0 * 2.0 + 1010375.9) * 1024,
                 "per": "launch (4096 instances, n=24)"},
-    "dense": {"sha": "832b27751174ac25", "bytes": ((142.2 + 65640.8) * 2.0 + 131072.0 + 65536.0) * 1024,
+    "dense": {"sha": "595b5903c5538b60", "bytes": ((142.3 + 65640.8) * 2.0 + 131072.0 + 65536.0) * 1024,
               "per": "grid (k_fft_first + k_fft_next, n=24)"},
 }
 
