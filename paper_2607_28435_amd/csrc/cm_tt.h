@@ -103,13 +103,18 @@ __device__ __forceinline__ double round_train(int n, int d, const CoreSrc &src, 
   for (int l = 0; l < n && !skip_a; ++l) {
     const int rl = src.ranks[l], rr = src.ranks[l + 1];
     const int rows = kprev * d;
+    const int kq = rows < rr ? rows : rr;
+    // the product and its Q factor go to the LDS scratch when both fit (the QR is a chain of
+    // small dependent steps)
+    const bool in_lds = lds != nullptr && l < n - 1 && rows * rr + rows * kq <= lds_elems;
+    double2 *Yw = in_lds ? lds : w.Y;
     for (int e = tid; e < rows * rr; e += CM_WG) {
       const int i = e % rows, j = e / rows;
       const int a = i / d, ph = i % d;
       double2 acc = cmk(0.0, 0.0);
       for (int t = 0; t < rl; ++t)
         cfma(acc, w.C[a + kprev * t], src.get(l, ((int64_t)t * d + ph) * rr + j));
-      w.Y[e] = acc;
+      Yw[e] = acc;
     }
     __syncthreads();
     double2 *core = w.tt + (int64_t)l * w.core_cap;
@@ -124,8 +129,13 @@ __device__ __forceinline__ double round_train(int n, int d, const CoreSrc &src, 
       __syncthreads();
       break;
     }
-    const int kq = la::qr_thin(w.Y, rows, rr, w.Z, w.L, sh);
-    for (int e = tid; e < rows * kq; e += CM_WG) core[e] = w.Z[e];
+    if (in_lds) {
+      la::qr_thin(lds, rows, rr, lds + rows * rr, w.L, sh);
+      for (int e = tid; e < rows * kq; e += CM_WG) core[e] = lds[rows * rr + e];
+    } else {
+      la::qr_thin(w.Y, rows, rr, w.Z, w.L, sh);
+      for (int e = tid; e < rows * kq; e += CM_WG) core[e] = w.Z[e];
+    }
     for (int e = tid; e < kq * rr; e += CM_WG) w.C[e] = w.L[e];
     if (tid == 0) rk[l + 1] = kq;
     __syncthreads();
