@@ -17,7 +17,7 @@ from typing import List, Optional, Sequence, Tuple
 
 import numpy as np
 
-MODELS = ("bs", "merton", "heston")
+MODELS = ("bs", "merton", "heston", "vg")
 QUADS = ("rect2", "simpson1")
 
 
@@ -26,7 +26,9 @@ class Problem:
     """One European-call pricing instance on a Carr–Madan log-strike grid.
 
     model   : "bs" (params = (sigma,)), "merton" (sigma, lam_J, mu_J, delta_J),
-              "heston" (kappa, theta, sigma_v, rho, v0)
+              "heston" (kappa, theta, sigma_v, rho, v0), "vg" (sigma, nu, theta): Variance
+              Gamma, a Brownian motion with drift theta and volatility sigma run on a gamma
+              clock of unit mean rate and variance rate nu
     quad    : "rect2"  - two-sided rectangle rule on v in [-M eta/2, M eta/2)
                          (the paper's symmetric truncation, Section 2.1)
               "simpson1" - one-sided Simpson rule on v in [0, M eta) (Carr & Madan 1999)
@@ -85,6 +87,36 @@ def merton_big(n: int) -> Problem:
     r=0.02, T=1; alpha=1.5, eta=40/2^(n/2); n = 30 or 40."""
     return Problem("merton", "simpson1", n, 100.0, 0.02, 0.0, 1.0, 1.5, eta_rule(n),
                    (0.15, 0.5, -0.1, 0.2))
+
+
+def vg_n20() -> Problem:
+    """Variance Gamma sigma=0.12, nu=0.17, theta=-0.14 (a typical equity-index fit),
+    S0=100, r=0.05, q=0.01, T=0.5; alpha=1.5, eta=40/2^(n/2), n=20, Simpson."""
+    return Problem("vg", "simpson1", 20, 100.0, 0.05, 0.01, 0.5, 1.5, eta_rule(20), (0.12, 0.17, -0.14))
+
+
+def vg_batch(count: int, seed: int = 31, n: int = 20) -> List[Problem]:
+    """Seeded Variance Gamma draws: sigma ~ U(0.08, 0.3), nu ~ U(0.05, 0.5),
+    theta ~ U(-0.3, 0.05), T ~ U(0.1, 1.5), kept when the damping moment condition holds
+    for alpha = 1.5 with margin and T >= nu (the characteristic function then decays at
+    least like |v|^-2; shorter gamma clocks decay more slowly than the QTT build's partition
+    supports, which it reports as CM_E_NOCONV)."""
+    g = _rng(seed)
+    out = []
+    while len(out) < count:
+        sig, nu, th, T = g.uniform(0.08, 0.3), g.uniform(0.05, 0.5), g.uniform(-0.3, 0.05), g.uniform(0.1, 1.5)
+        b = 2.5   # alpha + 1
+        if 1.0 - b * th * nu - 0.5 * sig * sig * nu * b * b <= 0.05 or T < nu:
+            continue
+        out.append(Problem("vg", "simpson1", n, 100.0, 0.03, 0.0, float(T), 1.5, eta_rule(n),
+                           (float(sig), float(nu), float(th))))
+    return out
+
+
+def vg_slow_decay() -> Problem:
+    """A Variance Gamma instance with a short gamma clock (T/nu = 0.38): its characteristic
+    function decays like |v|^-0.76."""
+    return Problem("vg", "simpson1", 24, 100.0, 0.03, 0.0, 0.105, 1.5, eta_rule(24), (0.1854, 0.276, -0.1228))
 
 
 def paper_bs_grid(n: int) -> Problem:

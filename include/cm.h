@@ -48,7 +48,10 @@ typedef enum {
   CM_E_UNSUPPORTED = 7,  /* valid request outside what this build supports (e.g. n too large for a path) */
 } cm_status;
 
-enum { CM_BS = 0, CM_MERTON = 1, CM_HESTON = 2 };
+/* CM_VG: Variance Gamma, the log-price a Brownian motion with drift run on an independent
+ *        gamma clock (Section 2); cf (1 - i u theta nu + sigma^2 nu u^2/2)^(-T/nu) times the
+ *        martingale drift. */
+enum { CM_BS = 0, CM_MERTON = 1, CM_HESTON = 2, CM_VG = 3 };
 /* CM_QUAD_RECT2: the paper's symmetric rectangle rule (Eq. Ck_from_psi), v0 = -M eta/2,
  *                w_j = eta, price factor 1/(2 pi).
  * CM_QUAD_SIMPSON1: one-sided Simpson rule folded into x (the higher-order option noted at
@@ -59,7 +62,9 @@ enum { CM_C64 = 0, CM_C128 = 1 };
 
 /* One pricing instance (128 bytes, plain data; arrays of it live in device memory).
  *   p[] : BS {sigma}; Merton {sigma, lambda_J, mu_J, delta_J}; Heston {kappa, theta,
- *         sigma_v, rho, v0}.
+ *         sigma_v, rho, v0}; Variance Gamma {sigma, nu, theta} (nu the variance rate of the
+ *         gamma clock; invalid unless 1 - theta nu - sigma^2 nu/2 > 0, which the martingale
+ *         drift needs).
  *   k0  : lowest log-strike; NaN selects ln(S0) - pi/eta (at-the-money at u = M/2). */
 typedef struct {
   int32_t model, quad, n, flags;

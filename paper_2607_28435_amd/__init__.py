@@ -25,13 +25,13 @@ LIB_PATH = os.path.join(_HERE, "libcm.so")
 CM_MAX_N = 48
 CM_RANKS_STRIDE = 49
 CM_OK, CM_E_INVALID, CM_E_MOMENT, CM_E_RANKCAP, CM_E_NOCONV, CM_E_NONFINITE, CM_E_HIP, CM_E_UNSUPPORTED = range(8)
-CM_BS, CM_MERTON, CM_HESTON = range(3)
+CM_BS, CM_MERTON, CM_HESTON, CM_VG = range(4)
 CM_QUAD_RECT2, CM_QUAD_SIMPSON1 = range(2)
 CM_C64, CM_C128 = range(2)
 CM_OP_QFT_MPO, CM_OP_BUILD_QTT, CM_OP_SFFT_APPLY, CM_OP_TT_ROUND, CM_OP_FFT_PRICE = range(5)
 CM_TT_LEFT_ORTHO, CM_TT_RIGHT_ORTHO = 1, 2
 
-_MODEL = {"bs": CM_BS, "merton": CM_MERTON, "heston": CM_HESTON}
+_MODEL = {"bs": CM_BS, "merton": CM_MERTON, "heston": CM_HESTON, "vg": CM_VG}
 _QUAD = {"rect2": CM_QUAD_RECT2, "simpson1": CM_QUAD_SIMPSON1}
 
 PROBLEM_DTYPE = np.dtype([

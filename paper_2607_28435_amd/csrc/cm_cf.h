@@ -73,6 +73,7 @@ template <typename R> struct CfModel {
   R pref;        // -r T + (alpha + 1) m_f  (log prefactor of h)
   R a0, a1, a2, a3, a4;  // model parameters (see cm_problem.p)
   R kJ;          // Merton: E[e^J] - 1
+  R omT;         // Variance Gamma: omega T, omega = ln(1 - theta nu - sigma^2 nu / 2) / nu
 };
 
 template <typename R>
@@ -85,6 +86,9 @@ __device__ __forceinline__ CfModel<R> make_model(const cm_problem &pr) {
   m.pref = (R)(-pr.r * pr.T + (pr.alpha + 1.0) * mf);
   m.a0 = (R)pr.p[0]; m.a1 = (R)pr.p[1]; m.a2 = (R)pr.p[2]; m.a3 = (R)pr.p[3]; m.a4 = (R)pr.p[4];
   m.kJ = (R)(pr.model == CM_MERTON ? exp(pr.p[2] + 0.5 * pr.p[3] * pr.p[3]) - 1.0 : 0.0);
+  m.omT = (R)(pr.model == CM_VG
+                  ? log(1.0 - pr.p[2] * pr.p[1] - 0.5 * pr.p[0] * pr.p[0] * pr.p[1]) / pr.p[1] * pr.T
+                  : 0.0);
   return m;
 }
 
@@ -102,6 +106,14 @@ __device__ __forceinline__ cx<R> logcf_centered(const CfModel<R> &m, cx<R> u) {
     const R lam = m.a1, muJ = m.a2, dJ = m.a3;
     cx<R> jump = cexp(mk(-u.y * muJ, u.x * muJ) - (R(0.5) * dJ * dJ) * u2) - mk(R(1), R(0));
     return (R(-0.5) * s2T) * (u2 + iu) - (lam * m.kJ * m.T) * iu + (lam * m.T) * jump;
+  }
+  if (m.model == CM_VG) {
+    // gamma time change: E[e^{G (i u theta - sigma^2 u^2 / 2)}] with G of mean T and
+    // variance nu T; the base has a positive real part wherever the damping moment exists,
+    // so the principal logarithm is continuous along the integration line
+    const R sig = m.a0, nu = m.a1, th = m.a2;
+    const cx<R> base = mk(R(1), R(0)) - (th * nu) * iu + (R(0.5) * sig * sig * nu) * u2;
+    return m.omT * iu - (m.T / nu) * clog(base);
   }
   // Heston, Albrecher et al. (2007) form
   const R kappa = m.a0, theta = m.a1, sv = m.a2, rho = m.a3, v0 = m.a4;
@@ -145,7 +157,7 @@ __host__ __device__ inline double heston_explosion_time(double kappa, double sv,
 // Per-instance validation shared by every entry point. Returns a cm_status.
 __host__ __device__ inline int check_problem(const cm_problem &pr) {
   if (pr.n < 1 || pr.n > CM_MAX_N) return CM_E_INVALID;
-  if (pr.model < CM_BS || pr.model > CM_HESTON) return CM_E_INVALID;
+  if (pr.model < CM_BS || pr.model > CM_VG) return CM_E_INVALID;
   if (pr.quad != CM_QUAD_RECT2 && pr.quad != CM_QUAD_SIMPSON1) return CM_E_INVALID;
   if (!(pr.S0 > 0.0) || !(pr.T > 0.0) || !(pr.eta > 0.0)) return CM_E_INVALID;
   if (!(pr.alpha == pr.alpha) || pr.alpha == 0.0 || pr.alpha == -1.0) return CM_E_INVALID;
@@ -156,6 +168,14 @@ __host__ __device__ inline int check_problem(const cm_problem &pr) {
         !(pr.p[4] >= 0.0))
       return CM_E_INVALID;
     if (pr.T >= heston_explosion_time(pr.p[0], pr.p[2], pr.p[3], pr.alpha + 1.0)) return CM_E_MOMENT;
+  }
+  if (pr.model == CM_VG) {
+    const double sig = pr.p[0], nu = pr.p[1], th = pr.p[2];
+    if (!(sig > 0.0) || !(nu > 0.0) || !(th == th) || !(1.0 - th * nu - 0.5 * sig * sig * nu > 0.0))
+      return CM_E_INVALID;
+    // E[S_T^w] is finite iff the gamma moment generating function exists at the exponent
+    const double w = pr.alpha + 1.0;
+    if (!(1.0 - w * th * nu - 0.5 * sig * sig * nu * w * w > 0.0)) return CM_E_MOMENT;
   }
   return CM_OK;
 }

@@ -62,13 +62,14 @@ def test_qft_mpo_rank_is_small():
 
 # ------------------------------------------------------------------ QTT of the integrand
 
-@pytest.mark.parametrize("name", ["bs_rect", "bs_simpson", "heston16", "merton16", "heston_rect14"])
+@pytest.mark.parametrize("name", ["bs_rect", "bs_simpson", "heston16", "merton16", "heston_rect14", "vg16"])
 def test_build_qtt_matches_integrand(name):
     say("qtt", name)
     p = {"bs_rect": W.bs_rect_n12(), "bs_simpson": W.bs_simpson_n12(),
          "heston16": W.heston_n24().replace(n=16),
          "merton16": W.merton_big(30).replace(n=16, eta=W.eta_rule(16)),
-         "heston_rect14": W.heston_n24().replace(n=14, quad="rect2", eta=0.1)}[name]
+         "heston_rect14": W.heston_n24().replace(n=14, quad="rect2", eta=0.1),
+         "vg16": W.vg_n20().replace(n=16, eta=W.eta_rule(16))}[name]
     pr = cm.SfftPricer([p], cm.CM_C128, tol=1e-10, cap=32)
     pr.build()
     torch.cuda.synchronize()
@@ -269,6 +270,81 @@ def test_merton_large_grid_vs_series(n):
     assert all(v[0] == cm.CM_OK for v in st.values()), st
     ref = O.merton_call(p, O.strike_of(p, u))
     assert np.abs(got - ref).max() / p.S0 < C64_TOL
+
+
+def test_vg_fp64_sfft_and_dense_window():
+    """Variance Gamma (the model the paper names for its time-changed Brownian motion),
+    n = 16, FP64 SFFT at tol 1e-10 and the FP64 dense FFT against the oracle's dense
+    Carr–Madan prices on 4096 strikes strided through 0.5 <= K/S0 <= 1.5 (far from the money
+    e^{-alpha k} magnifies any transform error by up to e^{23} on this grid, so every FP64
+    test past n = 12 compares on a strike window)."""
+    say("vg n16 fp64")
+    p = W.vg_n20().replace(n=16, eta=W.eta_rule(16))
+    u = W.window_strided(p, 4096)
+    ref = O.prices_dense(p)[u]
+    pr = cm.SfftPricer([p], cm.CM_C128, tol=1e-10, cap=32)
+    got = pr.run(_strikes_dev([u])).cpu().numpy()[0]
+    st = pr.statuses()
+    assert all(v[0] == cm.CM_OK for v in st.values()), st
+    dense, _ = cm.dense_prices([p], cm.CM_C128)
+    e_sfft = np.abs(got - ref).max() / p.S0
+    e_dense = np.abs(dense.cpu().numpy()[0][u] - ref).max() / p.S0
+    say("errors sfft", e_sfft, "dense", e_dense, "y ranks", pr.y.ranks[0, : p.n + 1].tolist())
+    assert e_sfft < FP64_TOL and e_dense < FP64_TOL
+
+
+def test_vg_batch_c64_n20_vs_oracle_and_gamma_mixture():
+    """Eight seeded Variance Gamma draws at n = 20 through the complex64 SFFT chain: 64
+    near-money strikes each within 1e-4 S0 of the oracle, and the first draw's prices
+    against the gamma mixture of Black–Scholes prices."""
+    say("vg batch c64")
+    probs = W.vg_batch(8, seed=31, n=20)
+    u = [W.near_money(p, 64) for p in probs]
+    pr = cm.SfftPricer(probs, cm.CM_C64, tol=1e-8, cap=32)
+    got = pr.run(_strikes_dev(u)).cpu().numpy()
+    st = pr.statuses()
+    for k, v in st.items():
+        assert np.all(v == cm.CM_OK), (k, v)
+    for b, p in enumerate(probs):
+        ref = O.prices_direct(p, u[b])
+        assert np.abs(got[b] - ref).max() / p.S0 < C64_TOL, (b, p)
+    sel = u[0][::16]
+    mix = O.vg_call_gamma_mixture(probs[0], O.strike_of(probs[0], sel))
+    assert np.abs(got[0][::16] - mix).max() / probs[0].S0 < C64_TOL
+
+
+def test_vg_status_codes():
+    """Variance Gamma validation: a non-positive variance rate is invalid, and a positive
+    drift that makes E[S_T^(alpha+1)] infinite reports the moment condition; the valid
+    instance in the same batch is priced."""
+    say("vg status")
+    good = W.vg_n20().replace(n=12, eta=0.25)
+    bad_nu = good.replace(params=(0.12, -0.1, -0.14))
+    moment = good.replace(params=(0.3, 0.9, 0.5))
+    pr = cm.SfftPricer([good, bad_nu, moment], cm.CM_C128, tol=1e-10, cap=32)
+    u = np.stack([W.near_money(good, 16)] * 3)
+    got = pr.run(torch.from_numpy(u).cuda()).cpu().numpy()
+    st = pr.statuses()
+    assert st["build"].tolist() == [cm.CM_OK, cm.CM_E_INVALID, cm.CM_E_MOMENT]
+    ref = O.prices_direct(good, u[0])
+    assert np.abs(got[0] - ref).max() / good.S0 < FP64_TOL
+    _, dst = cm.dense_prices([good, bad_nu, moment], cm.CM_C128)
+    assert dst.cpu().numpy().tolist() == [cm.CM_OK, cm.CM_E_INVALID, cm.CM_E_MOMENT]
+
+
+def test_vg_slow_decay_reports_noconv():
+    """A Variance Gamma draw whose characteristic function decays too slowly for the QTT
+    build's partition is reported per instance (CM_E_NOCONV; its train is left as the zero
+    train) without disturbing its neighbour in the batch."""
+    say("vg slow decay")
+    good = W.vg_n20().replace(n=24, eta=W.eta_rule(24))
+    slow = W.vg_slow_decay()
+    pr = cm.SfftPricer([good, slow], cm.CM_C64, tol=1e-8, cap=32)
+    u = np.stack([W.near_money(good, 64), W.near_money(slow, 64)])
+    got = pr.run(torch.from_numpy(u).cuda()).cpu().numpy()
+    st = pr.statuses()
+    assert st["build"].tolist() == [cm.CM_OK, cm.CM_E_NOCONV]
+    assert np.abs(got[0] - O.prices_direct(good, u[0])).max() / good.S0 < C64_TOL
 
 
 # ------------------------------------------------------------------ status codes and edges

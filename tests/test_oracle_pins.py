@@ -79,6 +79,7 @@ def _rand_problems(seed=3):
                              g.uniform(.2, 2), 1.5, .25,
                              (g.uniform(.1, .4), g.uniform(0, 1), g.uniform(-.2, .1), g.uniform(.05, .3))))
     out += W.heston_batch(4, seed=seed, n=12)
+    out += W.vg_batch(4, seed=seed, n=12)
     return out
 
 
@@ -227,10 +228,18 @@ def test_bs_simpson_alias_clean_strikes_vs_closed_form():
     assert np.abs(C - ref)[~clean].max() / 100 > 1.0     # the alias is real
 
 
-@pytest.mark.parametrize("model", ["bs", "heston"])
+def _model_grid(model):
+    if model == "bs":
+        return W.bs_simpson_n12().replace(n=14, eta=0.1)
+    if model == "vg":
+        return W.vg_n20().replace(n=16, eta=W.eta_rule(16))
+    return W.heston_n24().replace(n=16)
+
+
+@pytest.mark.parametrize("model", ["bs", "heston", "vg"])
 def test_alpha_invariance(model):
     """Every admissible alpha gives the same price (Section 2.1, after Eq. psi)."""
-    p = W.bs_simpson_n12().replace(n=14, eta=0.1) if model == "bs" else W.heston_n24().replace(n=16)
+    p = _model_grid(model)
     u = W.window_strided(p, 256)
     ref = O.prices_direct(p, u)
     for a in (1.0, 2.0, 3.0):
@@ -238,10 +247,10 @@ def test_alpha_invariance(model):
         assert np.abs(C - ref).max() / p.S0 < 1e-9, (a, np.abs(C - ref).max())
 
 
-@pytest.mark.parametrize("model", ["bs", "heston"])
+@pytest.mark.parametrize("model", ["bs", "heston", "vg"])
 def test_put_call_parity(model):
     """alpha = -2.5 transforms the damped put; C - P = S0 e^{-qT} - K e^{-rT}."""
-    p = W.bs_simpson_n12().replace(n=14, eta=0.1) if model == "bs" else W.heston_n24().replace(n=16)
+    p = _model_grid(model)
     u = W.window_strided(p, 256)
     K = O.strike_of(p, u)
     C = O.prices_direct(p, u)
@@ -264,6 +273,33 @@ def test_heston_gil_pelaez():
     C = O.prices_direct(p, u)
     ref = O.heston_call_gil_pelaez(p, O.strike_of(p, u))
     assert np.abs(C - ref).max() / p.S0 < 1e-10
+
+
+def test_vg_gamma_mixture():
+    """Variance Gamma: the Carr–Madan prices against the gamma mixture of Black–Scholes
+    prices (conditioning on the gamma clock), across the strike window."""
+    p = W.vg_n20()
+    u = W.window_strided(p, 9)
+    C = O.prices_direct(p, u)
+    ref = O.vg_call_gamma_mixture(p, O.strike_of(p, u))
+    assert np.abs(C - ref).max() / p.S0 < 1e-10
+
+
+def test_vg_small_nu_is_bs():
+    """With theta = 0 and a vanishing variance rate the gamma clock becomes deterministic and
+    Variance Gamma reduces to Black–Scholes with the same sigma."""
+    p = W.vg_n20().replace(n=12, eta=0.25, params=(0.2, 1e-7, 0.0))
+    q = W.Problem("bs", "simpson1", 12, p.S0, p.r, p.q, p.T, p.alpha, p.eta, (0.2,))
+    v = np.linspace(0, 40, 17)
+    assert np.abs(O.psi(p, v) - O.psi(q, v)).max() < 1e-6 * np.abs(O.psi(q, v)).max()
+
+
+def test_vg_moment_condition():
+    """E[S_T^(alpha+1)] exists for the fixture and fails once theta nu drives the gamma
+    moment generating function's argument past 1 (theta > 0 here)."""
+    p = W.vg_n20()
+    assert O.vg_moment_ok(p, p.alpha + 1.0)
+    assert not O.vg_moment_ok(p.replace(params=(0.3, 0.9, 0.5)), 2.5)
 
 
 def test_direct_truncated_dft_matches_full_fft():
