@@ -54,6 +54,10 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true", help="run one 1 GiB device copy first: the "
                     "reference a traffic counter is scaled by")
     ap.add_argument("--surrogate-steps", type=int, default=60000)
+    ap.add_argument("--curves", action="store_true", help="instead of the benchmark line, print one JSON "
+                    "line per n of the paper's memory / rank / time / NRMSE curves (Section 4)")
+    ap.add_argument("--curves-n", type=int, nargs=2, default=(3, 40))
+    ap.add_argument("--curves-dense-max", type=int, default=30)
     return ap.parse_args()
 
 
@@ -152,6 +156,75 @@ def vg_run(cm, torch, batch, nk, steps, n):
             "y_max_rank": int(pr.y.ranks[:, : n + 1].max().item())}
 
 
+def _bs_call(S0, K, r, q, T, sigma):
+    """Black–Scholes call (the reference the paper's NRMSE is measured against)."""
+    from scipy import special
+    sq = sigma * math.sqrt(T)
+    d1 = (np.log(S0 / K) + (r - q + 0.5 * sigma * sigma) * T) / sq
+    return S0 * math.exp(-q * T) * special.ndtr(d1) - K * math.exp(-r * T) * special.ndtr(d1 - sq)
+
+
+def paper_curves(cm, torch, n_lo, n_hi, dense_max, tol=1e-10, reps=3):
+    """Memory, maximal rank, run time and NRMSE against n on the paper's Black–Scholes grid
+    (Section 4: S0 = 100, r = 0.05, sigma = 0.3, T = 0.5, alpha = 2.5, N = 2^(n-1),
+    Delta_k = N^(-1/2)), FP64 throughout, one instance per run as in the paper:
+      - sfft: operator construction (Q_n), QTT construction (x), and the Core (zip-up,
+        rounding, read-out of the window strikes); memory = bytes of the final y train;
+      - fft: the dense FFT with read-out of the same strikes (n <= dense_max); memory = the
+        2^n complex array;
+      - nrmse: over the grid strikes with 0.5 <= K/S0 <= 1.5 (at most 2^16 of them, evenly
+        strided) against the Black–Scholes formula (Eq. error_measure)."""
+    rows = []
+    for n in range(n_lo, n_hi + 1):
+        p = W.paper_bs_grid(n)
+        M = 2 ** n
+        lam = 2.0 * math.pi / (M * p.eta)
+        u_lo = max(0, math.ceil((math.log(50.0) - p.k0) / lam))
+        u_hi = min(M - 1, math.floor((math.log(150.0) - p.k0) / lam))
+        u = np.arange(u_lo, u_hi + 1, dtype=np.int64)
+        if len(u) > 65536:
+            u = u[np.linspace(0, len(u) - 1, 65536).round().astype(np.int64)]
+        K = np.exp(p.k0 + lam * u.astype(np.float64))
+        ref = _bs_call(100.0, K, 0.05, 0.0, 0.5, 0.3)
+        sd = torch.from_numpy(u[None, :]).cuda()
+
+        def timed(fn):
+            best = float("inf")
+            for _ in range(reps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                fn()
+                torch.cuda.synchronize()
+                best = min(best, time.perf_counter() - t0)
+            return best
+
+        box = {}
+        t_op = timed(lambda: box.__setitem__("mpo", cm.MpoCache([n], tol / 10, 64, cm.CM_C128)))
+        pr = cm.SfftPricer([p], cm.CM_C128, tol=tol, cap=64, mpo=box["mpo"])
+        prices = torch.empty((1, len(u)), dtype=torch.float64, device="cuda")
+        t_x = timed(pr.build)
+        t_core = timed(lambda: (pr.apply(), pr.round(), pr.read(sd, prices)))
+        got = prices.cpu().numpy()[0]
+        st = pr.statuses()
+        yr = pr.y.ranks[0, : n + 1].cpu().numpy().astype(np.int64)
+        row = {"n": n, "strikes": int(len(u)),
+               "sfft": {"construct_operator_s": t_op, "construct_x_s": t_x, "core_s": t_core,
+                        "total_s": t_op + t_x + t_core,
+                        "memory_MB": float((yr[:-1] * 2 * yr[1:]).sum() * 16 / 1e6),
+                        "max_rank": int(yr.max()), "x_max_rank": int(pr.x.ranks[0, : n + 1].max().item()),
+                        "nrmse": float(np.sqrt(np.mean((got - ref) ** 2)) / 100.0),
+                        "status": {k: int(v[0]) for k, v in st.items()}}}
+        if n <= dense_max:
+            dbox = {}
+            t_fft = timed(lambda: dbox.__setitem__("r", cm.dense_prices([p], cm.CM_C128, strikes=sd)))
+            dgot = dbox["r"][0].cpu().numpy()[0]
+            row["fft"] = {"total_s": t_fft, "memory_MB": M * 16 / 1e6,
+                          "nrmse": float(np.sqrt(np.mean((dgot - ref) ** 2)) / 100.0)}
+        print(json.dumps(row), flush=True)
+        rows.append(row)
+    return rows
+
+
 BF16_DENSE_TFLOPS = 2500.0
 
 # HBM bytes per dispatch from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs recorded in
@@ -244,6 +317,9 @@ def main():
     import paper_2607_28435_amd as cm
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.curves:
+        paper_curves(cm, torch, args.curves_n[0], args.curves_n[1], args.curves_dense_max)
+        return
     dev = "cuda"
     if args.copy_calibration:
         a = torch.ones(2 ** 28, dtype=torch.float32, device=dev)

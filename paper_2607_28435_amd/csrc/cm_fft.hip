@@ -273,6 +273,7 @@ __device__ __forceinline__ void fft_block(T *a, int logc, int Lp, const Src &src
 // Per-problem constants of the integrand and readout.
 struct DenseConst {
   double eta, v0;
+  int64_t jmid;            // index of v = 0: 2^(n-1) for the symmetric rule, else 0
   double th_hi, th_lo;     // theta / (2 pi) as double-double, theta = eta (m_f - k0)
   double2 g0;              // exp(i v0 m_f)
   double z0, dz;           // log2 of the readout scale e^{-alpha k_u} / (s pi) is z0 + dz u
@@ -297,6 +298,7 @@ __device__ inline DenseConst dense_const(const cm_problem &pr) {
   c.eta = pr.eta;
   c.simpson = pr.quad == CM_QUAD_SIMPSON1;
   c.v0 = c.simpson ? 0.0 : -ldexp(pr.eta, n - 1);
+  c.jmid = c.simpson ? 0 : ((int64_t)1 << (n - 1));
   const double rq = (pr.r - pr.q) * pr.T;
   double p, e;
   if (k0_is_default(pr)) {
@@ -346,7 +348,9 @@ __device__ __forceinline__ T integrand_at(const DenseProb<T> &d, int64_t j) {
   using R = typename fr<T>::R;
   if (j < d.jlo || j >= d.jhi) return fr<T>::mk(0.0, 0.0);
   const DenseConst &c = d.c;
-  const double v = c.v0 + (double)j * c.eta;
+  // v_j = v0 + j eta formed from the exact offset j - jmid: adding v0 to j eta would cancel
+  // to an absolute error of |v0| ulp near v = 0 on large symmetric grids
+  const double v = (double)(j - c.jmid) * c.eta;
   const cx<R> h = h_centered<R>(d.m, (R)v);
   // exp(i j theta): fraction of j * (th_hi + th_lo)
   double p, e;

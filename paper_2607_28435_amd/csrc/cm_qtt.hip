@@ -212,7 +212,10 @@ __global__ __launch_bounds__(CM_WG, 2) void k_build_qtt(const cm_problem *__rest
         double pos;
         if (exact) pos = (double)q;
         else pos = (q < QP) ? node_pos(Lm1, cq[q]) : node_pos(Lm1, ck[q - QP]);
-        const double v = v0 + ((double)c + pos) * eta;
+        // v = v0 + (c + pos) eta from the exact offset c - jpeak (jpeak eta = -v0): the
+        // direct sum cancels to an absolute error of |v0| ulp near the peak on large
+        // symmetric grids, which breaks the leaf tests there
+        const double v = ((double)(c - jpeak) + pos) * eta;
         const cx<double> h = h_centered<double>(cm, v);
         vals[ci * QNPT + q] = cmk(h.x, h.y);
       }

@@ -19,7 +19,7 @@
 
 namespace {
 
-constexpr int ZCHI = 32;          // zip-up bond limit
+constexpr int ZCHI = 48;          // zip-up bond limit (sites above 24 take the generic path)
 constexpr int ZW = 24;            // largest operator bond supported by the workspace layout
 // LDS arena per workgroup. The pair-resident path holds half a column of T (up to 24 rows)
 // in 96 VGPRs per lane; the kernel is bounded to 168 VGPRs (three waves per SIMD, which

@@ -178,6 +178,28 @@ def test_paper_grid_statevector_pin_through_gpu():
     assert e < 1e-13
 
 
+@pytest.mark.parametrize("n", [24, 32])
+def test_paper_grid_large_n_sfft(n):
+    """The paper's two-sided grid (Section 4) at n = 24 and 32 through the FP64 SFFT chain:
+    the QTT build converges (its sample points are formed from exact index offsets, so the
+    symmetric grid's large v0 does not cancel into the leaf tests) and the prices match the
+    Black–Scholes formula over 0.5 <= K/S0 <= 1.5."""
+    say("paper grid sfft n", n)
+    p = W.paper_bs_grid(n)
+    lam = 2 * math.pi / (2 ** n * p.eta)
+    lo = math.ceil((math.log(50.0) - p.k0) / lam)
+    hi = math.floor((math.log(150.0) - p.k0) / lam)
+    u = np.linspace(lo, hi, 4096).round().astype(np.int64)
+    pr = cm.SfftPricer([p], cm.CM_C128, tol=1e-10, cap=64)
+    got = pr.run(_strikes_dev([u])).cpu().numpy()[0]
+    st = pr.statuses()
+    assert all(v[0] == cm.CM_OK for v in st.values()), st
+    ref = O.bs_call(100.0, O.strike_of(p, u), 0.05, 0.0, 0.5, 0.3)
+    e = O.nrmse(got, ref, 100.0)
+    say("  nrmse", e, "max", np.abs(got - ref).max() / 100)
+    assert e < 1e-9 and np.abs(got - ref).max() / 100 < FP64_TOL
+
+
 def test_dense_fft_fp64_batched_multi_instance_launch():
     """Four instances in one launch (n = 20, two passes): every instance against the oracle's
     direct DFT on strikes strided over 0.5 <= K/S0 <= 1.5."""
