@@ -40,7 +40,8 @@ from scipy import integrate, special
 __all__ = [
     "char_fn", "psi", "grid", "weights", "integrand", "dft_direct", "dft_fft",
     "prices_from_y", "prices_dense", "prices_direct", "bs_call", "merton_call",
-    "heston_call_gil_pelaez", "vg_call_gamma_mixture", "qft_observable_prices", "nrmse", "qn_matrix",
+    "heston_call_gil_pelaez", "vg_call_gamma_mixture", "qft_observable_prices", "qft_probabilities",
+    "sample_outcomes", "shot_prices", "prices_from_counts", "nrmse", "qn_matrix",
     "heston_explosion_time", "strike_of",
 ]
 
@@ -364,6 +365,51 @@ def qft_observable_prices(p, u=None):
     uu = j if u is None else np.asarray(u, dtype=np.int64)
     k = g.k(uu)
     return np.exp(-p.alpha * k) / (g.s * math.pi) * nx * math.sqrt(g.M) * np.sqrt(prob[uu])
+
+
+def qft_probabilities(p):
+    """p_l = |y_l / ||x|| |^2 for every outcome l (Eq. qft_probabilities) and ||x||^2."""
+    g = grid(p)
+    x = integrand(p, np.arange(g.M, dtype=np.int64))
+    nx2 = float(np.vdot(x, x).real)
+    return np.abs(dft_fft(x)) ** 2 / nx2, nx2
+
+
+def sample_outcomes(prob, uniforms):
+    """Measurement outcomes l in [0, M) drawn from the probabilities `prob` (Eq.
+    qft_probabilities) by exact sequential conditional sampling, one bit at a time from
+    bit 0 (weight 1): with bits 0..t-1 fixed to `pre`, q_b is the total probability of the
+    outcomes whose low t+1 bits are pre + b 2^t, and bit t is 1 iff U_t (q0 + q1) >= q0.
+    uniforms: [R, n] in [0, 1), one per shot and bit. Returns int64 [R]."""
+    prob = np.asarray(prob, dtype=np.float64)
+    M = len(prob)
+    n = M.bit_length() - 1
+    U = np.asarray(uniforms, dtype=np.float64)
+    out = np.zeros(U.shape[0], dtype=np.int64)
+    for t in range(n):
+        S = prob.reshape(-1, 2 ** (t + 1)).sum(axis=0)   # mass of each residue mod 2^(t+1)
+        q0 = S[out]
+        q1 = S[out + 2 ** t]
+        out = out + np.where(U[:, t] * (q0 + q1) >= q0, 2 ** t, 0)
+    return out
+
+
+def shot_prices(p, samples, u, norm2):
+    """Observable prices from R measured outcomes (Eqs. qft_probability_estimator and
+    qft_observable_price): p_hat_l = R_l / R and C_hat(k_l) = e^{-alpha k_l} / (s pi) sqrt(M)
+    ||x|| sqrt(p_hat_l), with norm2 = ||x||^2."""
+    samples = np.sort(np.asarray(samples, dtype=np.int64))
+    u = np.asarray(u, dtype=np.int64)
+    counts = np.searchsorted(samples, u, side="right") - np.searchsorted(samples, u, side="left")
+    return prices_from_counts(p, u, counts, len(samples), norm2)
+
+
+def prices_from_counts(p, u, counts, R, norm2):
+    """C_hat(k_u) = e^{-alpha k_u} / (s pi) sqrt(M) sqrt(norm2 R_u / R) (Eq.
+    qft_observable_price with p_hat = R_u / R)."""
+    g = grid(p)
+    k = g.k(np.asarray(u, dtype=np.int64))
+    return np.exp(-p.alpha * k) / (g.s * math.pi) * math.sqrt(g.M) * np.sqrt(norm2 * np.asarray(counts) / R)
 
 
 def nrmse(C, Cref, S0):

@@ -47,6 +47,60 @@ def test_statevector_nrmse_matches_paper_printed_values():
         assert abs(e - val) <= half_ulp, (n, e, val)
 
 
+def test_sampler_point_mass_and_uniform():
+    """A point mass always yields its outcome; under the uniform law bit t is just
+    U_t >= 1/2 (bit 0 has weight 1)."""
+    g = np.random.default_rng(5)
+    U = g.random((500, 6))
+    pm = np.zeros(64)
+    pm[37] = 1.0
+    assert np.all(O.sample_outcomes(pm, U) == 37)
+    ref = (U >= 0.5).astype(np.int64) @ (2 ** np.arange(6))
+    assert np.array_equal(O.sample_outcomes(np.full(64, 1 / 64), U), ref)
+
+
+def test_sampler_independent_bits_closed_form():
+    """For a law with independent bits, P(bit t = 1) = theta_t, the rule 'bit t is 1 iff
+    U_t (q0 + q1) >= q0' sets bit t exactly when U_t >= 1 - theta_t."""
+    g = np.random.default_rng(6)
+    th = g.uniform(0.1, 0.9, 7)
+    u = np.arange(128)
+    bits = (u[:, None] >> np.arange(7)) & 1
+    prob = np.prod(np.where(bits == 1, th, 1 - th), axis=1)
+    U = g.random((2000, 7))
+    ref = (U >= 1 - th).astype(np.int64) @ (2 ** np.arange(7))
+    got = O.sample_outcomes(prob, U)
+    # outcomes agree except where U_t sits within rounding of the threshold
+    assert np.mean(got == ref) > 0.999
+
+
+def test_sampler_frequencies():
+    """Empirical frequencies of many shots from a random law stay within 5 standard errors."""
+    g = np.random.default_rng(7)
+    prob = g.random(32) ** 3
+    prob /= prob.sum()
+    R = 200000
+    s = O.sample_outcomes(prob, g.random((R, 5)))
+    f = np.bincount(s, minlength=32) / R
+    assert np.all(np.abs(f - prob) <= 5 * np.sqrt(prob * (1 - prob) / R) + 1e-12)
+
+
+def test_shot_prices_equal_statevector_prices_for_exact_counts():
+    """When every outcome is counted in exact proportion R_l = R p_l, the shot estimator
+    (Eqs. qft_probability_estimator, qft_observable_price) equals the exact-probability
+    observable prices of the statevector readout; and shot_prices counts samples."""
+    p = W.paper_bs_grid(5)
+    prob, nx2 = O.qft_probabilities(p)
+    u = np.arange(2 ** 5)
+    R = 1e9
+    got = O.prices_from_counts(p, u, prob * R, R, nx2)
+    ref = O.qft_observable_prices(p, u)
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+    samples = np.array([3, 7, 7, 3, 3, 30, 7, 3])
+    c = O.shot_prices(p, samples, np.array([3, 7, 30, 31]), 2.0)
+    assert np.allclose(c, O.prices_from_counts(p, np.array([3, 7, 30, 31]), np.array([4, 3, 1, 0]), 8, 2.0), rtol=1e-15)
+
+
 def test_statevector_n3_discriminates_readout():
     """At n=3 the Re(.) readout differs from the sqrt(p) readout beyond the printed digits,
     so the pin above really fixes the reconstruction formula."""
