@@ -108,7 +108,7 @@ typedef struct {
 
 /* Operation identifiers for cm_workspace_bytes. */
 enum { CM_OP_QFT_MPO = 0, CM_OP_BUILD_QTT = 1, CM_OP_SFFT_APPLY = 2, CM_OP_TT_ROUND = 3,
-       CM_OP_FFT_PRICE = 4 };
+       CM_OP_FFT_PRICE = 4, CM_OP_SAMPLE = 5 };
 
 /* Host helper. Writes the capacity layout of one train with n cores into off[0..n-1]
  * (complex-element offsets relative to the train's first core; add a per-train base) and
@@ -118,7 +118,8 @@ int64_t cm_tt_layout(int n, int d_out, int d_in, int cap_rank, int64_t *off);
 
 /* Host helper. Bytes of device workspace the operation needs for `batch` instances of
  * chain length at most n_max and bond dimensions at most cap_rank (0 on bad arguments).
- * For CM_OP_FFT_PRICE, n_max is the grid exponent and cap_rank is ignored.
+ * For CM_OP_FFT_PRICE, n_max is the grid exponent and cap_rank is ignored; for
+ * CM_OP_SAMPLE, cap_rank is the train's storage cap y->cap_rank.
  * Sweep ops (CM_OP_BUILD_QTT, CM_OP_SFFT_APPLY, CM_OP_TT_ROUND) run persistent workgroups,
  * one per workspace slab of cm_workspace_bytes(op, 1, n_max, cap_rank, dtype) bytes, each
  * looping over instances b, b + slots, ...: the default size gives min(batch, 2048) slots;
@@ -181,6 +182,46 @@ cm_status cm_tt_round(cm_tt_batch *t, double tol, int cap_rank, double *err_out,
  * index outside [0, M) yields NaN and CM_E_INVALID for that instance. */
 cm_status cm_readout_prices(const cm_tt_batch *y, const cm_problem *prob, const int64_t *strike_idx,
                             int nk, double *prices, int32_t *status, void *stream);
+
+/* Observable read-out with exact probabilities (Section 3.4, Eqs. qft_probabilities and
+ * qft_observable_price with p_hat = p): the QFT measurement gives p_u = |y_u|^2 / ||x||^2,
+ * which loses the phase of y_u, so the price is
+ *   C_hat(k_u) = exp(-alpha k_u)/(s pi) * sqrt(M) * |y_u|,
+ * equal to |complex price| of cm_readout_prices. Arguments, layout and errors as for
+ * cm_readout_prices. */
+cm_status cm_readout_observable(const cm_tt_batch *y, const cm_problem *prob, const int64_t *strike_idx,
+                                int nk, double *prices, int32_t *status, void *stream);
+
+/* Emulated measurement of the QFT register (Section 3.4, Eq. qft_probabilities): R outcomes
+ * per train b drawn from p_u = |y_u|^2 / ||y||^2 without forming the 2^n amplitudes, by
+ * exact sequential conditional sampling from bit 0 (weight 1) upward: with the low t bits
+ * fixed and q_0, q_1 the masses of the two continuations, bit t is 1 iff U_t (q_0 + q_1) >= q_0.
+ * The masses come from right environments (Gram matrices of the partial contractions of
+ * cores t+1..n-1) built in FP64; every decision is taken in FP64.
+ * uniforms: device double [batch][R][y->n_max] in [0, 1) (the caller's random numbers;
+ * train b reads the first n[b] of each row, U_t at position t); out: device int64
+ * [batch][R] outcome indices u in [0, 2^n[b]) (bit t of u is bit t of the outcome, the
+ * log-strike index of cm_readout_prices); norm2: device double [batch] receives ||y_b||^2.
+ * Bonds above 32 give CM_E_UNSUPPORTED for that instance, a zero train CM_E_INVALID, a
+ * non-finite one CM_E_NONFINITE; such instances get out = -1. status: device [batch] (may
+ * be NULL). R = 0 computes norm2 only.
+ * Workspace: cm_workspace_bytes(CM_OP_SAMPLE, batch, y->n_max, y->cap_rank, y->dtype). */
+cm_status cm_sample_outcomes(const cm_tt_batch *y, const double *uniforms, int R, int64_t *out,
+                             double *norm2, int32_t *status, void *ws, size_t ws_bytes, void *stream);
+
+/* Observable prices from R measured outcomes per instance (Eqs. qft_probability_estimator
+ * and qft_observable_price): counts[b][i] = number of samples[b][:] equal to strike_idx[b][i],
+ * p_hat = counts / R and
+ *   C_hat(k_u) = exp(-alpha k_u)/(s pi) * sqrt(M) * sqrt(norm2[b] * p_hat_u).
+ * prob: device [batch] (grid of each instance); norm2: device [batch] (||x||^2, e.g. from
+ * cm_sample_outcomes); samples: device int64 [batch][R] (entries -1 are skipped, other
+ * entries outside [0, M) set CM_E_INVALID); strike_idx: device int64 [batch][nk], strictly
+ * increasing per row (a row that is not, or that leaves [0, M), gets NaN prices and
+ * CM_E_INVALID); counts: device int32 [batch][nk] (written); prices: device double
+ * [batch][nk]. R >= 1. status: device [batch] (may be NULL). */
+cm_status cm_shot_prices(const cm_problem *prob, int batch, const double *norm2, const int64_t *samples, int R,
+                         const int64_t *strike_idx, int nk, int32_t *counts, double *prices, int32_t *status,
+                         void *stream);
 
 /* Dense Carr–Madan baseline (Section 2.1): evaluates x (Eq. x) inside the first FFT pass,
  * applies the minus-sign DFT of Eq. dft with a Stockham FFT in the storage precision, and

@@ -28,7 +28,7 @@ CM_OK, CM_E_INVALID, CM_E_MOMENT, CM_E_RANKCAP, CM_E_NOCONV, CM_E_NONFINITE, CM_
 CM_BS, CM_MERTON, CM_HESTON, CM_VG = range(4)
 CM_QUAD_RECT2, CM_QUAD_SIMPSON1 = range(2)
 CM_C64, CM_C128 = range(2)
-CM_OP_QFT_MPO, CM_OP_BUILD_QTT, CM_OP_SFFT_APPLY, CM_OP_TT_ROUND, CM_OP_FFT_PRICE = range(5)
+CM_OP_QFT_MPO, CM_OP_BUILD_QTT, CM_OP_SFFT_APPLY, CM_OP_TT_ROUND, CM_OP_FFT_PRICE, CM_OP_SAMPLE = range(6)
 CM_TT_LEFT_ORTHO, CM_TT_RIGHT_ORTHO = 1, 2
 
 _MODEL = {"bs": CM_BS, "merton": CM_MERTON, "heston": CM_HESTON, "vg": CM_VG}
@@ -78,6 +78,9 @@ def lib() -> C.CDLL:
         "cm_sfft_apply": (C.c_int, [pb, pb, f64, C.c_int, pb, vp, vp, sz, vp]),
         "cm_tt_round": (C.c_int, [pb, f64, C.c_int, vp, vp, vp, sz, vp]),
         "cm_readout_prices": (C.c_int, [pb, vp, vp, C.c_int, vp, vp, vp]),
+        "cm_readout_observable": (C.c_int, [pb, vp, vp, C.c_int, vp, vp, vp]),
+        "cm_sample_outcomes": (C.c_int, [pb, vp, C.c_int, vp, vp, vp, vp, sz, vp]),
+        "cm_shot_prices": (C.c_int, [vp, C.c_int, vp, vp, C.c_int, vp, C.c_int, vp, vp, vp, vp]),
         "cm_fft_price": (C.c_int, [vp, C.c_int, C.c_int, C.c_int, vp, C.c_int, vp, vp, vp, sz, vp]),
         "cm_mlp_act_bytes": (sz, [C.c_int]),
         "cm_mlp_sync_bf16": (C.c_int, [C.POINTER(CmMlp), vp]),
@@ -100,7 +103,8 @@ def lib() -> C.CDLL:
 
 def exported_symbols() -> List[str]:
     return ["cm_tt_layout", "cm_workspace_bytes", "cm_qft_mpo", "cm_build_qtt", "cm_sfft_apply",
-            "cm_tt_round", "cm_readout_prices", "cm_fft_price", "cm_mlp_act_bytes", "cm_mlp_sync_bf16",
+            "cm_tt_round", "cm_readout_prices", "cm_readout_observable", "cm_sample_outcomes",
+            "cm_shot_prices", "cm_fft_price", "cm_mlp_act_bytes", "cm_mlp_sync_bf16",
             "cm_mlp_forward", "cm_mlp_backward", "cm_mlp_mse", "cm_adam_step", "cm_surrogate_gate",
             "cm_status_str", "cm_version"]
 
@@ -327,6 +331,28 @@ def cm_readout_prices(y: TTBatch, prob_dev, strike_idx, nk: int, prices, status=
     code = lib().cm_readout_prices(C.byref(y.struct), _ptr(prob_dev), _ptr(strike_idx), nk, _ptr(prices),
                                    _ptr(status), _stream_ptr(stream))
     return _check(code, "cm_readout_prices")
+
+
+def cm_readout_observable(y: TTBatch, prob_dev, strike_idx, nk: int, prices, status=None, stream=None) -> int:
+    code = lib().cm_readout_observable(C.byref(y.struct), _ptr(prob_dev), _ptr(strike_idx), nk, _ptr(prices),
+                                       _ptr(status), _stream_ptr(stream))
+    return _check(code, "cm_readout_observable")
+
+
+def cm_sample_outcomes(y: TTBatch, uniforms, R: int, out, norm2, status, ws: Workspace, stream=None) -> int:
+    """uniforms: float64 [batch][R][y.n_max]; out: int64 [batch][R]; norm2: float64 [batch]."""
+    need = cm_workspace_bytes(CM_OP_SAMPLE, y.batch, y.struct.n_max, y.cap_rank, y.dtype)
+    buf = ws.get(need)
+    code = lib().cm_sample_outcomes(C.byref(y.struct), _ptr(uniforms), R, _ptr(out), _ptr(norm2), _ptr(status),
+                                    _ptr(buf), need, _stream_ptr(stream))
+    return _check(code, "cm_sample_outcomes")
+
+
+def cm_shot_prices(prob_dev, batch: int, norm2, samples, R: int, strike_idx, nk: int, counts, prices, status=None,
+                   stream=None) -> int:
+    code = lib().cm_shot_prices(_ptr(prob_dev), batch, _ptr(norm2), _ptr(samples), R, _ptr(strike_idx), nk,
+                                _ptr(counts), _ptr(prices), _ptr(status), _stream_ptr(stream))
+    return _check(code, "cm_shot_prices")
 
 
 def cm_fft_price(prob_dev, batch: int, n: int, dtype: int, strike_idx, nk: int, prices, status, ws: Workspace,

@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "libcm.so")
 OBJ = os.path.join(ROOT, "_build", "obj")
 
 SOURCES = ["cm_abi.cpp", "cm_mpo.hip", "cm_qtt.hip", "cm_zipup.hip", "cm_round.hip", "cm_readout.hip",
-           "cm_fft.hip", "cm_mlp.hip"]
+           "cm_fft.hip", "cm_mlp.hip", "cm_sample.hip"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("CM_OFFLOAD_ARCH", "gfx950")

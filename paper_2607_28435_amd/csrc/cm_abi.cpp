@@ -9,6 +9,7 @@ extern "C" size_t cm_mpo_ws_bytes(int n, int cap);
 extern "C" size_t cm_zip_slab_bytes(int cap);
 extern "C" size_t cm_round_slab_bytes(int n_max, int d, int cap);
 extern "C" size_t cm_fft_ws_bytes(int batch, int n, int dtype, int gather);
+extern "C" size_t cm_sample_ws_bytes(int batch, int n_max, int cap_rank);
 
 // Workgroups kept resident by the batched sweep kernels (each processes trains
 // blockIdx.x, blockIdx.x + slots, ...). Four per compute unit of a 256-CU device.
@@ -60,6 +61,9 @@ extern "C" size_t cm_workspace_bytes(int op, int batch, int n_max, int cap_rank,
       return slots * cm_round_slab_bytes(n_max, 4, cap_rank);
     case CM_OP_FFT_PRICE:
       return cm_fft_ws_bytes(batch, n_max, dtype, 1);
+    case CM_OP_SAMPLE:
+      if (cap_rank < 1 || cap_rank > 256) return 0;
+      return cm_sample_ws_bytes(batch, n_max, cap_rank);
     default:
       return 0;
   }

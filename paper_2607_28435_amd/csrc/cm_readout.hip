@@ -11,6 +11,8 @@
 // The price is
 //   C(k_u) = Re[ exp(-alpha k_u)/(s pi) * exp(-i v0 k_u) * sqrt(M) * y_u ],
 // with exp(-i v0 k_u) = exp(-i v0 k0) (-1)^u for the symmetric rule and 1 for Simpson.
+// The observable mode (the measurement read-out of Section 3.4 with exact probabilities)
+// drops the phase: C(k_u) = exp(-alpha k_u)/(s pi) * sqrt(M) * |y_u|.
 #include <climits>
 
 #include "cm_cf.h"
@@ -61,8 +63,9 @@ __device__ __forceinline__ ReadConst read_const(const cm_problem &pr, int n) {
   return c;
 }
 
-__device__ __forceinline__ double read_price(const ReadConst &c, int64_t u, double2 yu) {
+__device__ __forceinline__ double read_price(const ReadConst &c, int64_t u, double2 yu, int absval) {
   const double k = c.k0 + c.lam * (double)u;
+  if (absval) return exp(-c.alpha * k) * c.sfac * hypot(yu.x, yu.y);
   double2 ro = c.ro;
   if (c.alt && (u & 1)) ro = cmk(-ro.x, -ro.y);
   return exp(-c.alpha * k) * c.sfac * (ro.x * yu.x - ro.y * yu.y);
@@ -176,7 +179,7 @@ template <typename T, int RM>
 __global__ __launch_bounds__(RD_WG) void k_readout(TTView y, const cm_problem *__restrict__ prob,
                                                    const int64_t *__restrict__ strike_idx, int nk,
                                                    double *__restrict__ prices, int32_t *__restrict__ status,
-                                                   int rm_lo) {
+                                                   int rm_lo, int absval) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   __shared__ int32_t s_off[CM_MAX_N + 1], s_rk[CM_MAX_N + 1];
   __shared__ int s_ok;
@@ -299,7 +302,7 @@ __global__ __launch_bounds__(RD_WG) void k_readout(TTView y, const cm_problem *_
       const T *mr = MR + (((int)((u >> TB_H) - hmin) * TB_MID) + (int)((u >> TB_LO) & (TB_MID - 1))) * r5;
       typename rd<T>::V acc = rd<T>::zero();
       for (int a = 0; a < r5; ++a) rd<T>::fma_(acc, lo[a], mr[a]);
-      prices[(int64_t)b * nk + s] = read_price(rc, u, rd<T>::to(acc));
+      prices[(int64_t)b * nk + s] = read_price(rc, u, rd<T>::to(acc), absval);
     }
     return;
   }
@@ -316,7 +319,7 @@ __global__ __launch_bounds__(RD_WG) void k_readout(TTView y, const cm_problem *_
       T yu;
       if (in_lds) yu = contract_strike<T, RM>(arena, LdsOff{s_off}, s_rk, n, u);
       else yu = contract_strike<T, RM>(gcores, GlobalOff{&y, b}, s_rk, n, u);
-      price = read_price(rc, u, rd<T>::to(yu));
+      price = read_price(rc, u, rd<T>::to(yu), absval);
     }
     prices[(int64_t)b * nk + s] = price;
   }
@@ -326,7 +329,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_readout_groups(TTView y, const cm_problem *__restrict__ prob,
                                                  const int64_t *__restrict__ strike_idx, int nk,
                                                  double *__restrict__ prices, int32_t *__restrict__ status, int RW,
-                                                 int rm_lo) {
+                                                 int rm_lo, int absval) {
   extern __shared__ unsigned char lds_raw[];
   T *buf = (T *)lds_raw;  // [2][256]
   const int tid = threadIdx.x;
@@ -368,14 +371,14 @@ __global__ __launch_bounds__(256) void k_readout_groups(TTView y, const cm_probl
       price = NAN;
       set_status(status, b, CM_E_INVALID);
     } else {
-      price = read_price(read_const(pr, n), u, yu);
+      price = read_price(read_const(pr, n), u, yu, absval);
     }
     prices[(int64_t)b * nk + s] = price;
   }
 }
 
-extern "C" cm_status cm_readout_prices(const cm_tt_batch *y, const cm_problem *prob, const int64_t *strike_idx,
-                                       int nk, double *prices, int32_t *status, void *stream) {
+static cm_status readout(const cm_tt_batch *y, const cm_problem *prob, const int64_t *strike_idx, int nk,
+                         double *prices, int32_t *status, void *stream, int absval) {
   if (!y || !prob || !strike_idx || !prices || nk < 0) return CM_E_INVALID;
   if (y->d_out != 2 || y->d_in != 1 || y->batch < 0) return CM_E_INVALID;
   if (y->dtype != CM_C64 && y->dtype != CM_C128) return CM_E_INVALID;
@@ -394,22 +397,22 @@ extern "C" cm_status cm_readout_prices(const cm_tt_batch *y, const cm_problem *p
     CM_HIP_CHECK(cm_allow_lds(k_readout<float2, 16>, RD_LDS));
     CM_HIP_CHECK(cm_allow_lds(k_readout<float2, 32>, RD_LDS));
     hipLaunchKernelGGL((k_readout<float2, 8>), grid, dim3(RD_WG), RD_LDS, s, v, prob, strike_idx, nk, prices, status,
-                       0);
+                       0, absval);
     if (cap > 8)
       hipLaunchKernelGGL((k_readout<float2, 16>), grid, dim3(RD_WG), RD_LDS, s, v, prob, strike_idx, nk, prices,
-                         status, 8);
+                         status, 8, absval);
     if (cap > 16)
       hipLaunchKernelGGL((k_readout<float2, 32>), grid, dim3(RD_WG), RD_LDS, s, v, prob, strike_idx, nk, prices,
-                         status, 16);
+                         status, 16, absval);
     fast_max = 32;
   } else {
     CM_HIP_CHECK(cm_allow_lds(k_readout<double2, 8>, RD_LDS));
     CM_HIP_CHECK(cm_allow_lds(k_readout<double2, 16>, RD_LDS));
     hipLaunchKernelGGL((k_readout<double2, 8>), grid, dim3(RD_WG), RD_LDS, s, v, prob, strike_idx, nk, prices,
-                       status, 0);
+                       status, 0, absval);
     if (cap > 8)
       hipLaunchKernelGGL((k_readout<double2, 16>), grid, dim3(RD_WG), RD_LDS, s, v, prob, strike_idx, nk, prices,
-                         status, 8);
+                         status, 8, absval);
     fast_max = 16;
   }
   CM_LAUNCH_CHECK();
@@ -421,11 +424,101 @@ extern "C" cm_status cm_readout_prices(const cm_tt_batch *y, const cm_problem *p
     dim3 g2((unsigned)((nk + spw - 1) / spw), (unsigned)y->batch);
     if (y->dtype == CM_C64)
       hipLaunchKernelGGL(k_readout_groups<float2>, g2, dim3(256), 2 * 256 * sizeof(float2), s, v, prob, strike_idx,
-                         nk, prices, status, RW, fast_max);
+                         nk, prices, status, RW, fast_max, absval);
     else
       hipLaunchKernelGGL(k_readout_groups<double2>, g2, dim3(256), 2 * 256 * sizeof(double2), s, v, prob,
-                         strike_idx, nk, prices, status, RW, fast_max);
+                         strike_idx, nk, prices, status, RW, fast_max, absval);
   }
+  CM_LAUNCH_CHECK();
+  return CM_OK;
+}
+
+extern "C" cm_status cm_readout_prices(const cm_tt_batch *y, const cm_problem *prob, const int64_t *strike_idx,
+                                       int nk, double *prices, int32_t *status, void *stream) {
+  return readout(y, prob, strike_idx, nk, prices, status, stream, 0);
+}
+
+extern "C" cm_status cm_readout_observable(const cm_tt_batch *y, const cm_problem *prob, const int64_t *strike_idx,
+                                           int nk, double *prices, int32_t *status, void *stream) {
+  return readout(y, prob, strike_idx, nk, prices, status, stream, 1);
+}
+
+// ------------------------------------------------------------------ shot prices
+// Observable prices from measured outcomes (Eqs. qft_probability_estimator and
+// qft_observable_price): R_u of the R shots landed on outcome u, p_hat_u = R_u / R, and
+//   C_hat(k_u) = exp(-alpha k_u)/(s pi) * sqrt(M) * sqrt(||y||^2 p_hat_u).
+// k_shot_count: one lane per shot, a binary search of the instance's sorted strike list
+// and an atomic increment of the matching count. k_shot_price: one lane per strike.
+__global__ __launch_bounds__(256) void k_fill_zero_i32(int32_t *__restrict__ p, int64_t count) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < count; i += (int64_t)gridDim.x * 256) p[i] = 0;
+}
+
+__global__ __launch_bounds__(256) void k_shot_count(const cm_problem *__restrict__ prob,
+                                                    const int64_t *__restrict__ samples, int R,
+                                                    const int64_t *__restrict__ strike_idx, int nk,
+                                                    int32_t *__restrict__ counts, int32_t *__restrict__ status) {
+  const int b = blockIdx.y;
+  const int s = blockIdx.x * 256 + threadIdx.x;
+  if (s >= R) return;
+  const int n = prob[b].n;
+  const int64_t u = samples[(int64_t)b * R + s];
+  if (u == -1) return;  // the sampler's mark for an instance it could not sample
+  if (n < 1 || n > CM_MAX_N || u < 0 || u >= ((int64_t)1 << n)) {
+    set_status(status, b, CM_E_INVALID);
+    return;
+  }
+  const int64_t *row = strike_idx + (int64_t)b * nk;
+  int lo = 0, hi = nk;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (row[mid] < u) lo = mid + 1;
+    else hi = mid;
+  }
+  if (lo < nk && row[lo] == u) atomicAdd(counts + (int64_t)b * nk + lo, 1);
+}
+
+__global__ __launch_bounds__(256) void k_shot_price(const cm_problem *__restrict__ prob,
+                                                    const double *__restrict__ norm2, int R,
+                                                    const int64_t *__restrict__ strike_idx, int nk,
+                                                    const int32_t *__restrict__ counts, double *__restrict__ prices,
+                                                    int32_t *__restrict__ status) {
+  const int b = blockIdx.y;
+  const int s = blockIdx.x * 256 + threadIdx.x;
+  if (s >= nk) return;
+  const cm_problem pr = prob[b];
+  const int n = pr.n;
+  const int64_t *row = strike_idx + (int64_t)b * nk;
+  const int64_t u = row[s];
+  const double nv = norm2[b];
+  const bool ok = n >= 1 && n <= CM_MAX_N && u >= 0 && u < ((int64_t)1 << n) && (s == 0 || row[s - 1] < u) &&
+                  isfinite(nv) && nv > 0.0;
+  double price = NAN;
+  if (!ok) {
+    set_status(status, b, CM_E_INVALID);
+  } else {
+    const ReadConst rc = read_const(pr, n);
+    const double k = rc.k0 + rc.lam * (double)u;
+    const double c = (double)counts[(int64_t)b * nk + s];
+    price = exp(-rc.alpha * k) * rc.sfac * sqrt(nv * c / (double)R);
+  }
+  prices[(int64_t)b * nk + s] = price;
+}
+
+extern "C" cm_status cm_shot_prices(const cm_problem *prob, int batch, const double *norm2, const int64_t *samples,
+                                    int R, const int64_t *strike_idx, int nk, int32_t *counts, double *prices,
+                                    int32_t *status, void *stream) {
+  if (!prob || !norm2 || batch < 0 || nk < 0 || R < 1) return CM_E_INVALID;
+  if (batch == 0 || nk == 0) return CM_OK;
+  if (!samples || !strike_idx || !counts || !prices) return CM_E_INVALID;
+  if (batch > 65535) return CM_E_UNSUPPORTED;
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t total = (int64_t)batch * nk;
+  const int64_t zb = (total + 255) / 256;
+  hipLaunchKernelGGL(k_fill_zero_i32, dim3((unsigned)(zb < 65536 ? zb : 65536)), dim3(256), 0, st, counts, total);
+  hipLaunchKernelGGL(k_shot_count, dim3((unsigned)((R + 255) / 256), (unsigned)batch), dim3(256), 0, st, prob,
+                     samples, R, strike_idx, nk, counts, status);
+  hipLaunchKernelGGL(k_shot_price, dim3((unsigned)((nk + 255) / 256), (unsigned)batch), dim3(256), 0, st, prob,
+                     norm2, R, strike_idx, nk, counts, prices, status);
   CM_LAUNCH_CHECK();
   return CM_OK;
 }

@@ -1,0 +1,242 @@
+// cm_sample_outcomes: measurement outcomes of the QFT register (Section 3.4, Eq.
+// qft_probabilities) drawn from an SFFT output train without forming its 2^n amplitudes.
+//
+// Output core l carries outcome bit 2^l, so the probability mass of the outcomes whose low
+// t+1 bits are (b_0, ..., b_t) is
+//   q(b_0..b_t) = w E_{t+1} w^H,   w = Y_0[0,b_0,:] Y_1[:,b_1,:] ... Y_t[:,b_t,:]  (a row),
+// with the right environments E_l = sum_b Y_l[:,b,:] E_{l+1} Y_l[:,b,:]^H, E_n = [1]: E_l
+// is the Gram matrix of the right partial contractions, and E_0 = ||y||^2. A shot fixes
+// bit 0 first. With prefix row w of mass q, let w0 = w Y_t[:,0,:] and q0 = w0 E_{t+1} w0^H;
+// bit t is 1 iff U_t q >= q0 for the shot's uniform U_t, and the prefix becomes
+// w Y_t[:,bit,:] with its own mass. Every decision is taken in FP64 whatever the storage
+// precision of the train.
+//
+// k_envs: one workgroup per instance builds E_n, ..., E_0 in LDS and stores E_1..E_n in
+// the workspace. k_sample: one lane per shot holding its prefix row in registers (sized
+// by a compile-time bound on the instance's largest bond); for each level t the workgroup
+// stages core t and E_{t+1} in LDS, where every lane reads the same element at a time.
+#include "cm_internal.h"
+
+namespace {
+
+constexpr int SMP_WG = 256;
+constexpr int SMP_RS = 32;  // largest bond dimension the sampler takes
+
+__device__ __forceinline__ int max_bond_of(const int32_t *rk, int n) {
+  int r = 1;
+  for (int l = 0; l <= n; ++l) r = rk[l] > r ? rk[l] : r;
+  return r;
+}
+
+// Environment slab of instance b: E_l at l * RS * RS, stored compact (leading dimension
+// r_l), l = 1..n.
+template <typename T>
+__global__ __launch_bounds__(SMP_WG) void k_envs(TTView y, int RS, int64_t inst_stride, double2 *__restrict__ env,
+                                                 double *__restrict__ norm2, int32_t *__restrict__ status) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  double2 *Yd = (double2 *)lds_raw;   // [r_l][2][r_{l+1}]
+  double2 *Tm = Yd + 2 * RS * RS;     // [2][r_l][r_{l+1}]
+  double2 *Ea = Tm + 2 * RS * RS;     // E_{l+1}
+  double2 *Eb = Ea + RS * RS;         // E_l
+  const int tid = threadIdx.x;
+  const int b = blockIdx.x;
+  const int n = y.n[b];
+  const int32_t *rk = y.rk(b);
+  if (max_bond_of(rk, n) > RS) {
+    if (tid == 0) {
+      norm2[b] = NAN;
+      set_status(status, b, CM_E_UNSUPPORTED);
+    }
+    return;
+  }
+  double2 *Eg = env + (int64_t)b * inst_stride;
+  const T *cores = (const T *)y.cores;
+  if (tid == 0) {
+    Ea[0] = cmk(1.0, 0.0);
+    Eg[(int64_t)n * RS * RS] = cmk(1.0, 0.0);
+  }
+  __syncthreads();
+  for (int l = n - 1; l >= 0; --l) {
+    const int ra = rk[l], rb = rk[l + 1];
+    const T *C = cores + y.coff(b, l);
+    for (int e = tid; e < ra * 2 * rb; e += SMP_WG) Yd[e] = cstore<T>::ld(C, e);
+    __syncthreads();
+    // Tm[bit][c][f] = sum_e Y[c][bit][e] E_{l+1}[e][f]
+    for (int e = tid; e < 2 * ra * rb; e += SMP_WG) {
+      const int bit = e / (ra * rb), c = (e / rb) % ra, f = e % rb;
+      const double2 *row = Yd + (c * 2 + bit) * rb;
+      double2 acc = cmk(0.0, 0.0);
+      for (int q = 0; q < rb; ++q) cfma(acc, row[q], Ea[q * rb + f]);
+      Tm[e] = acc;
+    }
+    __syncthreads();
+    // E_l[c][d] = sum_bit sum_f Tm[bit][c][f] conj(Y[d][bit][f])
+    for (int e = tid; e < ra * ra; e += SMP_WG) {
+      const int c = e / ra, d = e % ra;
+      double2 acc = cmk(0.0, 0.0);
+      for (int bit = 0; bit < 2; ++bit) {
+        const double2 *tr = Tm + (bit * ra + c) * rb;
+        const double2 *yr = Yd + (d * 2 + bit) * rb;
+        for (int f = 0; f < rb; ++f) ccfma(acc, yr[f], tr[f]);
+      }
+      Eb[e] = acc;
+      if (l > 0) Eg[(int64_t)l * RS * RS + e] = acc;
+    }
+    __syncthreads();
+    double2 *t = Ea; Ea = Eb; Eb = t;
+  }
+  if (tid == 0) {
+    const double nv = Ea[0].x;
+    norm2[b] = nv;
+    if (!isfinite(nv)) set_status(status, b, CM_E_NONFINITE);
+    else if (!(nv > 0.0)) set_status(status, b, CM_E_INVALID);
+  }
+}
+
+// w E w^H for Hermitian E (r x r, leading dimension r), from its upper triangle.
+template <int RM>
+__device__ __forceinline__ double quad_form(const double2 *w, const double2 *E, int r) {
+  double acc = 0.0;
+#pragma unroll
+  for (int c = 0; c < RM; ++c) {
+    if (c < r) {
+      // zc = sum_{d>c} conj(E[c][d]) w[d]; Re(w_c E_cd conj(w_d)) summed = Re(w_c conj(zc))
+      double2 zc = cmk(0.0, 0.0);
+#pragma unroll
+      for (int d = c + 1; d < RM; ++d)
+        if (d < r) ccfma(zc, E[c * r + d], w[d]);
+      acc = fma(E[c * r + c].x, cabs2(w[c]), acc);
+      acc = fma(2.0, w[c].x * zc.x + w[c].y * zc.y, acc);
+    }
+  }
+  return acc;
+}
+
+// w <- v Y[:, bit, :] for the staged core Y ([ra][2][rb] in LDS).
+template <int RM>
+__device__ __forceinline__ void row_times_core(const double2 *v, const double2 *Y, int ra, int rb, int bit,
+                                               double2 *w) {
+#pragma unroll
+  for (int c = 0; c < RM; ++c) w[c] = cmk(0.0, 0.0);
+#pragma unroll
+  for (int a = 0; a < RM; ++a) {
+    if (a < ra) {
+      const double2 va = v[a];
+      const double2 *row = Y + (a * 2 + bit) * rb;
+#pragma unroll
+      for (int c = 0; c < RM; ++c)
+        if (c < rb) cfma(w[c], va, row[c]);
+    }
+  }
+}
+
+template <typename T, int RM>
+__global__ __launch_bounds__(SMP_WG) void k_sample(TTView y, const double2 *__restrict__ env, int RS,
+                                                   int64_t inst_stride, const double *__restrict__ norm2,
+                                                   const double *__restrict__ uni, int ustride, int R,
+                                                   int64_t *__restrict__ out, int rm_lo) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  double2 *Yd = (double2 *)lds_raw;   // [ra][2][rb]
+  double2 *Ed = Yd + 2 * RM * RM;     // [rb][rb]
+  const int tid = threadIdx.x;
+  const int b = blockIdx.y;
+  const int n = y.n[b];
+  const int32_t *rk = y.rk(b);
+  // this instantiation serves instances whose largest bond lies in (rm_lo, RM]; the widest
+  // one also writes -1 for instances above every bound
+  const int rmax = max_bond_of(rk, n);
+  if (rmax <= rm_lo) return;
+  const int s = blockIdx.x * SMP_WG + tid;
+  const bool live = s < R;
+  const double q_all = norm2[b];
+  if (rmax > RM || !(q_all > 0.0) || !isfinite(q_all)) {
+    if (live && (rmax <= RM || RM == SMP_RS)) out[(int64_t)b * R + s] = -1;
+    return;
+  }
+  const double *U = uni + ((int64_t)b * R + (live ? s : 0)) * ustride;
+  const T *cores = (const T *)y.cores;
+  const double2 *Eg = env + (int64_t)b * inst_stride;
+  double2 v[RM], w[RM];
+#pragma unroll
+  for (int a = 0; a < RM; ++a) v[a] = cmk(0.0, 0.0);
+  v[0] = cmk(1.0, 0.0);
+  double q = q_all;
+  int64_t idx = 0;
+  for (int t = 0; t < n; ++t) {
+    const int ra = rk[t], rb = rk[t + 1];
+    const double ut = live ? U[t] : 0.0;
+    __syncthreads();
+    const T *C = cores + y.coff(b, t);
+    for (int e = tid; e < ra * 2 * rb; e += SMP_WG) Yd[e] = cstore<T>::ld(C, e);
+    const double2 *Et = Eg + (int64_t)(t + 1) * RS * RS;
+    for (int e = tid; e < rb * rb; e += SMP_WG) Ed[e] = Et[e];
+    __syncthreads();
+    row_times_core<RM>(v, Yd, ra, rb, 0, w);
+    const double q0 = quad_form<RM>(w, Ed, rb);
+    const bool one = ut * q >= q0;
+    q = q0;
+    if (one) {
+      row_times_core<RM>(v, Yd, ra, rb, 1, w);
+      q = quad_form<RM>(w, Ed, rb);
+      idx |= (int64_t)1 << t;
+    }
+#pragma unroll
+    for (int a = 0; a < RM; ++a) v[a] = w[a];
+  }
+  if (live) out[(int64_t)b * R + s] = idx;
+}
+
+int env_rs(int cap_rank) { return cap_rank < SMP_RS ? cap_rank : SMP_RS; }
+
+}  // namespace
+
+extern "C" size_t cm_sample_ws_bytes(int batch, int n_max, int cap_rank) {
+  const int RS = env_rs(cap_rank);
+  return (size_t)batch * (size_t)(n_max + 1) * RS * RS * sizeof(double2);
+}
+
+extern "C" cm_status cm_sample_outcomes(const cm_tt_batch *y, const double *uniforms, int R, int64_t *out,
+                                        double *norm2, int32_t *status, void *ws, size_t ws_bytes, void *stream) {
+  if (!y || !norm2 || R < 0) return CM_E_INVALID;
+  if (y->d_out != 2 || y->d_in != 1 || y->batch < 0) return CM_E_INVALID;
+  if (y->dtype != CM_C64 && y->dtype != CM_C128) return CM_E_INVALID;
+  if (y->cap_rank < 1 || y->cap_rank > 256 || y->n_max < 1 || y->n_max > CM_MAX_N) return CM_E_INVALID;
+  if (y->batch == 0) return CM_OK;
+  if (y->batch > 65535) return CM_E_UNSUPPORTED;
+  if (R > 0 && (!uniforms || !out)) return CM_E_INVALID;
+  const int RS = env_rs(y->cap_rank);
+  const int64_t inst_stride = (int64_t)(y->n_max + 1) * RS * RS;
+  if (!ws || ws_bytes < cm_sample_ws_bytes(y->batch, y->n_max, y->cap_rank)) return CM_E_INVALID;
+  hipStream_t s = (hipStream_t)stream;
+  TTView v = tt_view(y);
+  double2 *env = (double2 *)ws;
+  const size_t env_lds = (size_t)6 * RS * RS * sizeof(double2);
+  if (y->dtype == CM_C64) {
+    CM_HIP_CHECK(cm_allow_lds(k_envs<float2>, env_lds));
+    hipLaunchKernelGGL(k_envs<float2>, dim3((unsigned)y->batch), dim3(SMP_WG), env_lds, s, v, RS, inst_stride, env,
+                       norm2, status);
+  } else {
+    CM_HIP_CHECK(cm_allow_lds(k_envs<double2>, env_lds));
+    hipLaunchKernelGGL(k_envs<double2>, dim3((unsigned)y->batch), dim3(SMP_WG), env_lds, s, v, RS, inst_stride, env,
+                       norm2, status);
+  }
+  CM_LAUNCH_CHECK();
+  if (R == 0) return CM_OK;
+  const dim3 grid((unsigned)((R + SMP_WG - 1) / SMP_WG), (unsigned)y->batch);
+  const int us = y->n_max;
+#define CM_SAMPLE_LAUNCH(T, RM, LO)                                                                              \
+  hipLaunchKernelGGL((k_sample<T, RM>), grid, dim3(SMP_WG), (size_t)3 * RM * RM * sizeof(double2), s, v, env, RS, \
+                     inst_stride, norm2, uniforms, us, R, out, LO)
+  if (y->dtype == CM_C64) {
+    CM_SAMPLE_LAUNCH(float2, 8, 0);
+    if (y->cap_rank > 8) CM_SAMPLE_LAUNCH(float2, 16, 8);
+    if (y->cap_rank > 16) CM_SAMPLE_LAUNCH(float2, 32, 16);
+  } else {
+    CM_SAMPLE_LAUNCH(double2, 8, 0);
+    if (y->cap_rank > 8) CM_SAMPLE_LAUNCH(double2, 16, 8);
+    if (y->cap_rank > 16) CM_SAMPLE_LAUNCH(double2, 32, 16);
+  }
+#undef CM_SAMPLE_LAUNCH
+  CM_LAUNCH_CHECK();
+  return CM_OK;
+}

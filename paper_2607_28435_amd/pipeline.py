@@ -7,7 +7,8 @@ from typing import Dict, Iterable, Optional, Sequence
 import numpy as np
 
 from . import (CM_C64, CM_C128, ProblemArrays, TTBatch, Workspace, cm_build_qtt, cm_fft_price, cm_qft_mpo,
-               cm_readout_prices, cm_sfft_apply, cm_tt_round, pack_problems)
+               cm_readout_observable, cm_readout_prices, cm_sample_outcomes, cm_sfft_apply, cm_shot_prices,
+               cm_tt_round, pack_problems)
 
 
 def _torch():
@@ -82,6 +83,7 @@ class SfftPricer:
                                                         device, stream)
         z = lambda: torch.zeros(self.batch, dtype=torch.int32, device=device)
         self.st_build, self.st_apply, self.st_round, self.st_read = z(), z(), z(), z()
+        self.st_sample, self.st_shot = z(), z()
         self.round_err = torch.zeros(self.batch, dtype=torch.float64, device=device)
         self.ws = Workspace(device)
         self.stream = stream
@@ -140,7 +142,7 @@ class SfftPricer:
 
     def statuses(self) -> Dict[str, np.ndarray]:
         out = {}
-        for k in ("build", "apply", "round", "read"):
+        for k in ("build", "apply", "round", "read", "sample", "shot"):
             v = getattr(self, "st_" + k).cpu().numpy()
             if not self.identity:
                 w = np.empty_like(v)
@@ -148,6 +150,52 @@ class SfftPricer:
                 v = w
             out[k] = v
         return out
+
+    def _to_caller(self, rows):
+        if self.identity:
+            return rows
+        out = _torch().empty_like(rows)
+        out.index_copy_(0, self._perm, rows)
+        return out
+
+    # -- the QFT-observable arm (Section 3.4)
+    def observable(self, strikes):
+        """Observable prices with exact probabilities, exp(-alpha k)/(s pi) sqrt(M) |y_u|, for
+        device int64 strikes [batch, nk] (caller's order); returns float64 [batch, nk]."""
+        torch = _torch()
+        s_int = self.to_internal(strikes)
+        p_int = torch.empty(s_int.shape, dtype=torch.float64, device=strikes.device)
+        self.build()
+        self.apply()
+        self.round()
+        self.st_read.zero_()
+        cm_readout_observable(self.y, self.prob, s_int, s_int.shape[-1], p_int, self.st_read, self.stream)
+        return self._to_caller(p_int)
+
+    def measure(self, strikes, uniforms):
+        """Emulated QFT measurement: builds the output trains, draws R outcomes per
+        instance with the caller's uniforms (device float64 [batch, R, n_max]) and prices
+        the strikes (device int64 [batch, nk], strictly increasing per row) from the
+        outcome counts. Returns (prices float64 [batch, nk], counts int32 [batch, nk],
+        samples int64 [batch, R], norm2 float64 [batch]), all in the caller's order."""
+        torch = _torch()
+        R = int(uniforms.shape[1])
+        dev = strikes.device
+        s_int = self.to_internal(strikes)
+        u_int = self.to_internal(uniforms)
+        samples = torch.empty((self.batch, R), dtype=torch.int64, device=dev)
+        norm2 = torch.empty(self.batch, dtype=torch.float64, device=dev)
+        counts = torch.empty(s_int.shape, dtype=torch.int32, device=dev)
+        prices = torch.empty(s_int.shape, dtype=torch.float64, device=dev)
+        self.build()
+        self.apply()
+        self.round()
+        self.st_sample.zero_()
+        self.st_shot.zero_()
+        cm_sample_outcomes(self.y, u_int, R, samples, norm2, self.st_sample, self.ws, self.stream)
+        cm_shot_prices(self.prob, self.batch, norm2, samples, R, s_int, s_int.shape[-1], counts, prices,
+                       self.st_shot, self.stream)
+        return tuple(self._to_caller(t) for t in (prices, counts, samples, norm2))
 
     # -- HIP graph of the whole chain
     def capture(self, strikes):

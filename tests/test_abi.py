@@ -77,3 +77,11 @@ def test_sweep_workspace_is_per_slot():
         assert _sweep_ws_bytes(op, 100, 24, 32, cm.CM_C64, 7) == 7 * slab
         assert _sweep_ws_bytes(op, 5, 24, 32, cm.CM_C64, 7) == 5 * slab
         assert _sweep_ws_bytes(op, 100, 24, 32, cm.CM_C64, None) == 100 * slab
+
+
+def test_sample_workspace_is_environment_slab():
+    """The sampler keeps (n_max + 1) FP64 complex environments of min(cap, 32)^2 entries
+    per instance."""
+    assert cm.cm_workspace_bytes(cm.CM_OP_SAMPLE, 3, 24, 64, cm.CM_C64) == 3 * 25 * 32 * 32 * 16
+    assert cm.cm_workspace_bytes(cm.CM_OP_SAMPLE, 2, 10, 8, cm.CM_C128) == 2 * 11 * 8 * 8 * 16
+    assert cm.cm_workspace_bytes(cm.CM_OP_SAMPLE, 2, 10, 257, cm.CM_C128) == 0
