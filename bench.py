@@ -48,6 +48,9 @@ def parse():
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--no-ragged", action="store_true")
     ap.add_argument("--no-vg", action="store_true")
+    ap.add_argument("--no-qft", action="store_true")
+    ap.add_argument("--shots", type=int, default=4096, help="measurement shots per instance in the QFT-observable "
+                    "section (the paper's hardware default)")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="time eager steps instead of graph replays "
                     "(for counter-collection runs)")
@@ -156,6 +159,87 @@ def vg_run(cm, torch, batch, nk, steps, n):
             "y_max_rank": int(pr.y.ranks[:, : n + 1].max().item())}
 
 
+def sampler_flops(rk, n, shots, ones):
+    """Algorithmic FP64 flops of the sampler on one train: at level t every shot forms
+    w0 = w Y_t[:,0,:] (8 r_t r_{t+1}) and its mass w0 E w0^H from the upper triangle
+    (4 r(r-1) + 8 r with r = r_{t+1}); shots whose bit t is 1 repeat both for bit 1."""
+    f = 0.0
+    for t in range(n):
+        ra, rb = int(rk[t]), int(rk[t + 1])
+        per = 8 * ra * rb + 4 * rb * (rb - 1) + 8 * rb
+        f += per * (shots + int(ones[t]))
+    return f
+
+
+def qft_run(cm, torch, pr, strikes, shots, steps):
+    """The QFT-observable arm (Section 3.4) emulated on the output trains of the main
+    workload: `shots` measurement outcomes per instance (uniforms drawn on the device
+    from a seeded generator), outcome counts at the read-out strikes and the observable
+    prices from them, next to the exact-probability observable read-out. The error of the
+    shot prices against the exact observable prices is the estimator's shot noise."""
+    batch, n = pr.batch, int(pr.y.struct.n_max)
+    dev = "cuda"
+    stream = torch.cuda.current_stream()
+    g = torch.Generator(device=dev)
+    g.manual_seed(4242)
+    U = torch.rand((batch, shots, n), dtype=torch.float64, device=dev, generator=g)
+    samples = torch.empty((batch, shots), dtype=torch.int64, device=dev)
+    norm2 = torch.empty(batch, dtype=torch.float64, device=dev)
+    st = torch.zeros(batch, dtype=torch.int32, device=dev)
+    st_shot = torch.zeros(batch, dtype=torch.int32, device=dev)
+    nk = strikes.shape[-1]
+    counts = torch.empty((batch, nk), dtype=torch.int32, device=dev)
+    shot_px = torch.empty((batch, nk), dtype=torch.float64, device=dev)
+    exact_px = torch.empty((batch, nk), dtype=torch.float64, device=dev)
+    ws = cm.Workspace(dev)
+
+    def once(ev=None):
+        if ev:
+            ev[0].record(stream)
+        cm.cm_sample_outcomes(pr.y, U, shots, samples, norm2, st, ws)
+        if ev:
+            ev[1].record(stream)
+        cm.cm_shot_prices(pr.prob, batch, norm2, samples, shots, strikes, nk, counts, shot_px, st_shot)
+        if ev:
+            ev[2].record(stream)
+        cm.cm_readout_observable(pr.y, pr.prob, strikes, nk, exact_px, st_shot)
+        if ev:
+            ev[3].record(stream)
+
+    once()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    acc = [0.0, 0.0, 0.0]
+    for _ in range(steps):
+        once(ev)
+        torch.cuda.synchronize()
+        for i in range(3):
+            acc[i] += ev[i].elapsed_time(ev[i + 1])
+    sample_ms, shot_ms, exact_ms = (a / steps for a in acc)
+    sm = samples.cpu().numpy()
+    rk = pr.y.ranks.cpu().numpy()
+    flops = 0.0
+    for b in range(batch):
+        nb = pr.ns[b]
+        ones = ((sm[b][:, None] >> np.arange(nb)) & 1).sum(axis=0)
+        flops += sampler_flops(rk[b], nb, shots, ones)
+    achieved = flops / (sample_ms * 1e-3) / 1e12
+    sp, ep = shot_px.cpu().numpy(), exact_px.cpu().numpy()
+    S0 = np.array([float(p.S0) for p in pr.problems])
+    nrmse = np.sqrt(np.mean((sp - ep) ** 2, axis=1)) / S0
+    cn = counts.cpu().numpy()
+    return {"shots_per_instance": shots, "instances": batch,
+            "shots_per_s": batch * shots / (sample_ms * 1e-3),
+            "sample_ms": sample_ms, "shot_price_ms": shot_ms, "exact_observable_readout_ms": exact_ms,
+            "sampler_roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_TFLOPS,
+                                 "unit": "TFLOP/s (FP64 vector)", "frac": achieved / FP64_VECTOR_TFLOPS},
+            "shots_on_readout_strikes_frac": float(cn.sum() / (batch * shots)),
+            "shot_vs_exact_observable_nrmse_mean": float(nrmse.mean()),
+            "shot_vs_exact_observable_nrmse_max": float(nrmse.max()),
+            "status_errors": {"sample": int((st.cpu().numpy() != 0).sum()),
+                              "shot": int((st_shot.cpu().numpy() != 0).sum())}}
+
+
 def _bs_call(S0, K, r, q, T, sigma):
     """Black–Scholes call (the reference the paper's NRMSE is measured against)."""
     from scipy import special
@@ -164,7 +248,7 @@ def _bs_call(S0, K, r, q, T, sigma):
     return S0 * math.exp(-q * T) * special.ndtr(d1) - K * math.exp(-r * T) * special.ndtr(d1 - sq)
 
 
-def paper_curves(cm, torch, n_lo, n_hi, dense_max, tol=1e-10, reps=3):
+def paper_curves(cm, torch, n_lo, n_hi, dense_max, tol=1e-10, reps=3, shots=4096):
     """Memory, maximal rank, run time and NRMSE against n on the paper's Black–Scholes grid
     (Section 4: S0 = 100, r = 0.05, sigma = 0.3, T = 0.5, alpha = 2.5, N = 2^(n-1),
     Delta_k = N^(-1/2)), FP64 throughout, one instance per run as in the paper:
@@ -173,7 +257,10 @@ def paper_curves(cm, torch, n_lo, n_hi, dense_max, tol=1e-10, reps=3):
       - fft: the dense FFT with read-out of the same strikes (n <= dense_max); memory = the
         2^n complex array;
       - nrmse: over the grid strikes with 0.5 <= K/S0 <= 1.5 (at most 2^16 of them, evenly
-        strided) against the Black–Scholes formula (Eq. error_measure)."""
+        strided) against the Black–Scholes formula (Eq. error_measure);
+      - qft: the observable arm (Section 3.4) from the same y train: the statevector NRMSE
+        (exact probabilities, Eq. qft_observable_price with p_hat = p) and the NRMSE of the
+        shot estimator with `shots` outcomes (seeded uniforms)."""
     rows = []
     for n in range(n_lo, n_hi + 1):
         p = W.paper_bs_grid(n)
@@ -214,6 +301,22 @@ def paper_curves(cm, torch, n_lo, n_hi, dense_max, tol=1e-10, reps=3):
                         "max_rank": int(yr.max()), "x_max_rank": int(pr.x.ranks[0, : n + 1].max().item()),
                         "nrmse": float(np.sqrt(np.mean((got - ref) ** 2)) / 100.0),
                         "status": {k: int(v[0]) for k, v in st.items()}}}
+        obs = torch.empty((1, len(u)), dtype=torch.float64, device="cuda")
+        cm.cm_readout_observable(pr.y, pr.prob, sd, len(u), obs)
+        g = torch.Generator(device="cuda")
+        g.manual_seed(1000 + n)
+        U = torch.rand((1, shots, n), dtype=torch.float64, device="cuda", generator=g)
+        smp = torch.empty((1, shots), dtype=torch.int64, device="cuda")
+        nrm = torch.empty(1, dtype=torch.float64, device="cuda")
+        cnt = torch.empty((1, len(u)), dtype=torch.int32, device="cuda")
+        spx = torch.empty((1, len(u)), dtype=torch.float64, device="cuda")
+        qst = torch.zeros(1, dtype=torch.int32, device="cuda")
+        cm.cm_sample_outcomes(pr.y, U, shots, smp, nrm, qst, cm.Workspace())
+        cm.cm_shot_prices(pr.prob, 1, nrm, smp, shots, sd, len(u), cnt, spx, qst)
+        row["qft"] = {"statevector_nrmse": float(np.sqrt(np.mean((obs.cpu().numpy()[0] - ref) ** 2)) / 100.0),
+                      "shots": shots,
+                      "shot_nrmse": float(np.sqrt(np.mean((spx.cpu().numpy()[0] - ref) ** 2)) / 100.0),
+                      "status": int(qst.item())}
         if n <= dense_max:
             dbox = {}
             t_fft = timed(lambda: dbox.__setitem__("r", cm.dense_prices([p], cm.CM_C128, strikes=sd)))
@@ -392,6 +495,10 @@ def main():
     stat = pr.statuses()
     bad = {k: int((v != 0).sum()) for k, v in stat.items()}
 
+    qft = None
+    if not args.no_qft:
+        qft = qft_run(cm, torch, pr, strikes, args.shots, args.steps)
+
     # ranks for the flop model
     xr = pr.x.ranks.cpu().numpy()
     yr = pr.y.ranks.cpu().numpy()
@@ -472,6 +579,7 @@ def main():
         "eager_ms_per_step": sum(acc.values()) / args.steps,
         "ragged": ragged,
         "variance_gamma": vg,
+        "qft_observable": qft,
         "surrogate": surrogate,
         "mpo_build_s": mpo_s,
         "status_errors": bad,

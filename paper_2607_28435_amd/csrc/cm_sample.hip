@@ -11,10 +11,12 @@
 // w Y_t[:,bit,:] with its own mass. Every decision is taken in FP64 whatever the storage
 // precision of the train.
 //
-// k_envs: one workgroup per instance builds E_n, ..., E_0 in LDS and stores E_1..E_n in
-// the workspace. k_sample: one lane per shot holding its prefix row in registers (sized
-// by a compile-time bound on the instance's largest bond); for each level t the workgroup
-// stages core t and E_{t+1} in LDS, where every lane reads the same element at a time.
+// k_envs: one workgroup per instance builds E_n, ..., E_0 in LDS and stores E_1..E_n and
+// the FP64 cores in the workspace, zero-padded to bond dimensions rounded up to multiples
+// of 4. k_sample: one lane per shot holding its prefix row in registers (sized by a
+// compile-time bound on the instance's largest bond); the products run over 4 x 4 blocks
+// of the padded operands, whose addresses are the same for every lane, so the operands
+// arrive through scalar loads and each block's loads are issued together.
 #include "cm_internal.h"
 
 namespace {
@@ -28,11 +30,16 @@ __device__ __forceinline__ int max_bond_of(const int32_t *rk, int n) {
   return r;
 }
 
-// Environment slab of instance b: E_l at l * RS * RS, stored compact (leading dimension
-// r_l), l = 1..n.
+__host__ __device__ __forceinline__ int pad4(int r) { return (r + 3) & ~3; }
+
+// Workspace slab of one instance (complex FP64 elements):
+//   E_l, l = 1..n:   at l * RS * RS, [p4(r_l)][p4(r_l)]
+//   Y_l, l = 0..n-1: at (n_max + 1) RS^2 + l * 2 RS^2, [p4(r_l)][2][p4(r_{l+1})]
+// with p4 = round up to a multiple of 4 and zeros in the padding.
 template <typename T>
-__global__ __launch_bounds__(SMP_WG) void k_envs(TTView y, int RS, int64_t inst_stride, double2 *__restrict__ env,
-                                                 double *__restrict__ norm2, int32_t *__restrict__ status) {
+__global__ __launch_bounds__(SMP_WG) void k_envs(TTView y, int RS, int n_max, int64_t inst_stride,
+                                                 double2 *__restrict__ ws, double *__restrict__ norm2,
+                                                 int32_t *__restrict__ status) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   double2 *Yd = (double2 *)lds_raw;   // [r_l][2][r_{l+1}]
   double2 *Tm = Yd + 2 * RS * RS;     // [2][r_l][r_{l+1}]
@@ -49,17 +56,24 @@ __global__ __launch_bounds__(SMP_WG) void k_envs(TTView y, int RS, int64_t inst_
     }
     return;
   }
-  double2 *Eg = env + (int64_t)b * inst_stride;
+  double2 *Eg = ws + (int64_t)b * inst_stride;
+  double2 *Yg = Eg + (int64_t)(n_max + 1) * RS * RS;
   const T *cores = (const T *)y.cores;
-  if (tid == 0) {
-    Ea[0] = cmk(1.0, 0.0);
-    Eg[(int64_t)n * RS * RS] = cmk(1.0, 0.0);
-  }
+  // E_n = [1], padded to 4 x 4
+  for (int e = tid; e < 16; e += SMP_WG) Eg[(int64_t)n * RS * RS + e] = cmk(e == 0 ? 1.0 : 0.0, 0.0);
+  if (tid == 0) Ea[0] = cmk(1.0, 0.0);
   __syncthreads();
   for (int l = n - 1; l >= 0; --l) {
     const int ra = rk[l], rb = rk[l + 1];
+    const int pa = pad4(ra), pb = pad4(rb);
     const T *C = cores + y.coff(b, l);
     for (int e = tid; e < ra * 2 * rb; e += SMP_WG) Yd[e] = cstore<T>::ld(C, e);
+    // padded FP64 copy of the core for the sampler
+    double2 *Yl = Yg + (int64_t)l * 2 * RS * RS;
+    for (int e = tid; e < pa * 2 * pb; e += SMP_WG) {
+      const int a = e / (2 * pb), bit = (e / pb) % 2, c = e % pb;
+      Yl[e] = (a < ra && c < rb) ? cstore<T>::ld(C, (a * 2 + bit) * rb + c) : cmk(0.0, 0.0);
+    }
     __syncthreads();
     // Tm[bit][c][f] = sum_e Y[c][bit][e] E_{l+1}[e][f]
     for (int e = tid; e < 2 * ra * rb; e += SMP_WG) {
@@ -80,9 +94,15 @@ __global__ __launch_bounds__(SMP_WG) void k_envs(TTView y, int RS, int64_t inst_
         for (int f = 0; f < rb; ++f) ccfma(acc, yr[f], tr[f]);
       }
       Eb[e] = acc;
-      if (l > 0) Eg[(int64_t)l * RS * RS + e] = acc;
     }
     __syncthreads();
+    if (l > 0) {
+      double2 *El = Eg + (int64_t)l * RS * RS;
+      for (int e = tid; e < pa * pa; e += SMP_WG) {
+        const int c = e / pa, d = e % pa;
+        El[e] = (c < ra && d < ra) ? Eb[c * ra + d] : cmk(0.0, 0.0);
+      }
+    }
     double2 *t = Ea; Ea = Eb; Eb = t;
   }
   if (tid == 0) {
@@ -93,51 +113,80 @@ __global__ __launch_bounds__(SMP_WG) void k_envs(TTView y, int RS, int64_t inst_
   }
 }
 
-// w E w^H for Hermitian E (r x r, leading dimension r), from its upper triangle.
+// w <- v Y[:, bit, :] over 4 x 4 blocks of the padded core Y ([pa][2][pb], pa, pb <= RM).
+// Entries of v past the bond are zero, and so are the padded columns of Y.
 template <int RM>
-__device__ __forceinline__ double quad_form(const double2 *w, const double2 *E, int r) {
+__device__ __forceinline__ void row_times_core(const double2 *v, const double2 *__restrict__ Y, int pa, int pb,
+                                               int bit, double2 *w) {
+#pragma unroll
+  for (int c = 0; c < RM; ++c) w[c] = cmk(0.0, 0.0);
+#pragma unroll
+  for (int c4 = 0; c4 < RM; c4 += 4) {
+    if (c4 < pb) {
+#pragma unroll
+      for (int a4 = 0; a4 < RM; a4 += 4) {
+        if (a4 < pa) {
+          double2 yb[4][4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) yb[i][j] = Y[((a4 + i) * 2 + bit) * pb + c4 + j];
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) cfma(w[c4 + j], v[a4 + i], yb[i][j]);
+        }
+      }
+    }
+  }
+}
+
+// w E w^H for Hermitian E (padded [p][p], p <= RM) from its upper triangle, 4 x 4 blocks.
+template <int RM>
+__device__ __forceinline__ double quad_form(const double2 *w, const double2 *__restrict__ E, int p) {
   double acc = 0.0;
 #pragma unroll
-  for (int c = 0; c < RM; ++c) {
-    if (c < r) {
-      // zc = sum_{d>c} conj(E[c][d]) w[d]; Re(w_c E_cd conj(w_d)) summed = Re(w_c conj(zc))
-      double2 zc = cmk(0.0, 0.0);
+  for (int c4 = 0; c4 < RM; c4 += 4) {
+    if (c4 < p) {
+      // z_i = sum_{d > c4+i} conj(E[c4+i][d]) w[d]
+      double2 z[4];
 #pragma unroll
-      for (int d = c + 1; d < RM; ++d)
-        if (d < r) ccfma(zc, E[c * r + d], w[d]);
-      acc = fma(E[c * r + c].x, cabs2(w[c]), acc);
-      acc = fma(2.0, w[c].x * zc.x + w[c].y * zc.y, acc);
+      for (int i = 0; i < 4; ++i) z[i] = cmk(0.0, 0.0);
+      double diag[4];
+#pragma unroll
+      for (int d4 = c4; d4 < RM; d4 += 4) {
+        if (d4 < p) {
+          double2 eb[4][4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+              if (d4 > c4 || j >= i) eb[i][j] = E[(c4 + i) * p + d4 + j];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            if (d4 == c4) diag[i] = eb[i][i].x;
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+              if (d4 > c4 || j > i) ccfma(z[i], eb[i][j], w[d4 + j]);
+          }
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const double2 wc = w[c4 + i];
+        acc = fma(diag[i], cabs2(wc), acc);
+        acc = fma(2.0, wc.x * z[i].x + wc.y * z[i].y, acc);
+      }
     }
   }
   return acc;
 }
 
-// w <- v Y[:, bit, :] for the staged core Y ([ra][2][rb] in LDS).
 template <int RM>
-__device__ __forceinline__ void row_times_core(const double2 *v, const double2 *Y, int ra, int rb, int bit,
-                                               double2 *w) {
-#pragma unroll
-  for (int c = 0; c < RM; ++c) w[c] = cmk(0.0, 0.0);
-#pragma unroll
-  for (int a = 0; a < RM; ++a) {
-    if (a < ra) {
-      const double2 va = v[a];
-      const double2 *row = Y + (a * 2 + bit) * rb;
-#pragma unroll
-      for (int c = 0; c < RM; ++c)
-        if (c < rb) cfma(w[c], va, row[c]);
-    }
-  }
-}
-
-template <typename T, int RM>
-__global__ __launch_bounds__(SMP_WG) void k_sample(TTView y, const double2 *__restrict__ env, int RS,
+__global__ __launch_bounds__(SMP_WG) void k_sample(TTView y, const double2 *__restrict__ ws, int RS, int n_max,
                                                    int64_t inst_stride, const double *__restrict__ norm2,
                                                    const double *__restrict__ uni, int ustride, int R,
                                                    int64_t *__restrict__ out, int rm_lo) {
-  extern __shared__ __align__(16) unsigned char lds_raw[];
-  double2 *Yd = (double2 *)lds_raw;   // [ra][2][rb]
-  double2 *Ed = Yd + 2 * RM * RM;     // [rb][rb]
   const int tid = threadIdx.x;
   const int b = blockIdx.y;
   const int n = y.n[b];
@@ -147,15 +196,15 @@ __global__ __launch_bounds__(SMP_WG) void k_sample(TTView y, const double2 *__re
   const int rmax = max_bond_of(rk, n);
   if (rmax <= rm_lo) return;
   const int s = blockIdx.x * SMP_WG + tid;
-  const bool live = s < R;
+  if (s >= R) return;
   const double q_all = norm2[b];
   if (rmax > RM || !(q_all > 0.0) || !isfinite(q_all)) {
-    if (live && (rmax <= RM || RM == SMP_RS)) out[(int64_t)b * R + s] = -1;
+    if (rmax <= RM || RM == SMP_RS) out[(int64_t)b * R + s] = -1;
     return;
   }
-  const double *U = uni + ((int64_t)b * R + (live ? s : 0)) * ustride;
-  const T *cores = (const T *)y.cores;
-  const double2 *Eg = env + (int64_t)b * inst_stride;
+  const double *U = uni + ((int64_t)b * R + s) * ustride;
+  const double2 *Eg = ws + (int64_t)b * inst_stride;
+  const double2 *Yg = Eg + (int64_t)(n_max + 1) * RS * RS;
   double2 v[RM], w[RM];
 #pragma unroll
   for (int a = 0; a < RM; ++a) v[a] = cmk(0.0, 0.0);
@@ -163,36 +212,34 @@ __global__ __launch_bounds__(SMP_WG) void k_sample(TTView y, const double2 *__re
   double q = q_all;
   int64_t idx = 0;
   for (int t = 0; t < n; ++t) {
-    const int ra = rk[t], rb = rk[t + 1];
-    const double ut = live ? U[t] : 0.0;
-    __syncthreads();
-    const T *C = cores + y.coff(b, t);
-    for (int e = tid; e < ra * 2 * rb; e += SMP_WG) Yd[e] = cstore<T>::ld(C, e);
-    const double2 *Et = Eg + (int64_t)(t + 1) * RS * RS;
-    for (int e = tid; e < rb * rb; e += SMP_WG) Ed[e] = Et[e];
-    __syncthreads();
-    row_times_core<RM>(v, Yd, ra, rb, 0, w);
-    const double q0 = quad_form<RM>(w, Ed, rb);
+    const int pa = pad4(rk[t]), pb = pad4(rk[t + 1]);
+    const double ut = U[t];
+    const double2 *Y = Yg + (int64_t)t * 2 * RS * RS;
+    const double2 *E = Eg + (int64_t)(t + 1) * RS * RS;
+    row_times_core<RM>(v, Y, pa, pb, 0, w);
+    const double q0 = quad_form<RM>(w, E, pb);
     const bool one = ut * q >= q0;
     q = q0;
     if (one) {
-      row_times_core<RM>(v, Yd, ra, rb, 1, w);
-      q = quad_form<RM>(w, Ed, rb);
+      row_times_core<RM>(v, Y, pa, pb, 1, w);
+      q = quad_form<RM>(w, E, pb);
       idx |= (int64_t)1 << t;
     }
 #pragma unroll
     for (int a = 0; a < RM; ++a) v[a] = w[a];
   }
-  if (live) out[(int64_t)b * R + s] = idx;
+  out[(int64_t)b * R + s] = idx;
 }
 
-int env_rs(int cap_rank) { return cap_rank < SMP_RS ? cap_rank : SMP_RS; }
+// slot edge: the bond bound rounded up to a multiple of 4 (the padded blocks fit)
+int env_rs(int cap_rank) { return pad4(cap_rank < SMP_RS ? cap_rank : SMP_RS); }
 
 }  // namespace
 
+// environments (n_max + 1) RS^2 plus padded FP64 cores 2 n_max RS^2 per instance
 extern "C" size_t cm_sample_ws_bytes(int batch, int n_max, int cap_rank) {
   const int RS = env_rs(cap_rank);
-  return (size_t)batch * (size_t)(n_max + 1) * RS * RS * sizeof(double2);
+  return (size_t)batch * (size_t)(3 * n_max + 1) * RS * RS * sizeof(double2);
 }
 
 extern "C" cm_status cm_sample_outcomes(const cm_tt_batch *y, const double *uniforms, int R, int64_t *out,
@@ -205,37 +252,32 @@ extern "C" cm_status cm_sample_outcomes(const cm_tt_batch *y, const double *unif
   if (y->batch > 65535) return CM_E_UNSUPPORTED;
   if (R > 0 && (!uniforms || !out)) return CM_E_INVALID;
   const int RS = env_rs(y->cap_rank);
-  const int64_t inst_stride = (int64_t)(y->n_max + 1) * RS * RS;
+  const int64_t inst_stride = (int64_t)(3 * y->n_max + 1) * RS * RS;
   if (!ws || ws_bytes < cm_sample_ws_bytes(y->batch, y->n_max, y->cap_rank)) return CM_E_INVALID;
   hipStream_t s = (hipStream_t)stream;
   TTView v = tt_view(y);
-  double2 *env = (double2 *)ws;
+  double2 *slab = (double2 *)ws;
+  const int nm = y->n_max;
   const size_t env_lds = (size_t)6 * RS * RS * sizeof(double2);
   if (y->dtype == CM_C64) {
     CM_HIP_CHECK(cm_allow_lds(k_envs<float2>, env_lds));
-    hipLaunchKernelGGL(k_envs<float2>, dim3((unsigned)y->batch), dim3(SMP_WG), env_lds, s, v, RS, inst_stride, env,
-                       norm2, status);
+    hipLaunchKernelGGL(k_envs<float2>, dim3((unsigned)y->batch), dim3(SMP_WG), env_lds, s, v, RS, nm, inst_stride,
+                       slab, norm2, status);
   } else {
     CM_HIP_CHECK(cm_allow_lds(k_envs<double2>, env_lds));
-    hipLaunchKernelGGL(k_envs<double2>, dim3((unsigned)y->batch), dim3(SMP_WG), env_lds, s, v, RS, inst_stride, env,
-                       norm2, status);
+    hipLaunchKernelGGL(k_envs<double2>, dim3((unsigned)y->batch), dim3(SMP_WG), env_lds, s, v, RS, nm, inst_stride,
+                       slab, norm2, status);
   }
   CM_LAUNCH_CHECK();
   if (R == 0) return CM_OK;
   const dim3 grid((unsigned)((R + SMP_WG - 1) / SMP_WG), (unsigned)y->batch);
   const int us = y->n_max;
-#define CM_SAMPLE_LAUNCH(T, RM, LO)                                                                              \
-  hipLaunchKernelGGL((k_sample<T, RM>), grid, dim3(SMP_WG), (size_t)3 * RM * RM * sizeof(double2), s, v, env, RS, \
-                     inst_stride, norm2, uniforms, us, R, out, LO)
-  if (y->dtype == CM_C64) {
-    CM_SAMPLE_LAUNCH(float2, 8, 0);
-    if (y->cap_rank > 8) CM_SAMPLE_LAUNCH(float2, 16, 8);
-    if (y->cap_rank > 16) CM_SAMPLE_LAUNCH(float2, 32, 16);
-  } else {
-    CM_SAMPLE_LAUNCH(double2, 8, 0);
-    if (y->cap_rank > 8) CM_SAMPLE_LAUNCH(double2, 16, 8);
-    if (y->cap_rank > 16) CM_SAMPLE_LAUNCH(double2, 32, 16);
-  }
+#define CM_SAMPLE_LAUNCH(RM, LO)                                                                         \
+  hipLaunchKernelGGL((k_sample<RM>), grid, dim3(SMP_WG), 0, s, v, slab, RS, nm, inst_stride, norm2, uniforms, us, R, \
+                     out, LO)
+  CM_SAMPLE_LAUNCH(8, 0);
+  if (y->cap_rank > 8) CM_SAMPLE_LAUNCH(16, 8);
+  if (y->cap_rank > 16) CM_SAMPLE_LAUNCH(32, 16);
 #undef CM_SAMPLE_LAUNCH
   CM_LAUNCH_CHECK();
   return CM_OK;

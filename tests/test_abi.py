@@ -80,8 +80,9 @@ def test_sweep_workspace_is_per_slot():
 
 
 def test_sample_workspace_is_environment_slab():
-    """The sampler keeps (n_max + 1) FP64 complex environments of min(cap, 32)^2 entries
-    per instance."""
-    assert cm.cm_workspace_bytes(cm.CM_OP_SAMPLE, 3, 24, 64, cm.CM_C64) == 3 * 25 * 32 * 32 * 16
-    assert cm.cm_workspace_bytes(cm.CM_OP_SAMPLE, 2, 10, 8, cm.CM_C128) == 2 * 11 * 8 * 8 * 16
+    """The sampler keeps, per instance, n_max + 1 environment slots and n_max core slots of
+    two FP64 complex blocks each, of edge RS = min(cap, 32) rounded up to a multiple of 4."""
+    assert cm.cm_workspace_bytes(cm.CM_OP_SAMPLE, 3, 24, 64, cm.CM_C64) == 3 * (3 * 24 + 1) * 32 * 32 * 16
+    assert cm.cm_workspace_bytes(cm.CM_OP_SAMPLE, 2, 10, 8, cm.CM_C128) == 2 * 31 * 8 * 8 * 16
+    assert cm.cm_workspace_bytes(cm.CM_OP_SAMPLE, 1, 10, 10, cm.CM_C128) == 31 * 12 * 12 * 16
     assert cm.cm_workspace_bytes(cm.CM_OP_SAMPLE, 2, 10, 257, cm.CM_C128) == 0
