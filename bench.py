@@ -49,6 +49,7 @@ def parse():
     ap.add_argument("--no-ragged", action="store_true")
     ap.add_argument("--no-vg", action="store_true")
     ap.add_argument("--no-qft", action="store_true")
+    ap.add_argument("--no-mpo-table", action="store_true")
     ap.add_argument("--shots", type=int, default=4096, help="measurement shots per instance in the QFT-observable "
                     "section (the paper's hardware default)")
     ap.add_argument("--no-surrogate", action="store_true")
@@ -157,6 +158,44 @@ def vg_run(cm, torch, batch, nk, steps, n):
     return {"grids_per_s": batch / dt, "ms_per_step": dt * 1e3, "max_abs_diff_vs_dense_over_S0": diff,
             "status_errors": {k: int((v != 0).sum()) for k, v in st.items()},
             "y_max_rank": int(pr.y.ranks[:, : n + 1].max().item())}
+
+
+def mpo_table_run(cm, torch, n_lo=1, n_hi=40, tol=1e-9, cap=32, reps=3):
+    """The operator look-up table: Q_n for every n in [n_lo, n_hi] (complex64, the bench
+    chain's operator tolerance) built by one cm_qft_mpo_table launch, against one
+    cm_qft_mpo call per n, and against loading the saved table from a file."""
+    import tempfile
+
+    def best(fn):
+        t = float("inf")
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            t = min(t, time.perf_counter() - t0)
+        return t
+
+    box = {}
+    t_table = best(lambda: box.__setitem__("m", cm.MpoCache(range(n_lo, n_hi + 1), tol, cap, cm.CM_C64)))
+    m = box["m"]
+    single = cm.TTBatch([n if n >= n_lo else 0 for n in range(n_hi + 1)], 2, 2, cap, cm.CM_C64)
+    ws = cm.Workspace()
+
+    def seq():
+        for n in range(n_lo, n_hi + 1):
+            cm.cm_qft_mpo(n, tol, cap, single, n, ws)
+
+    t_seq = best(seq)
+    identical = bool(torch.equal(single.cores, m.w.cores) and torch.equal(single.ranks, m.w.ranks))
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "qft_table.npz")
+        m.save(path)
+        size = os.path.getsize(path)
+        t_load = best(lambda: cm.MpoCache.load(path))
+    return {"n_range": [n_lo, n_hi], "tol": tol, "cap": cap, "table_build_ms": t_table * 1e3,
+            "one_call_per_n_ms": t_seq * 1e3, "load_from_file_ms": t_load * 1e3, "file_bytes": size,
+            "max_rank": int(m.w.rank_max), "table_equals_per_n_builds": identical}
 
 
 def sampler_flops(rk, n, shots, ones):
@@ -495,6 +534,9 @@ def main():
     stat = pr.statuses()
     bad = {k: int((v != 0).sum()) for k, v in stat.items()}
 
+    mpo_table = None
+    if not args.no_mpo_table:
+        mpo_table = mpo_table_run(cm, torch)
     qft = None
     if not args.no_qft:
         qft = qft_run(cm, torch, pr, strikes, args.shots, args.steps)
@@ -580,6 +622,7 @@ def main():
         "ragged": ragged,
         "variance_gamma": vg,
         "qft_observable": qft,
+        "mpo_table": mpo_table,
         "surrogate": surrogate,
         "mpo_build_s": mpo_s,
         "status_errors": bad,

@@ -118,6 +118,7 @@ int64_t cm_tt_layout(int n, int d_out, int d_in, int cap_rank, int64_t *off);
 
 /* Host helper. Bytes of device workspace the operation needs for `batch` instances of
  * chain length at most n_max and bond dimensions at most cap_rank (0 on bad arguments).
+ * For CM_OP_QFT_MPO, batch is the number of operators one call builds (1 for cm_qft_mpo).
  * For CM_OP_FFT_PRICE, n_max is the grid exponent and cap_rank is ignored; for
  * CM_OP_SAMPLE, cap_rank is the train's storage cap y->cap_rank.
  * Sweep ops (CM_OP_BUILD_QTT, CM_OP_SFFT_APPLY, CM_OP_TT_ROUND) run persistent workgroups,
@@ -138,6 +139,16 @@ size_t cm_workspace_bytes(int op, int batch, int n_max, int cap_rank, int dtype)
  * Workspace: cm_workspace_bytes(CM_OP_QFT_MPO, 1, n, cap_rank, dtype). */
 cm_status cm_qft_mpo(int n, double tol, int cap_rank, cm_tt_batch *w, int slot,
                      void *ws, size_t ws_bytes, void *stream);
+
+/* Operator look-up table (the stored SFFT operators of Sections 3.3 and 4.1: Q_n depends only
+ * on n and the tolerance, so it is built once and reused): builds Q_n exactly as cm_qft_mpo
+ * does, for every n in [n_lo, n_hi], into train slot n of `w` (w->batch > n_hi, w->n[n] == n
+ * on the device), with one workgroup per operator in a single launch. The operators are
+ * bit-identical to those of separate cm_qft_mpo calls. Synchronises `stream` once; returns
+ * the first non-OK status among the operators.
+ * Workspace: cm_workspace_bytes(CM_OP_QFT_MPO, n_hi - n_lo + 1, n_hi, cap_rank, dtype). */
+cm_status cm_qft_mpo_table(int n_lo, int n_hi, double tol, int cap_rank, cm_tt_batch *w,
+                           void *ws, size_t ws_bytes, void *stream);
 
 /* Builds, for each problem b, the QTT of the integrand
  *   x_j = w_j psi(v_j) exp(-i j eta k0)          (Eq. x; psi from Eq. psi)

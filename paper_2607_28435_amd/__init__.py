@@ -74,6 +74,7 @@ def lib() -> C.CDLL:
         "cm_tt_layout": (i64, [C.c_int, C.c_int, C.c_int, C.c_int, vp]),
         "cm_workspace_bytes": (sz, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]),
         "cm_qft_mpo": (C.c_int, [C.c_int, f64, C.c_int, pb, C.c_int, vp, sz, vp]),
+        "cm_qft_mpo_table": (C.c_int, [C.c_int, C.c_int, f64, C.c_int, pb, vp, sz, vp]),
         "cm_build_qtt": (C.c_int, [vp, C.c_int, f64, C.c_int, pb, vp, vp, sz, vp]),
         "cm_sfft_apply": (C.c_int, [pb, pb, f64, C.c_int, pb, vp, vp, sz, vp]),
         "cm_tt_round": (C.c_int, [pb, f64, C.c_int, vp, vp, vp, sz, vp]),
@@ -102,7 +103,7 @@ def lib() -> C.CDLL:
 
 
 def exported_symbols() -> List[str]:
-    return ["cm_tt_layout", "cm_workspace_bytes", "cm_qft_mpo", "cm_build_qtt", "cm_sfft_apply",
+    return ["cm_tt_layout", "cm_workspace_bytes", "cm_qft_mpo", "cm_qft_mpo_table", "cm_build_qtt", "cm_sfft_apply",
             "cm_tt_round", "cm_readout_prices", "cm_readout_observable", "cm_sample_outcomes",
             "cm_shot_prices", "cm_fft_price", "cm_mlp_act_bytes", "cm_mlp_sync_bf16",
             "cm_mlp_forward", "cm_mlp_backward", "cm_mlp_mse", "cm_adam_step", "cm_surrogate_gate",
@@ -298,6 +299,15 @@ def cm_qft_mpo(n: int, tol: float, cap_rank: int, w: TTBatch, slot: int, ws: Wor
     buf = ws.get(need)
     code = lib().cm_qft_mpo(n, tol, cap_rank, C.byref(w.struct), slot, _ptr(buf), buf.numel(), _stream_ptr(stream))
     return _check(code, "cm_qft_mpo")
+
+
+def cm_qft_mpo_table(n_lo: int, n_hi: int, tol: float, cap_rank: int, w: TTBatch, ws: Workspace,
+                     stream=None) -> int:
+    need = cm_workspace_bytes(CM_OP_QFT_MPO, n_hi - n_lo + 1, n_hi, cap_rank, w.dtype)
+    buf = ws.get(need)
+    code = lib().cm_qft_mpo_table(n_lo, n_hi, tol, cap_rank, C.byref(w.struct), _ptr(buf), buf.numel(),
+                                  _stream_ptr(stream))
+    return _check(code, "cm_qft_mpo_table")
 
 
 def cm_build_qtt(prob_dev, batch: int, tol: float, cap_rank: int, x: TTBatch, status, ws: Workspace,

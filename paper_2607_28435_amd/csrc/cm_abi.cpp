@@ -48,8 +48,10 @@ extern "C" size_t cm_workspace_bytes(int op, int batch, int n_max, int cap_rank,
   const size_t slots = (size_t)cm_slots_for(batch);
   switch (op) {
     case CM_OP_QFT_MPO:
-      if (cap_rank < 1 || cap_rank > 64) return 0;
-      return cm_mpo_ws_bytes(n_max, cap_rank);
+      // `batch` operators built in one call (cm_qft_mpo: 1), slabs sized for n_max, then
+      // one 256-byte block of status words
+      if (cap_rank < 1 || cap_rank > 64 || batch > CM_MAX_N) return 0;
+      return (size_t)batch * cm_mpo_ws_bytes(n_max, cap_rank) + 256;
     case CM_OP_BUILD_QTT:
       if (cap_rank < 1 || cap_rank > 64) return 0;
       return slots * cm_qtt_slab_bytes(n_max, cap_rank);

@@ -64,10 +64,17 @@ __device__ double lagr01(int q, double x, const double *cn) {
 
 }  // namespace
 
+// Workgroup g builds Q_n with n = n_lo + g into train slot0 + g of w, in its own slab
+// ws + g * slab, and writes its status to code_out[g].
 template <typename OutT>
-__global__ __launch_bounds__(CM_WG) void k_qft_mpo(int n, double tol, int cap, TTView w, int slot,
-                                                   char *__restrict__ ws, int32_t *__restrict__ code_out) {
+__global__ __launch_bounds__(CM_WG) void k_qft_mpo(int n_lo, double tol, int cap, TTView w, int slot0,
+                                                   char *__restrict__ ws_all, size_t slab,
+                                                   int32_t *__restrict__ code_all) {
   extern __shared__ __align__(16) char lds_arena[];
+  const int n = n_lo + (int)blockIdx.x;
+  const int slot = slot0 + (int)blockIdx.x;
+  char *ws = ws_all + (size_t)blockIdx.x * slab;
+  int32_t *code_out = code_all + blockIdx.x;
   __shared__ la::Sh sh;
   __shared__ double cn[MP];
   __shared__ int code_sh;
@@ -118,39 +125,65 @@ __global__ __launch_bounds__(CM_WG) void k_qft_mpo(int n, double tol, int cap, T
   if (tid == 0) *code_out = code_sh;
 }
 
+// One operator's slab; the status words follow the slabs in the last 256-byte block.
 extern "C" size_t cm_mpo_ws_bytes(int n, int cap) {
   size_t parts[6];
-  return mpo_slab_bytes(n, cap, parts) + 256;
+  return mpo_slab_bytes(n, cap, parts);
 }
 
-extern "C" cm_status cm_qft_mpo(int n, double tol, int cap_rank, cm_tt_batch *w, int slot, void *ws,
-                                size_t ws_bytes, void *stream) {
-  if (!w || n < 1 || n > CM_MAX_N || !(tol > 0.0) || cap_rank < 1 || cap_rank > 64) return CM_E_INVALID;
-  if (w->d_out != 2 || w->d_in != 2 || slot < 0 || slot >= w->batch || cap_rank > w->cap_rank) return CM_E_INVALID;
+static size_t mpo_table_bytes(int count, int n_max, int cap) {
+  return (size_t)count * cm_mpo_ws_bytes(n_max, cap) + align256m(sizeof(int32_t) * (size_t)count);
+}
+
+// Builds Q_n for n = n_lo .. n_hi into slots slot0 .. slot0 + (n_hi - n_lo) with one
+// workgroup per operator, then reads the ranks back once.
+static cm_status mpo_build(int n_lo, int n_hi, double tol, int cap_rank, cm_tt_batch *w, int slot0, void *ws,
+                           size_t ws_bytes, void *stream) {
+  if (!w || n_lo < 1 || n_hi < n_lo || n_hi > CM_MAX_N || !(tol > 0.0) || cap_rank < 1 || cap_rank > 64)
+    return CM_E_INVALID;
+  const int count = n_hi - n_lo + 1;
+  if (w->d_out != 2 || w->d_in != 2 || slot0 < 0 || slot0 + count > w->batch || cap_rank > w->cap_rank)
+    return CM_E_INVALID;
   if (w->dtype != CM_C64 && w->dtype != CM_C128) return CM_E_INVALID;
-  const size_t need = cm_workspace_bytes(CM_OP_QFT_MPO, 1, n, cap_rank, w->dtype);
-  if (!ws || ws_bytes < need) return CM_E_INVALID;
+  const size_t slab = cm_mpo_ws_bytes(n_hi, cap_rank);
+  if (!ws || ws_bytes < mpo_table_bytes(count, n_hi, cap_rank)) return CM_E_INVALID;
   hipStream_t s = (hipStream_t)stream;
-  // status word lives at the end of the workspace
-  int32_t *code_d = (int32_t *)((char *)ws + need - 256);
+  int32_t *code_d = (int32_t *)((char *)ws + (size_t)count * slab);
   TTView v = tt_view(w);
   const size_t lds = MLDS;
   CM_HIP_CHECK(cm_allow_lds(k_qft_mpo<float2>, lds));
   CM_HIP_CHECK(cm_allow_lds(k_qft_mpo<double2>, lds));
   if (w->dtype == CM_C64)
-    hipLaunchKernelGGL(k_qft_mpo<float2>, dim3(1), dim3(CM_WG), lds, s, n, tol, cap_rank, v, slot, (char *)ws, code_d);
+    hipLaunchKernelGGL(k_qft_mpo<float2>, dim3((unsigned)count), dim3(CM_WG), lds, s, n_lo, tol, cap_rank, v, slot0,
+                       (char *)ws, slab, code_d);
   else
-    hipLaunchKernelGGL(k_qft_mpo<double2>, dim3(1), dim3(CM_WG), lds, s, n, tol, cap_rank, v, slot, (char *)ws, code_d);
+    hipLaunchKernelGGL(k_qft_mpo<double2>, dim3((unsigned)count), dim3(CM_WG), lds, s, n_lo, tol, cap_rank, v, slot0,
+                       (char *)ws, slab, code_d);
   CM_LAUNCH_CHECK();
-  int32_t ranks[CM_RANKS_STRIDE];
-  int32_t code = 0;
-  CM_HIP_CHECK(hipMemcpyAsync(ranks, w->ranks + (int64_t)slot * CM_RANKS_STRIDE, sizeof(int32_t) * (n + 1),
-                              hipMemcpyDeviceToHost, s));
-  CM_HIP_CHECK(hipMemcpyAsync(&code, code_d, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  int32_t ranks[CM_MAX_N][CM_RANKS_STRIDE];
+  int32_t codes[CM_MAX_N];
+  CM_HIP_CHECK(hipMemcpyAsync(ranks, w->ranks + (int64_t)slot0 * CM_RANKS_STRIDE,
+                              sizeof(int32_t) * CM_RANKS_STRIDE * (size_t)count, hipMemcpyDeviceToHost, s));
+  CM_HIP_CHECK(hipMemcpyAsync(codes, code_d, sizeof(int32_t) * (size_t)count, hipMemcpyDeviceToHost, s));
   CM_HIP_CHECK(hipStreamSynchronize(s));
-  int rmax = 0;
-  for (int l = 0; l <= n; ++l) rmax = ranks[l] > rmax ? ranks[l] : rmax;
-  if (rmax > w->rank_max) w->rank_max = rmax;
+  cm_status first = CM_OK;
+  for (int g = 0; g < count; ++g) {
+    const int n = n_lo + g;
+    int rmax = 0;
+    for (int l = 0; l <= n; ++l) rmax = ranks[g][l] > rmax ? ranks[g][l] : rmax;
+    if (rmax > w->rank_max) w->rank_max = rmax;
+    if (first == CM_OK && codes[g] != CM_OK) first = (cm_status)codes[g];
+  }
   w->flags = CM_TT_RIGHT_ORTHO;
-  return (cm_status)code;
+  return first;
+}
+
+extern "C" cm_status cm_qft_mpo(int n, double tol, int cap_rank, cm_tt_batch *w, int slot, void *ws,
+                                size_t ws_bytes, void *stream) {
+  return mpo_build(n, n, tol, cap_rank, w, slot, ws, ws_bytes, stream);
+}
+
+extern "C" cm_status cm_qft_mpo_table(int n_lo, int n_hi, double tol, int cap_rank, cm_tt_batch *w, void *ws,
+                                      size_t ws_bytes, void *stream) {
+  return mpo_build(n_lo, n_hi, tol, cap_rank, w, n_lo, ws, ws_bytes, stream);
 }

@@ -6,7 +6,8 @@ from typing import Dict, Iterable, Optional, Sequence
 
 import numpy as np
 
-from . import (CM_C64, CM_C128, ProblemArrays, TTBatch, Workspace, cm_build_qtt, cm_fft_price, cm_qft_mpo,
+from . import (CM_C64, CM_C128, CM_TT_RIGHT_ORTHO, ProblemArrays, TTBatch, Workspace, cm_build_qtt, cm_fft_price,
+               cm_qft_mpo, cm_qft_mpo_table,
                cm_readout_observable, cm_readout_prices, cm_sample_outcomes, cm_sfft_apply, cm_shot_prices,
                cm_tt_round, pack_problems)
 
@@ -17,20 +18,48 @@ def _torch():
 
 
 class MpoCache:
-    """Q_n operators for a set of chain lengths, stored so that train n is Q_n
-    (the layout cm_sfft_apply expects). Built once per (n, tol, cap, dtype)."""
+    """Operator look-up table: Q_n for every n from min(ns) to max(ns), stored so that train
+    n is Q_n (the layout cm_sfft_apply expects) and built by one cm_qft_mpo_table launch
+    (one workgroup per operator). Q_n depends only on n, the tolerance, the bond cap and the
+    storage type, so `save` writes the table to an .npz file and `load` restores it without
+    constructing anything."""
 
-    def __init__(self, ns: Iterable[int], tol: float, cap: int, dtype: int, device="cuda", stream=None):
+    FORMAT = 1
+
+    def __init__(self, ns: Iterable[int], tol: float, cap: int, dtype: int, device="cuda", stream=None,
+                 build: bool = True):
         ns = sorted(set(int(n) for n in ns))
         self.tol, self.cap, self.dtype = tol, cap, dtype
-        n_max = max(ns)
-        slots = [n if n in ns else 0 for n in range(n_max + 1)]
+        self.n_lo, self.n_hi = ns[0], ns[-1]
+        slots = [n if self.n_lo <= n <= self.n_hi else 0 for n in range(self.n_hi + 1)]
         self.w = TTBatch(slots, 2, 2, cap, dtype, device)
-        self.w.struct.n_max = n_max
-        ws = Workspace(device)
-        for n in ns:
-            cm_qft_mpo(n, tol, cap, self.w, n, ws, stream)
-        self.ns = ns
+        self.w.struct.n_max = self.n_hi
+        self.ns = list(range(self.n_lo, self.n_hi + 1))
+        if build:
+            cm_qft_mpo_table(self.n_lo, self.n_hi, tol, cap, self.w, Workspace(device), stream)
+
+    def save(self, path: str) -> None:
+        """Writes the table (cores, bond dimensions and the parameters it was built with)."""
+        np.savez(path, format=self.FORMAT, tol=self.tol, cap=self.cap, dtype=self.dtype, n_lo=self.n_lo,
+                 n_hi=self.n_hi, rank_max=self.w.rank_max, ranks=self.w.ranks.cpu().numpy(),
+                 core_off=self.w.core_off.cpu().numpy(), cores=self.w.cores.cpu().numpy())
+
+    @classmethod
+    def load(cls, path: str, device="cuda") -> "MpoCache":
+        """Restores a table written by `save` (plain arrays; nothing in the file is executed)."""
+        torch = _torch()
+        with np.load(path, allow_pickle=False) as z:
+            if int(z["format"]) != cls.FORMAT:
+                raise ValueError(f"{path}: operator table format {int(z['format'])}, expected {cls.FORMAT}")
+            m = cls(range(int(z["n_lo"]), int(z["n_hi"]) + 1), float(z["tol"]), int(z["cap"]), int(z["dtype"]),
+                    device, build=False)
+            if not np.array_equal(z["core_off"], m.w.core_off.cpu().numpy()) or z["cores"].shape != m.w.cores.shape:
+                raise ValueError(f"{path}: operator table layout does not match")
+            m.w.cores.copy_(torch.from_numpy(z["cores"]))
+            m.w.ranks.copy_(torch.from_numpy(z["ranks"]))
+            m.w.struct.rank_max = int(z["rank_max"])
+        m.w.struct.flags = CM_TT_RIGHT_ORTHO
+        return m
 
 
 _SWEEP_OPS = ("build", "apply", "round")

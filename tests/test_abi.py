@@ -86,3 +86,31 @@ def test_sample_workspace_is_environment_slab():
     assert cm.cm_workspace_bytes(cm.CM_OP_SAMPLE, 2, 10, 8, cm.CM_C128) == 2 * 31 * 8 * 8 * 16
     assert cm.cm_workspace_bytes(cm.CM_OP_SAMPLE, 1, 10, 10, cm.CM_C128) == 31 * 12 * 12 * 16
     assert cm.cm_workspace_bytes(cm.CM_OP_SAMPLE, 2, 10, 257, cm.CM_C128) == 0
+
+
+def test_operator_table_file_round_trip(tmp_path):
+    """The operator look-up table's file format (host logic only; no GPU): a table written by
+    `save` loads back with identical cores, bond dimensions and parameters, and a file of
+    another layout is refused."""
+    import torch
+    m = cm.MpoCache([3, 4, 5, 6], 1e-9, 8, cm.CM_C128, device="cpu", build=False)
+    g = np.random.default_rng(0)
+    m.w.cores.copy_(torch.from_numpy(g.standard_normal(m.w.cores.shape) + 1j * g.standard_normal(m.w.cores.shape)))
+    rk = np.ones(m.w.ranks.shape, dtype=np.int32)
+    for n in range(3, 7):
+        rk[n, 1:n] = 4
+    m.w.ranks.copy_(torch.from_numpy(rk))
+    m.w.struct.rank_max = 4
+    path = str(tmp_path / "qft_table.npz")
+    m.save(path)
+    r = cm.MpoCache.load(path, device="cpu")
+    assert (r.n_lo, r.n_hi, r.tol, r.cap, r.dtype) == (3, 6, 1e-9, 8, cm.CM_C128)
+    assert torch.equal(r.w.cores, m.w.cores) and torch.equal(r.w.ranks, m.w.ranks)
+    assert r.w.rank_max == 4 and r.w.struct.flags == cm.CM_TT_RIGHT_ORTHO
+    other = cm.MpoCache([3, 4, 5, 6], 1e-9, 16, cm.CM_C128, device="cpu", build=False)
+    other.save(path)
+    z = dict(np.load(path, allow_pickle=False))
+    z["cap"] = np.array(8)
+    np.savez(path, **z)
+    with pytest.raises(ValueError):
+        cm.MpoCache.load(path, device="cpu")

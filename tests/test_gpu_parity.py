@@ -60,6 +60,40 @@ def test_qft_mpo_rank_is_small():
         assert 8 <= rk.max() <= 14, rk
 
 
+@pytest.mark.parametrize("dtype", [cm.CM_C128, cm.CM_C64])
+def test_mpo_table_bit_identical_to_single_builds(dtype):
+    """One cm_qft_mpo_table launch for n = 1..14 gives, bit for bit, the operators that
+    separate cm_qft_mpo calls give, and each is the bit-reversed DFT."""
+    say("mpo table", dtype)
+    tol = 1e-12 if dtype == cm.CM_C128 else 1e-7
+    table = cm.MpoCache(range(1, 15), tol, 32, dtype)
+    ws = cm.Workspace()
+    for n in (1, 2, 5, 9, 14):
+        single = cm.TTBatch([0] * n + [n], 2, 2, 32, dtype)
+        cm.cm_qft_mpo(n, tol, 32, single, n, ws)
+        a, b = table.w.host_cores(n), single.host_cores(n)
+        assert len(a) == len(b) == n
+        assert all(x.shape == y.shape and np.array_equal(x, y) for x, y in zip(a, b)), n
+    for n in (3, 7, 10):
+        err = np.abs(contract_mpo(table.w.host_cores(n)) - O.qn_matrix(n)).max()
+        assert err < (1e-10 if dtype == cm.CM_C128 else 1e-5), (n, err)
+
+
+def test_mpo_table_saved_and_loaded_prices_identically(tmp_path):
+    """A table written to disk and loaded back prices bit-identically to the one built."""
+    say("mpo table save/load")
+    p = W.bs_rect_n12()
+    m = cm.MpoCache([10, 11, 12], 1e-11, 32, cm.CM_C128)
+    path = str(tmp_path / "q.npz")
+    m.save(path)
+    m2 = cm.MpoCache.load(path)
+    u = _strikes_dev([W.all_strikes(p)])
+    a = cm.SfftPricer([p], cm.CM_C128, tol=1e-10, cap=32, mpo=m).run(u).cpu().numpy()
+    b = cm.SfftPricer([p], cm.CM_C128, tol=1e-10, cap=32, mpo=m2).run(u).cpu().numpy()
+    assert np.array_equal(a, b)
+    assert np.abs(a[0] - O.prices_dense(p)).max() / p.S0 < FP64_TOL
+
+
 # ------------------------------------------------------------------ QTT of the integrand
 
 @pytest.mark.parametrize("name", ["bs_rect", "bs_simpson", "heston16", "merton16", "heston_rect14", "vg16"])
