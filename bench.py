@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--no-vg", action="store_true")
     ap.add_argument("--no-qft", action="store_true")
     ap.add_argument("--no-mpo-table", action="store_true")
+    ap.add_argument("--default-slots", action="store_true", help="skip the slot autotuner (library default: "
+                    "min(batch, 2048) persistent workgroups per sweep op)")
     ap.add_argument("--shots", type=int, default=4096, help="measurement shots per instance in the QFT-observable "
                     "section (the paper's hardware default)")
     ap.add_argument("--no-surrogate", action="store_true")
@@ -117,7 +119,7 @@ def ragged_run(cm, torch, batch, nk, steps):
     strikes = torch.from_numpy(np.stack([W.near_money(p, nk) for p in probs])).cuda()
     mpo = cm.MpoCache(ns, 1e-9, 32, cm.CM_C64)
     pr = cm.SfftPricer(probs, cm.CM_C64, tol=1e-8, cap=32, mpo=mpo)
-    slots = cm.autotune_slots(pr, strikes, candidates=(512, 1024, 2048, 4096), reps=1)
+    slots = cm.autotune_slots(pr, strikes, candidates=SLOT_CANDIDATES, reps=1)
     pr.capture(strikes)
     pr.replay()
     torch.cuda.synchronize()
@@ -158,6 +160,11 @@ def vg_run(cm, torch, batch, nk, steps, n):
     return {"grids_per_s": batch / dt, "ms_per_step": dt * 1e3, "max_abs_diff_vs_dense_over_S0": diff,
             "status_errors": {k: int((v != 0).sum()) for k, v in st.items()},
             "y_max_rank": int(pr.y.ranks[:, : n + 1].max().item())}
+
+
+# persistent-workgroup counts tried by the autotuner: multiples of the 256 CUs up to one
+# workgroup per instance
+SLOT_CANDIDATES = (768, 1024, 1536, 2048, 3072, 4096)
 
 
 def mpo_table_run(cm, torch, n_lo=1, n_hi=40, tol=1e-9, cap=32, reps=3):
@@ -480,6 +487,10 @@ def main():
     torch.cuda.synchronize()
     mpo_s = time.perf_counter() - t0
     pr = cm.SfftPricer(probs, cm.CM_C64, tol=1e-8, cap=32, mpo=mpo)
+    # persistent-workgroup counts of the three sweep ops, timed on this batch (untimed)
+    slots = {k: None for k in ("build", "apply", "round")}
+    if not args.default_slots:
+        slots = cm.autotune_slots(pr, strikes, candidates=SLOT_CANDIDATES, reps=2)
 
     ev = {k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for k in ("build", "apply", "round", "read")}
@@ -612,7 +623,8 @@ def main():
         "data": "synthetic seeded Heston parameter draws",
         "config": {"workload": f"batched Heston SFFT, {args.batch} instances, n={args.n} "
                                f"(M=2^{args.n}), eta=40/2^{args.n // 2}, tol 1e-8, {nk} read-out strikes",
-                   "batch": args.batch, "n": args.n, "parallelism": "none (1 GPU)"},
+                   "batch": args.batch, "n": args.n, "parallelism": "none (1 GPU)",
+                   "slots": {k: (int(v) if v is not None else "default") for k, v in slots.items()}},
         "dense_fft_grids_per_s": dense_gps,
         "sfft_over_dense": sfft_gps / dense_gps,
         "max_abs_err_over_S0": max_err,

@@ -61,13 +61,36 @@ __host__ __device__ inline size_t qtt_slab_bytes(int n_max, int cap, size_t *par
   size_t o = 0;
   parts[0] = o; o += align256(sizeof(TreeDepth) * (size_t)(n_max + 1));
   parts[1] = o; o += align256(sizeof(double2) * (size_t)PRE_CAP * 2 * PRE_CAP * n_max);
-  parts[2] = o; o += align256(sizeof(int32_t) * (CM_MAX_N + 1));
+  parts[2] = o; o += align256(sizeof(int32_t) * (CM_MAX_N + 2));   // ranks, then the instance mark
   parts[3] = o; o += align256(sizeof(int64_t) * CM_MAX_N);
   parts[4] = o; o += align256(sizeof(double2) * core_cap * n_max);  // rs.tt
   parts[5] = o; o += align256(sizeof(double2) * core_cap * 6);      // rs.Y..C
   parts[6] = o; o += align256(sizeof(double2) * 2 * 64 * 64);        // global Jacobi pair
   parts[7] = o; o += align256(sizeof(double2) * QNC * QNPT);         // candidate values
   return o;
+}
+
+// Index of the slab's instance mark: the instance whose pre-rounding train the slab holds,
+// or -1 (set by k_build_qtt, read by k_build_round).
+constexpr int QMARK = CM_MAX_N + 1;
+
+__device__ inline QttSlab qtt_slab_view(char *slab, int n_max, int cap) {
+  size_t parts[8];
+  qtt_slab_bytes(n_max, cap, parts);
+  QttSlab W;
+  W.tree = (TreeDepth *)(slab + parts[0]);
+  W.pre = (double2 *)(slab + parts[1]);
+  W.pre_ranks = (int32_t *)(slab + parts[2]);
+  W.pre_off = (int64_t *)(slab + parts[3]);
+  const int capm = cap > PRE_CAP ? cap : PRE_CAP;
+  W.rs.core_cap = (int64_t)capm * 2 * capm;
+  W.rs.tt = (double2 *)(slab + parts[4]);
+  double2 *mats = (double2 *)(slab + parts[5]);
+  W.rs.Y = mats; W.rs.X = mats + W.rs.core_cap; W.rs.Z = mats + 2 * W.rs.core_cap;
+  W.rs.L = mats + 3 * W.rs.core_cap; W.rs.R = mats + 4 * W.rs.core_cap; W.rs.C = mats + 5 * W.rs.core_cap;
+  W.rs.S = (double2 *)(slab + parts[6]);
+  W.rs.J = W.rs.S + 64 * 64;
+  return W;
 }
 
 __device__ __forceinline__ double node_pos(double Lm1, double c) { return Lm1 * 0.5 * (1.0 - c); }
@@ -117,10 +140,14 @@ __device__ __forceinline__ double v0mf_frac(const cm_problem &pr) {
   return f - floor(f);
 }
 
+// Tree and assembly for instances base + g (workgroup g, one instance each): the
+// pre-rounding train stays in slab g, marked with its instance; k_build_round then rounds it
+// into x. The two phases are separate launches because the tree phase (the characteristic
+// function) needs 256 VGPRs while the rounding runs at twice the occupancy without it.
 template <typename OutT>
 // At most 256 VGPRs (two waves per SIMD): left alone the compiler takes 256 VGPRs plus AGPRs
-// and one wave per SIMD; two halve the build time despite a small spill.
-__global__ __launch_bounds__(CM_WG, 2) void k_build_qtt(const cm_problem *__restrict__ prob, int batch,
+// and one wave per SIMD; two halve the time despite a small spill.
+__global__ __launch_bounds__(CM_WG, 2) void k_build_qtt(const cm_problem *__restrict__ prob, int batch, int base,
                                                      double tol, int cap, TTView x,
                                                      int32_t *__restrict__ status,
                                                      char *__restrict__ ws, size_t slab_bytes, int n_max) {
@@ -137,26 +164,18 @@ __global__ __launch_bounds__(CM_WG, 2) void k_build_qtt(const cm_problem *__rest
   qtt_slab_bytes(n_max, cap, parts);
   char *slab = ws + (size_t)blockIdx.x * slab_bytes;
   double2 *vals = (sizeof(double2) * QNC * QNPT <= (size_t)QLDS) ? (double2 *)lds_arena : (double2 *)(slab + parts[7]);
-  QttSlab W;
-  W.tree = (TreeDepth *)(slab + parts[0]);
-  W.pre = (double2 *)(slab + parts[1]);
-  W.pre_ranks = (int32_t *)(slab + parts[2]);
-  W.pre_off = (int64_t *)(slab + parts[3]);
-  const int capm = cap > PRE_CAP ? cap : PRE_CAP;
-  W.rs.core_cap = (int64_t)capm * 2 * capm;
-  W.rs.tt = (double2 *)(slab + parts[4]);
-  double2 *mats = (double2 *)(slab + parts[5]);
-  W.rs.Y = mats; W.rs.X = mats + W.rs.core_cap; W.rs.Z = mats + 2 * W.rs.core_cap;
-  W.rs.L = mats + 3 * W.rs.core_cap; W.rs.R = mats + 4 * W.rs.core_cap; W.rs.C = mats + 5 * W.rs.core_cap;
-  W.rs.S = (double2 *)(slab + parts[6]);
-  W.rs.J = W.rs.S + 64 * 64;
+  QttSlab W = qtt_slab_view(slab, n_max, cap);
   if (tid < QP) {
     cq[tid] = cos(M_PI * tid / (QP - 1));
     ck[tid] = cos(M_PI * (tid + 0.5) / (QP - 1));
   }
+  if (tid == 0) W.pre_ranks[QMARK] = -1;
   __syncthreads();
 
-  for (int b = blockIdx.x; b < batch; b += gridDim.x) {
+  // exactly one instance per workgroup (the host launches one workgroup per instance of the
+  // chunk); the loop form keeps `continue` for the early exits
+  const int end = (base + (int)gridDim.x < batch) ? base + (int)gridDim.x : batch;
+  for (int b = base + (int)blockIdx.x; b < end; b += gridDim.x) {
     const cm_problem pr = prob[b];
     if (tid == 0) {
       int c = check_problem(pr);
@@ -365,17 +384,35 @@ __global__ __launch_bounds__(CM_WG, 2) void k_build_qtt(const cm_problem *__rest
       __syncthreads();
     }
 
-    // ---------------- rounding into x
-    CoreSrc src;
-    src.cores = W.pre; src.off = W.pre_off; src.ranks = W.pre_ranks; src.dtype = CM_C128;
-    OutT *xc = (OutT *)x.cores;
-    const double err = round_train_auto<OutT>(n, 2, src, tol, cap, xc, x.off + (int64_t)b * CM_MAX_N, x.rk(b),
-                                              W.rs, lds_arena, QLDS, sh, &code_sh);
-    (void)err;
-    __syncthreads();
-    if (tid == 0 && status) status[b] = code_sh;
+    // the rounding into x is k_build_round's
+    if (tid == 0) W.pre_ranks[QMARK] = b;
     __syncthreads();
   }
+}
+
+// Rounds the pre-rounding train of slab g (if k_build_qtt marked one) into x, with cores
+// 1..n-1 right-orthonormal, and writes the instance's status.
+template <typename OutT>
+__global__ __launch_bounds__(CM_WG) void k_build_round(const cm_problem *__restrict__ prob, double tol, int cap,
+                                                       TTView x, int32_t *__restrict__ status,
+                                                       char *__restrict__ ws, size_t slab_bytes, int n_max) {
+  extern __shared__ __align__(16) char lds_arena[];
+  __shared__ la::Sh sh;
+  __shared__ int code_sh;
+  const int tid = threadIdx.x;
+  QttSlab W = qtt_slab_view(ws + (size_t)blockIdx.x * slab_bytes, n_max, cap);
+  const int b = W.pre_ranks[QMARK];
+  if (b < 0) return;
+  const int n = prob[b].n;
+  if (tid == 0) code_sh = CM_OK;
+  __syncthreads();
+  CoreSrc src;
+  src.cores = W.pre; src.off = W.pre_off; src.ranks = W.pre_ranks; src.dtype = CM_C128;
+  const double err = round_train_auto<OutT>(n, 2, src, tol, cap, (OutT *)x.cores, x.off + (int64_t)b * CM_MAX_N,
+                                            x.rk(b), W.rs, lds_arena, QLDS, sh, &code_sh);
+  (void)err;
+  __syncthreads();
+  if (tid == 0 && status) status[b] = code_sh;
 }
 
 // ------------------------------------------------------------------ host side
@@ -403,13 +440,25 @@ extern "C" cm_status cm_build_qtt(const cm_problem *prob, int batch, double tol,
   hipStream_t s = (hipStream_t)stream;
   CM_HIP_CHECK(cm_allow_lds(k_build_qtt<float2>, lds));
   CM_HIP_CHECK(cm_allow_lds(k_build_qtt<double2>, lds));
-  if (x->dtype == CM_C64)
-    hipLaunchKernelGGL(k_build_qtt<float2>, dim3(slots), dim3(CM_WG), lds, s, prob, batch, tol, cap_rank, v,
-                       status, (char *)ws, slab, x->n_max);
-  else
-    hipLaunchKernelGGL(k_build_qtt<double2>, dim3(slots), dim3(CM_WG), lds, s, prob, batch, tol, cap_rank, v,
-                       status, (char *)ws, slab, x->n_max);
-  CM_LAUNCH_CHECK();
+  CM_HIP_CHECK(cm_allow_lds(k_build_round<float2>, lds));
+  CM_HIP_CHECK(cm_allow_lds(k_build_round<double2>, lds));
+  // chunks of `slots` instances: tree and assembly (one workgroup per instance), then the
+  // rounding of the chunk's trains
+  for (int base = 0; base < batch; base += slots) {
+    const int cnt = batch - base < slots ? batch - base : slots;
+    if (x->dtype == CM_C64) {
+      hipLaunchKernelGGL(k_build_qtt<float2>, dim3(cnt), dim3(CM_WG), lds, s, prob, batch, base, tol, cap_rank, v,
+                         status, (char *)ws, slab, x->n_max);
+      hipLaunchKernelGGL(k_build_round<float2>, dim3(cnt), dim3(CM_WG), lds, s, prob, tol, cap_rank, v, status,
+                         (char *)ws, slab, x->n_max);
+    } else {
+      hipLaunchKernelGGL(k_build_qtt<double2>, dim3(cnt), dim3(CM_WG), lds, s, prob, batch, base, tol, cap_rank, v,
+                         status, (char *)ws, slab, x->n_max);
+      hipLaunchKernelGGL(k_build_round<double2>, dim3(cnt), dim3(CM_WG), lds, s, prob, tol, cap_rank, v, status,
+                         (char *)ws, slab, x->n_max);
+    }
+    CM_LAUNCH_CHECK();
+  }
   x->flags = CM_TT_RIGHT_ORTHO;
   return CM_OK;
 }
