@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--no-mpo-table", action="store_true")
     ap.add_argument("--default-slots", action="store_true", help="skip the slot autotuner (library default: "
                     "min(batch, 2048) persistent workgroups per sweep op)")
+    ap.add_argument("--slots", type=int, nargs=3, metavar=("BUILD", "APPLY", "ROUND"), default=None,
+                    help="fixed persistent-workgroup counts instead of the autotuner (for profiling runs)")
     ap.add_argument("--shots", type=int, default=4096, help="measurement shots per instance in the QFT-observable "
                     "section (the paper's hardware default)")
     ap.add_argument("--no-surrogate", action="store_true")
@@ -228,7 +230,7 @@ def qft_run(cm, torch, pr, strikes, shots, steps):
     stream = torch.cuda.current_stream()
     g = torch.Generator(device=dev)
     g.manual_seed(4242)
-    U = torch.rand((batch, shots, n), dtype=torch.float64, device=dev, generator=g)
+    U = torch.rand((batch, n, shots), dtype=torch.float64, device=dev, generator=g)
     samples = torch.empty((batch, shots), dtype=torch.int64, device=dev)
     norm2 = torch.empty(batch, dtype=torch.float64, device=dev)
     st = torch.zeros(batch, dtype=torch.int32, device=dev)
@@ -351,7 +353,7 @@ def paper_curves(cm, torch, n_lo, n_hi, dense_max, tol=1e-10, reps=3, shots=4096
         cm.cm_readout_observable(pr.y, pr.prob, sd, len(u), obs)
         g = torch.Generator(device="cuda")
         g.manual_seed(1000 + n)
-        U = torch.rand((1, shots, n), dtype=torch.float64, device="cuda", generator=g)
+        U = torch.rand((1, n, shots), dtype=torch.float64, device="cuda", generator=g)
         smp = torch.empty((1, shots), dtype=torch.int64, device="cuda")
         nrm = torch.empty(1, dtype=torch.float64, device="cuda")
         cnt = torch.empty((1, len(u)), dtype=torch.int32, device="cuda")
@@ -489,7 +491,10 @@ def main():
     pr = cm.SfftPricer(probs, cm.CM_C64, tol=1e-8, cap=32, mpo=mpo)
     # persistent-workgroup counts of the three sweep ops, timed on this batch (untimed)
     slots = {k: None for k in ("build", "apply", "round")}
-    if not args.default_slots:
+    if args.slots:
+        slots = dict(zip(("build", "apply", "round"), args.slots))
+        pr.slots.update(slots)
+    elif not args.default_slots:
         slots = cm.autotune_slots(pr, strikes, candidates=SLOT_CANDIDATES, reps=2)
 
     ev = {k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))

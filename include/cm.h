@@ -209,8 +209,8 @@ cm_status cm_readout_observable(const cm_tt_batch *y, const cm_problem *prob, co
  * fixed and q_0, q_1 the masses of the two continuations, bit t is 1 iff U_t (q_0 + q_1) >= q_0.
  * The masses come from right environments (Gram matrices of the partial contractions of
  * cores t+1..n-1) built in FP64; every decision is taken in FP64.
- * uniforms: device double [batch][R][y->n_max] in [0, 1) (the caller's random numbers;
- * train b reads the first n[b] of each row, U_t at position t); out: device int64
+ * uniforms: device double [batch][y->n_max][R] in [0, 1), bit-major (the caller's random
+ * numbers: U_t of shot s of train b at [b][t][s]; train b reads levels t < n[b]); out: device int64
  * [batch][R] outcome indices u in [0, 2^n[b]) (bit t of u is bit t of the outcome, the
  * log-strike index of cm_readout_prices); norm2: device double [batch] receives ||y_b||^2.
  * Bonds above 32 give CM_E_UNSUPPORTED for that instance, a zero train CM_E_INVALID, a

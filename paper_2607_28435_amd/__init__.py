@@ -350,7 +350,7 @@ def cm_readout_observable(y: TTBatch, prob_dev, strike_idx, nk: int, prices, sta
 
 
 def cm_sample_outcomes(y: TTBatch, uniforms, R: int, out, norm2, status, ws: Workspace, stream=None) -> int:
-    """uniforms: float64 [batch][R][y.n_max]; out: int64 [batch][R]; norm2: float64 [batch]."""
+    """uniforms: float64 [batch][y.n_max][R] (bit-major); out: int64 [batch][R]; norm2: float64 [batch]."""
     need = cm_workspace_bytes(CM_OP_SAMPLE, y.batch, y.struct.n_max, y.cap_rank, y.dtype)
     buf = ws.get(need)
     code = lib().cm_sample_outcomes(C.byref(y.struct), _ptr(uniforms), R, _ptr(out), _ptr(norm2), _ptr(status),

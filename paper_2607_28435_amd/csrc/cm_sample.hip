@@ -202,7 +202,8 @@ __global__ __launch_bounds__(SMP_WG) void k_sample(TTView y, const double2 *__re
     if (rmax <= RM || RM == SMP_RS) out[(int64_t)b * R + s] = -1;
     return;
   }
-  const double *U = uni + ((int64_t)b * R + s) * ustride;
+  // uniforms are bit-major, [batch][ustride][R]: level t of consecutive shots is contiguous
+  const double *U = uni + (int64_t)b * ustride * R + s;
   const double2 *Eg = ws + (int64_t)b * inst_stride;
   const double2 *Yg = Eg + (int64_t)(n_max + 1) * RS * RS;
   double2 v[RM], w[RM];
@@ -213,7 +214,7 @@ __global__ __launch_bounds__(SMP_WG) void k_sample(TTView y, const double2 *__re
   int64_t idx = 0;
   for (int t = 0; t < n; ++t) {
     const int pa = pad4(rk[t]), pb = pad4(rk[t + 1]);
-    const double ut = U[t];
+    const double ut = U[(int64_t)t * R];
     const double2 *Y = Yg + (int64_t)t * 2 * RS * RS;
     const double2 *E = Eg + (int64_t)(t + 1) * RS * RS;
     row_times_core<RM>(v, Y, pa, pb, 0, w);

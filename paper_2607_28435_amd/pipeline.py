@@ -203,12 +203,12 @@ class SfftPricer:
 
     def measure(self, strikes, uniforms):
         """Emulated QFT measurement: builds the output trains, draws R outcomes per
-        instance with the caller's uniforms (device float64 [batch, R, n_max]) and prices
+        instance with the caller's uniforms (device float64 [batch, n_max, R], bit-major) and prices
         the strikes (device int64 [batch, nk], strictly increasing per row) from the
         outcome counts. Returns (prices float64 [batch, nk], counts int32 [batch, nk],
         samples int64 [batch, R], norm2 float64 [batch]), all in the caller's order."""
         torch = _torch()
-        R = int(uniforms.shape[1])
+        R = int(uniforms.shape[2])
         dev = strikes.device
         s_int = self.to_internal(strikes)
         u_int = self.to_internal(uniforms)

@@ -105,12 +105,17 @@ def _random_trains(ns, rmax, dtype, cap, seed):
     return tt, host
 
 
+def _bit_major(U):
+    """[batch, R, n] (the oracle's row per shot) -> [batch, n, R] (the library's layout)."""
+    return np.ascontiguousarray(np.transpose(U, (0, 2, 1)))
+
+
 def _sample(tt, U):
     batch, R = U.shape[0], U.shape[1]
     out = torch.empty((batch, R), dtype=torch.int64, device="cuda")
     norm2 = torch.empty(batch, dtype=torch.float64, device="cuda")
     st = torch.zeros(batch, dtype=torch.int32, device="cuda")
-    cm.cm_sample_outcomes(tt, _dev(U), R, out, norm2, st, cm.Workspace())
+    cm.cm_sample_outcomes(tt, _dev(_bit_major(U)), R, out, norm2, st, cm.Workspace())
     torch.cuda.synchronize()
     return out.cpu().numpy(), norm2.cpu().numpy(), st.cpu().numpy()
 
@@ -238,7 +243,7 @@ def test_measure_fp64_bs_n10_matches_oracle_outcomes_and_prices():
     R = 4096
     U = _uniforms(1, R, p.n, seed=21)
     pr = cm.SfftPricer([p], cm.CM_C128, tol=1e-12, cap=32)
-    prices, counts, samples, norm2 = (t.cpu().numpy() for t in pr.measure(_dev(u[None]), _dev(U)))
+    prices, counts, samples, norm2 = (t.cpu().numpy() for t in pr.measure(_dev(u[None]), _dev(_bit_major(U))))
     st = pr.statuses()
     assert all(v[0] == cm.CM_OK for v in st.values()), st
     prob, nx2 = O.qft_probabilities(p)
@@ -264,7 +269,7 @@ def test_measure_c64_heston_n24_batch():
     idx = np.stack([W.near_money(p, 1024) for p in probs])
     idx.sort(axis=1)
     pr = cm.SfftPricer(probs, cm.CM_C64, tol=1e-6, cap=32)
-    prices, counts, samples, norm2 = (t.cpu().numpy() for t in pr.measure(_dev(idx), _dev(U)))
+    prices, counts, samples, norm2 = (t.cpu().numpy() for t in pr.measure(_dev(idx), _dev(_bit_major(U))))
     st = pr.statuses()
     assert all(np.all(v == cm.CM_OK) for v in st.values()), st
     for b, p in enumerate(probs):
