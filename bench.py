@@ -50,10 +50,11 @@ def parse():
     ap.add_argument("--no-vg", action="store_true")
     ap.add_argument("--no-qft", action="store_true")
     ap.add_argument("--no-mpo-table", action="store_true")
-    ap.add_argument("--default-slots", action="store_true", help="skip the slot autotuner (library default: "
-                    "min(batch, 2048) persistent workgroups per sweep op)")
-    ap.add_argument("--slots", type=int, nargs=3, metavar=("BUILD", "APPLY", "ROUND"), default=None,
-                    help="fixed persistent-workgroup counts instead of the autotuner (for profiling runs)")
+    ap.add_argument("--slots", type=int, nargs=3, metavar=("BUILD", "APPLY", "ROUND"), default=[4096, 1536, 4096],
+                    help="persistent-workgroup counts of the three sweep ops (default: what autotune_slots picks "
+                         "for this workload on MI355X, and the counts the committed profiles were taken with)")
+    ap.add_argument("--autotune", action="store_true", help="time the candidate slot counts first and use the best")
+    ap.add_argument("--default-slots", action="store_true", help="library default slot counts (min(batch, 2048))")
     ap.add_argument("--shots", type=int, default=4096, help="measurement shots per instance in the QFT-observable "
                     "section (the paper's hardware default)")
     ap.add_argument("--no-surrogate", action="store_true")
@@ -280,7 +281,9 @@ def qft_run(cm, torch, pr, strikes, shots, steps):
             "shots_per_s": batch * shots / (sample_ms * 1e-3),
             "sample_ms": sample_ms, "shot_price_ms": shot_ms, "exact_observable_readout_ms": exact_ms,
             "sampler_roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_TFLOPS,
-                                 "unit": "TFLOP/s (FP64 vector)", "frac": achieved / FP64_VECTOR_TFLOPS},
+                                 "unit": "TFLOP/s (FP64 vector)", "frac": achieved / FP64_VECTOR_TFLOPS,
+                                 "traffic": profiled_traffic("k_sample", SAMPLE_SOURCES),
+                                 "traffic_per": PROFILED_TRAFFIC["k_sample"]["per"]},
             "shots_on_readout_strikes_frac": float(cn.sum() / (batch * shots)),
             "shot_vs_exact_observable_nrmse_mean": float(nrmse.mean()),
             "shot_vs_exact_observable_nrmse_max": float(nrmse.max()),
@@ -387,11 +390,14 @@ ZIPUP_SOURCES = ["paper_2607_28435_amd/csrc/cm_zipup.hip", "paper_2607_28435_amd
 FFT_SOURCES = ["paper_2607_28435_amd/csrc/cm_fft.hip", "paper_2607_28435_amd/csrc/cm_cf.h",
                "paper_2607_28435_amd/csrc/cm_tt.h", "paper_2607_28435_amd/csrc/cm_linalg.h",
                "paper_2607_28435_amd/csrc/cm_internal.h", "include/cm.h"]
+SAMPLE_SOURCES = ["paper_2607_28435_amd/csrc/cm_sample.hip", "paper_2607_28435_amd/csrc/cm_internal.h", "include/cm.h"]
 PROFILED_TRAFFIC = {
-    "k_zipup": {"sha": "8884ced817093bd5", "bytes": (902532.0 * 2.0 + 1010375.9) * 1024,
-                "per": "launch (4096 instances, n=24)"},
-    "dense": {"sha": "595b5903c5538b60", "bytes": ((142.3 + 65640.8) * 2.0 + 131072.0 + 65536.0) * 1024,
+    "k_zipup": {"sha": "5a5228570fb8f9a1", "bytes": (990888.6 * 2.0 + 1006492.6) * 1024,
+                "per": "launch (4096 instances, n=24, 1536 workgroups)"},
+    "dense": {"sha": "8f2633ef05b9120e", "bytes": ((151.7 + 65640.5) * 2.0 + 131072.0 + 65536.0) * 1024,
               "per": "grid (k_fft_first + k_fft_next, n=24)"},
+    "k_sample": {"sha": "5b8efa3dc949c431", "bytes": (3780885.1 * 2.0 + 131072.0) * 1024,
+                 "per": "launch (4096 instances x 4096 shots, n=24)"},
 }
 
 
@@ -491,11 +497,11 @@ def main():
     pr = cm.SfftPricer(probs, cm.CM_C64, tol=1e-8, cap=32, mpo=mpo)
     # persistent-workgroup counts of the three sweep ops, timed on this batch (untimed)
     slots = {k: None for k in ("build", "apply", "round")}
-    if args.slots:
+    if args.autotune:
+        slots = cm.autotune_slots(pr, strikes, candidates=SLOT_CANDIDATES, reps=2)
+    elif not args.default_slots:
         slots = dict(zip(("build", "apply", "round"), args.slots))
         pr.slots.update(slots)
-    elif not args.default_slots:
-        slots = cm.autotune_slots(pr, strikes, candidates=SLOT_CANDIDATES, reps=2)
 
     ev = {k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for k in ("build", "apply", "round", "read")}
