@@ -339,3 +339,32 @@ def test_shot_prices_error_rows():
     pz = prices.cpu().numpy()
     assert np.all(np.isfinite(pz[0])) and np.isnan(pz[1]).any()
     assert counts.cpu().numpy()[0, 4] == R
+
+
+def test_measure_ragged_batch_caller_order():
+    """A ragged batch (n = 9, 12, 7, 12, 10; processed longest chain first inside the
+    pricer) through the full observable arm: prices, counts, outcomes and ||y||^2 come back
+    in the caller's order, each instance's outcomes equal to the oracle sampler's on its own
+    probabilities and its observable prices equal to the oracle's."""
+    say("measure ragged")
+    base = W.bs_rect_n12()
+    ns = [9, 12, 7, 12, 10]
+    probs = [base.replace(n=n, eta=W.eta_rule(n), params=(0.2 + 0.02 * i,)) for i, n in enumerate(ns)]
+    R, nk = 2048, 64
+    U = _uniforms(len(ns), R, max(ns), seed=77)
+    strikes = np.stack([W.near_money(p, nk) for p in probs])
+    pr = cm.SfftPricer(probs, cm.CM_C128, tol=1e-12, cap=32)
+    assert not pr.identity
+    prices, counts, samples, norm2 = (t.cpu().numpy() for t in pr.measure(_dev(strikes), _dev(_bit_major(U))))
+    obs = pr.observable(_dev(strikes)).cpu().numpy()
+    st = pr.statuses()
+    assert all(np.all(v == cm.CM_OK) for v in st.values()), st
+    for b, p in enumerate(probs):
+        prob, nx2 = O.qft_probabilities(p)
+        assert abs(norm2[b] - nx2) <= 1e-9 * nx2, b
+        ref, nbad = _check_samples(prob, U[b, :, :p.n], samples[b], margin_tol=1e-8, max_frac=0.0)
+        if nbad == 0:
+            want_c = np.bincount(ref, minlength=2 ** p.n)[strikes[b]]
+            assert np.array_equal(counts[b], want_c), b
+            assert np.allclose(prices[b], O.prices_from_counts(p, strikes[b], want_c, R, nx2), rtol=1e-9, atol=1e-12)
+        assert np.abs(obs[b] - O.qft_observable_prices(p, strikes[b])).max() / p.S0 < FP64_TOL
