@@ -48,6 +48,13 @@ __global__ __launch_bounds__(SMP_WG) void k_envs(TTView y, int RS, int n_max, in
   const int tid = threadIdx.x;
   const int b = blockIdx.x;
   const int n = y.n[b];
+  if (n < 0 || n > n_max) {   // the slab holds n_max levels
+    if (tid == 0) {
+      norm2[b] = NAN;
+      set_status(status, b, CM_E_INVALID);
+    }
+    return;
+  }
   const int32_t *rk = y.rk(b);
   if (max_bond_of(rk, n) > RS) {
     if (tid == 0) {
@@ -190,12 +197,16 @@ __global__ __launch_bounds__(SMP_WG) void k_sample(TTView y, const double2 *__re
   const int tid = threadIdx.x;
   const int b = blockIdx.y;
   const int n = y.n[b];
+  const int s = blockIdx.x * SMP_WG + tid;
+  if (n < 0 || n > n_max) {   // k_envs has set CM_E_INVALID
+    if (rm_lo == 0 && s < R) out[(int64_t)b * R + s] = -1;   // the always-launched bound marks it
+    return;
+  }
   const int32_t *rk = y.rk(b);
   // this instantiation serves instances whose largest bond lies in (rm_lo, RM]; the widest
   // one also writes -1 for instances above every bound
   const int rmax = max_bond_of(rk, n);
   if (rmax <= rm_lo) return;
-  const int s = blockIdx.x * SMP_WG + tid;
   if (s >= R) return;
   const double q_all = norm2[b];
   if (rmax > RM || !(q_all > 0.0) || !isfinite(q_all)) {

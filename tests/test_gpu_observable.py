@@ -368,3 +368,18 @@ def test_measure_ragged_batch_caller_order():
             assert np.array_equal(counts[b], want_c), b
             assert np.allclose(prices[b], O.prices_from_counts(p, strikes[b], want_c, R, nx2), rtol=1e-9, atol=1e-12)
         assert np.abs(obs[b] - O.qft_observable_prices(p, strikes[b])).max() / p.S0 < FP64_TOL
+
+
+def test_sampler_rejects_chain_longer_than_n_max():
+    """A train whose device-side length exceeds the batch's n_max (the workspace holds n_max
+    levels) gets CM_E_INVALID and outcomes -1 without being read; its neighbour samples."""
+    say("sampler n > n_max")
+    tt, host = _random_trains([8, 5], 4, cm.CM_C128, 8, seed=21)
+    tt.struct.n_max = 6
+    R = 300
+    U = _uniforms(2, R, 6, seed=4)
+    got, norm2, st = _sample(tt, U)
+    assert st[0] == cm.CM_E_INVALID and st[1] == cm.CM_OK, st
+    assert np.all(got[0] == -1) and np.isnan(norm2[0])
+    prob, _ = _probs_of_output_train(host[1])
+    _check_samples(prob, U[1, :, :5], got[1], margin_tol=1e-10, max_frac=0.0)
