@@ -392,11 +392,11 @@ FFT_SOURCES = ["paper_2607_28435_amd/csrc/cm_fft.hip", "paper_2607_28435_amd/csr
                "paper_2607_28435_amd/csrc/cm_internal.h", "include/cm.h"]
 SAMPLE_SOURCES = ["paper_2607_28435_amd/csrc/cm_sample.hip", "paper_2607_28435_amd/csrc/cm_internal.h", "include/cm.h"]
 PROFILED_TRAFFIC = {
-    "k_zipup": {"sha": "5a5228570fb8f9a1", "bytes": (990888.6 * 2.0 + 1006492.6) * 1024,
+    "k_zipup": {"sha": "b46cb358d81bc64c", "bytes": (996901.8 * 2.0 + 1006544.4) * 1024,
                 "per": "launch (4096 instances, n=24, 1536 workgroups)"},
     "dense": {"sha": "8f2633ef05b9120e", "bytes": ((151.7 + 65640.5) * 2.0 + 131072.0 + 65536.0) * 1024,
               "per": "grid (k_fft_first + k_fft_next, n=24)"},
-    "k_sample": {"sha": "5b8efa3dc949c431", "bytes": (3780885.1 * 2.0 + 131072.0) * 1024,
+    "k_sample": {"sha": "fc851dbe9b56783f", "bytes": (3780892.0 * 2.0 + 131072.0) * 1024,
                  "per": "launch (4096 instances x 4096 shots, n=24)"},
 }
 

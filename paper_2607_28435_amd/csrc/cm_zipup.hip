@@ -535,7 +535,7 @@ __device__ __forceinline__ int zip_site_pair(char *arena, const SiteDims &sd, co
 }  // namespace
 
 template <typename T>
-__global__ __launch_bounds__(CM_WG, 3) void k_zipup(TTView w, TTView x, TTView y, double tol, int cap,
+__global__ __launch_bounds__(CM_WG, 3) void k_zipup(TTView w, int w_slots, TTView x, TTView y, double tol, int cap,
                                                  int batch, int32_t *__restrict__ status,
                                                  char *__restrict__ ws, size_t slab_bytes, int64_t mat_cap) {
   extern __shared__ __align__(16) char lds_arena[];
@@ -558,7 +558,8 @@ __global__ __launch_bounds__(CM_WG, 3) void k_zipup(TTView w, TTView x, TTView y
     const int n = x.n[b];
     if (tid == 0) {
       int c = CM_OK;
-      if (n < 1 || n > CM_MAX_N || y.n[b] != n || w.n[n] != n) c = CM_E_INVALID;
+      // operator n is train n of w (w_slots trains)
+      if (n < 1 || n > CM_MAX_N || n >= w_slots || y.n[b] != n || w.n[n] != n) c = CM_E_INVALID;
       code_sh = c;
     }
     __syncthreads();
@@ -646,11 +647,11 @@ extern "C" cm_status cm_sfft_apply(const cm_tt_batch *w_by_n, const cm_tt_batch 
   CM_HIP_CHECK(cm_allow_lds(k_zipup<float2>, zlds_bytes<float2>()));
   CM_HIP_CHECK(cm_allow_lds(k_zipup<double2>, zlds_bytes<double2>()));
   if (x->dtype == CM_C64)
-    hipLaunchKernelGGL(k_zipup<float2>, dim3(slots), dim3(CM_WG), zlds_bytes<float2>(), s, vw, vx, vy, tol, cap_rank,
-                       batch, status, (char *)ws, slab, mc);
+    hipLaunchKernelGGL(k_zipup<float2>, dim3(slots), dim3(CM_WG), zlds_bytes<float2>(), s, vw, w_by_n->batch, vx, vy,
+                       tol, cap_rank, batch, status, (char *)ws, slab, mc);
   else
-    hipLaunchKernelGGL(k_zipup<double2>, dim3(slots), dim3(CM_WG), zlds_bytes<double2>(), s, vw, vx, vy, tol,
-                       cap_rank, batch, status, (char *)ws, slab, mc);
+    hipLaunchKernelGGL(k_zipup<double2>, dim3(slots), dim3(CM_WG), zlds_bytes<double2>(), s, vw, w_by_n->batch, vx,
+                       vy, tol, cap_rank, batch, status, (char *)ws, slab, mc);
   CM_LAUNCH_CHECK();
   y->flags = CM_TT_LEFT_ORTHO;
   return CM_OK;
