@@ -494,6 +494,55 @@ __global__ __launch_bounds__(64) void k_fft_prepare(const cm_problem *__restrict
   }
 }
 
+// Pass 1, from stage S + 1 on. With the support of x starting at 0, the work item's inputs
+// e >= E are zero. If E <= L / R^S (R the register radix), each of the first S stages sees at
+// most one non-zero input per butterfly, its first, which no twiddle touches; the radix-R
+// DFT of such a vector is that input repeated. So after S stages the array is
+// y[m] = x_e with e = m >> (S log2 R) for m < R^S E, and zero beyond. It is written directly
+// (one evaluation of x per e) and the transform continues with the remaining stages.
+template <typename T, int LOGR, int S, class Dst>
+__device__ __forceinline__ void first_pass_from(T *a, const DenseProb<T> &d, int64_t item, int64_t T_items, int64_t E,
+                                                const Dst &dst) {
+  constexpr int RB = pts_per_thread<T> >= 16 ? 4 : 3;
+  constexpr int SB = S * RB;
+  if constexpr (S == 0) {
+    for (int e = threadIdx.x; e < (1 << LOGR); e += NT) a[pidx(e)] = integrand_at<T>(d, item + (int64_t)e * T_items);
+  } else {
+    const T zero = fr<T>::mk(0.0, 0.0);
+    for (int e = threadIdx.x; e < E; e += NT) a[pidx(e << SB)] = integrand_at<T>(d, item + (int64_t)e * T_items);
+    __syncthreads();
+    for (int m = threadIdx.x; m < (1 << LOGR); m += NT) {
+      const int e = m >> SB;
+      if (e >= E) a[pidx(m)] = zero;
+      else if (m & ((1 << SB) - 1)) a[pidx(m)] = a[pidx(e << SB)];
+    }
+  }
+  __syncthreads();
+  fft_block<T, LOGR, SB, true>(a, 0, 0, NoSrc{}, dst);
+}
+
+template <typename T, int LOGR, class Dst>
+__device__ __forceinline__ void first_pass(T *a, const DenseProb<T> &d, int64_t item, int64_t T_items, const Dst &dst) {
+  constexpr int RB = pts_per_thread<T> >= 16 ? 4 : 3;
+  constexpr int MAXS = (LOGR - 1) / RB;   // keep at least one stage
+  int S = 0;
+  int64_t E = 0;
+  if (d.jlo == 0) {
+    E = (d.jhi + T_items - 1) / T_items;
+    while (S < MAXS && E <= ((int64_t)1 << (LOGR - (S + 1) * RB))) ++S;
+  }
+  if constexpr (MAXS >= 3) {
+    if (S == 3) { first_pass_from<T, LOGR, 3>(a, d, item, T_items, E, dst); return; }
+  }
+  if constexpr (MAXS >= 2) {
+    if (S == 2) { first_pass_from<T, LOGR, 2>(a, d, item, T_items, E, dst); return; }
+  }
+  if constexpr (MAXS >= 1) {
+    if (S == 1) { first_pass_from<T, LOGR, 1>(a, d, item, T_items, E, dst); return; }
+  }
+  first_pass_from<T, LOGR, 0>(a, d, item, T_items, E, dst);
+}
+
 // Pass 1: one work item (blockIdx.x) per workgroup; x is generated into LDS (only lanes
 // inside the support evaluate the characteristic function), then transformed.
 template <typename T, int LOGR>
@@ -505,14 +554,12 @@ __global__ __launch_bounds__(NT) void k_fft_first(const DenseProb<T> *__restrict
   const int64_t M = (int64_t)1 << n;
   const DenseProb<T> *d = dprob + inst0 + blockIdx.y;
   const int64_t item = blockIdx.x, T_items = M >> LOGR;
-  for (int e = threadIdx.x; e < (1 << LOGR); e += NT) a[pidx(e)] = integrand_at<T>(*d, item + (int64_t)e * T_items);
-  __syncthreads();
   if (single) {
     PriceDst<T> dst{prices + (int64_t)blockIdx.y * M, &d->c, item, 1, LOGR, d->bad};
-    fft_block<T, LOGR, 0, true>(a, 0, 0, NoSrc{}, dst);
+    first_pass<T, LOGR>(a, *d, item, T_items, dst);
   } else {
     BufDst<T> dst{out + (int64_t)blockIdx.y * M, item, 1, LOGR};
-    fft_block<T, LOGR, 0, true>(a, 0, 0, NoSrc{}, dst);
+    first_pass<T, LOGR>(a, *d, item, T_items, dst);
   }
 }
 

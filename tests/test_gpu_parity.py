@@ -200,6 +200,34 @@ def test_dense_fft_fp64_sizes(n):
     assert np.all(err <= bound), (err / bound).max()
 
 
+@pytest.mark.parametrize("dtype,n,eta", [(cm.CM_C128, 16, 2.0), (cm.CM_C128, 16, 0.25), (cm.CM_C128, 16, 0.05),
+                                         (cm.CM_C128, 16, 0.002), (cm.CM_C64, 20, 0.1), (cm.CM_C64, 20, 0.01),
+                                         (cm.CM_C64, 20, 0.0005)])
+def test_dense_pruned_first_stages(dtype, n, eta):
+    """Simpson rule (support of x starting at 0): from coarse to fine eta the support's share
+    of each pass-1 work item crosses the thresholds at which the first three, two, one or no
+    Stockham stages are written directly instead of computed (a single non-zero input per
+    butterfly is only repeated). Every case matches the oracle: within the FP64 rounding
+    bound on all strikes (complex128), within 1e-4 S0 on 0.5 <= K/S0 <= 1.5 (complex64)."""
+    say("dense pruned", dtype, n, eta)
+    p = W.bs_simpson_n12().replace(n=n, eta=eta)
+    got, st = cm.dense_prices([p], dtype)
+    assert st.cpu().numpy()[0] == cm.CM_OK
+    got = got.double().cpu().numpy()[0]
+    ref = O.prices_dense(p)
+    err = np.abs(got - ref)
+    if dtype == cm.CM_C128:
+        # strikes where exp(-alpha k) overflows carry no price on either side
+        bound = _dft_roundoff_bound(p) + 1e-12 * p.S0
+        ok = np.isfinite(bound) & np.isfinite(ref)
+        assert ok.sum() > 2 ** (n - 1) and np.all(np.isfinite(got[ok]))
+        assert np.all(err[ok] <= bound[ok]), (err[ok] / bound[ok]).max()
+    else:
+        K = O.strike_of(p, np.arange(2 ** n))
+        win = (K >= 50.0) & (K <= 150.0)
+        assert win.sum() > 0 and err[win].max() / p.S0 < C64_TOL, err[win].max()
+
+
 def test_paper_grid_statevector_pin_through_gpu():
     """The paper's grid (Section 4) priced on the GPU dense path reproduces the oracle's
     FFT NRMSE floor order (~1e-15) at n = 14."""
