@@ -367,20 +367,21 @@ __device__ __forceinline__ T integrand_at(const DenseProb<T> &d, int64_t j) {
 
 // C(k_u) = Re[e^{-alpha k_u}/(s pi) ro (+-1)^u y_u]; the scale is 2^{z0 + dz u} with the
 // exponent kept in FP64.
-__device__ __forceinline__ float price_at(const DenseConst &c, int64_t u, float2 y, bool bad) {
+// z = z0 + dz u, the log2 of the scale, is passed in: the last pass forms it for its R
+// outputs from the first one by adding multiples of dz times the output stride.
+__device__ __forceinline__ float price_at(const DenseConst &c, int64_t u, double z, float2 y, bool bad) {
   if (bad) return NAN;
-  const double z = fma(c.dz, (double)u, c.z0);
   const double zi = floor(z);
   float rx = (float)c.ro.x, ry = (float)c.ro.y;
   if (c.alt && (u & 1)) { rx = -rx; ry = -ry; }
   const float re = rx * y.x - ry * y.y;
   return ldexpf(re * exp2f((float)(z - zi)), (int)zi);
 }
-__device__ __forceinline__ double price_at(const DenseConst &c, int64_t u, double2 y, bool bad) {
+__device__ __forceinline__ double price_at(const DenseConst &c, int64_t u, double z, double2 y, bool bad) {
   if (bad) return NAN;
   double2 ro = c.ro;
   if (c.alt && (u & 1)) ro = cmk(-ro.x, -ro.y);
-  return exp2(fma(c.dz, (double)u, c.z0)) * (ro.x * y.x - ro.y * y.y);
+  return exp2(z) * (ro.x * y.x - ro.y * y.y);
 }
 
 // Sources and sinks of a pass. Work item of column col is item0 + col; a pass with radix R
@@ -430,10 +431,12 @@ template <typename T> struct PriceDst {   // last pass: readout scalars, prices
     const int64_t item = item0 + col;
     const int64_t k = item & (plen - 1);
     const int64_t b = ((item - k) << logR) + k;
+    const int64_t u0 = b + (int64_t)q0 * plen, du = (int64_t)dq * plen;
+    const double z0 = fma(c->dz, (double)u0, c->z0), dz = c->dz * (double)du;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const int64_t u = b + (int64_t)(q0 + r * dq) * plen;
-      prices[u] = price_at(*c, u, v[r], bad != 0);
+      const int64_t u = u0 + r * du;
+      prices[u] = price_at(*c, u, fma((double)r, dz, z0), v[r], bad != 0);
     }
   }
 };
