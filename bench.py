@@ -392,11 +392,11 @@ FFT_SOURCES = ["paper_2607_28435_amd/csrc/cm_fft.hip", "paper_2607_28435_amd/csr
                "paper_2607_28435_amd/csrc/cm_internal.h", "include/cm.h"]
 SAMPLE_SOURCES = ["paper_2607_28435_amd/csrc/cm_sample.hip", "paper_2607_28435_amd/csrc/cm_internal.h", "include/cm.h"]
 PROFILED_TRAFFIC = {
-    "k_zipup": {"sha": "b46cb358d81bc64c", "bytes": (996901.8 * 2.0 + 1006544.4) * 1024,
+    "k_zipup": {"sha": "b46cb358d81bc64c", "bytes": (996898.8 * 2.0 + 1006205.4) * 1024,
                 "per": "launch (4096 instances, n=24, 1536 workgroups)"},
-    "dense": {"sha": "8f2633ef05b9120e", "bytes": ((151.7 + 65640.5) * 2.0 + 131072.0 + 65536.0) * 1024,
+    "dense": {"sha": "669353a82288c8a3", "bytes": ((156.2 + 65630.0) * 2.0 + 131075.2 + 65536.0) * 1024,
               "per": "grid (k_fft_first + k_fft_next, n=24)"},
-    "k_sample": {"sha": "fc851dbe9b56783f", "bytes": (3780892.0 * 2.0 + 131072.0) * 1024,
+    "k_sample": {"sha": "fc851dbe9b56783f", "bytes": (3780884.4 * 2.0 + 131072.0) * 1024,
                  "per": "launch (4096 instances x 4096 shots, n=24)"},
 }
 
@@ -556,6 +556,30 @@ def main():
     stat = pr.statuses()
     bad = {k: int((v != 0).sum()) for k, v in stat.items()}
 
+    # dense baseline on a subset of the same problems (all 2^n prices per instance), timed right
+    # after the SFFT chain so that both run under the same conditions
+    nd = min(args.dense_instances, args.batch)
+    dprob = cm.pack_problems(probs[:nd], dev)
+    dprices = torch.empty((nd, 2 ** args.n), dtype=torch.float32, device=dev)
+    dstat = torch.zeros(nd, dtype=torch.int32, device=dev)
+    dws = cm.Workspace(dev)
+    cm.cm_fft_price(dprob, nd, args.n, cm.CM_C64, None, 0, dprices, dstat, dws)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 4
+    e0.record(stream)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        cm.cm_fft_price(dprob, nd, args.n, cm.CM_C64, None, 0, dprices, dstat, dws)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    dense_s = (time.perf_counter() - t0) / (reps * nd)
+    dense_ms_ev = e0.elapsed_time(e1) / (reps * nd)
+    dense_gps = 1.0 / dense_s
+    M = 2 ** args.n
+    dense_bytes = 8 * M + (8 * M + 4 * M) if args.n > 14 else 4 * M   # pass-1 write, pass-2 read + price write
+    dense_gbs = dense_bytes / (dense_ms_ev * 1e-3) / 1e9
+
     mpo_table = None
     if not args.no_mpo_table:
         mpo_table = mpo_table_run(cm, torch)
@@ -591,29 +615,6 @@ def main():
     surrogate = None
     if not args.no_surrogate:
         surrogate = surrogate_run(cm, torch, args.surrogate_steps)
-
-    # dense baseline on a subset of the same problems (all 2^n prices per instance)
-    nd = min(args.dense_instances, args.batch)
-    dprob = cm.pack_problems(probs[:nd], dev)
-    dprices = torch.empty((nd, 2 ** args.n), dtype=torch.float32, device=dev)
-    dstat = torch.zeros(nd, dtype=torch.int32, device=dev)
-    dws = cm.Workspace(dev)
-    cm.cm_fft_price(dprob, nd, args.n, cm.CM_C64, None, 0, dprices, dstat, dws)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    reps = 2
-    e0.record(stream)
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        cm.cm_fft_price(dprob, nd, args.n, cm.CM_C64, None, 0, dprices, dstat, dws)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    dense_s = (time.perf_counter() - t0) / (reps * nd)
-    dense_ms_ev = e0.elapsed_time(e1) / (reps * nd)
-    dense_gps = 1.0 / dense_s
-    M = 2 ** args.n
-    dense_bytes = 8 * M + (8 * M + 4 * M) if args.n > 14 else 4 * M   # pass-1 write, pass-2 read + price write
-    dense_gbs = dense_bytes / (dense_ms_ev * 1e-3) / 1e9
 
     # price errors are taken against the oracle prices of the cpu_baseline leg (below)
     max_err = None
