@@ -418,7 +418,7 @@ def profiled_traffic(name, files):
 def surrogate_run(cm, torch, steps):
     """Surrogate (config 5): train on 2^22 SFFT samples (2^16 parameter sets x 64 k, training
     box 20 % wider than the trusted box), then 2^20 held-out queries (90 % in the trusted
-    box, 10 % from a box enlarged by 20 %): gated prices vs the SFFT judge, accept rate, and
+    box, 10 % from a box enlarged by 20 %): gated prices vs the SFFT reference, accept rate, and
     network+gate throughput against batched SFFT pricing of the same queries."""
     from paper_2607_28435_amd.surrogate import Surrogate
     lo, hi = W.surrogate_box()
@@ -432,13 +432,13 @@ def surrogate_run(cm, torch, steps):
     q = np.concatenate([W.surrogate_queries(nq - nq // 10, 5001), W.surrogate_queries(nq // 10, 5002, enlarge=0.2)])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    judge, st = s.query_prices(q)
+    ref_prices, st = s.query_prices(q)
     torch.cuda.synchronize()
     sfft_s = time.perf_counter() - t0
     res = s.price(q)
     acc = res["accept"]
     ok = acc & (st == 0)
-    err = np.abs(res["price"] - judge)
+    err = np.abs(res["price"] - ref_prices)
     # network + gate throughput on all queries (device-resident inputs)
     qd = torch.from_numpy(q.astype(np.float32)).cuda()
     s.predict(qd)
@@ -458,7 +458,7 @@ def surrogate_run(cm, torch, steps):
             "data_gen_s": gen_s, "final_train_loss": info["final_loss"],
             "eval_queries": nq, "accept_rate": float(acc.mean()), "in_box_accept_rate": float(acc[:nq - nq // 10].mean()),
             "in_gate_max_abs_err_over_S0": float(err[ok].max()), "in_gate_p999_abs_err_over_S0":
-                float(np.quantile(err[ok], 0.999)), "judge_failures": int((st != 0).sum()),
+                float(np.quantile(err[ok], 0.999)), "sfft_reference_failures": int((st != 0).sum()),
             "queries_per_s": nq / net_s, "sfft_queries_per_s": nq / sfft_s, "speedup_vs_sfft": sfft_s / net_s,
             "roofline": {"kernel": "k_mlp_in + 3x k_gemm_ws + k_mlp_out + k_gate", "bound": "mfma",
                          "achieved": ach, "peak": BF16_DENSE_TFLOPS, "unit": "TFLOP/s",
@@ -468,7 +468,7 @@ def surrogate_run(cm, torch, steps):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "bench.py runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
     import torch
     import paper_2607_28435_amd as cm

@@ -45,7 +45,7 @@ typedef enum {
   CM_E_NOCONV = 4,       /* an iteration (Jacobi sweeps, QTT refinement) did not converge */
   CM_E_NONFINITE = 5,    /* NaN or Inf met in the data */
   CM_E_HIP = 6,          /* a HIP runtime call failed */
-  CM_E_UNSUPPORTED = 7,  /* valid request outside what this build supports (e.g. n too large for a path) */
+  CM_E_UNSUPPORTED = 7,  /* valid request outside what this library supports (e.g. n too large for a path) */
 } cm_status;
 
 /* CM_VG: Variance Gamma, the log-price a Brownian motion with drift run on an independent

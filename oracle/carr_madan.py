@@ -23,7 +23,7 @@ tensor trains and no blocking:
     error measure (Eq. error_measure);
   * the dense operator Q_n of Section 3.2 (the QFT circuit without its bit reversal).
 
-Conventions (readings of the paper, listed in the design doc): M = 2^n, lambda = 2 pi/(M eta),
+Conventions (readings of the paper): M = 2^n, lambda = 2 pi/(M eta),
 k_u = k0 + lambda u, v_j = v0 + j eta with v0 = -M eta/2 (rectangle) or 0 (Simpson);
 x_j = w_j psi(v_j) exp(-i j eta k0); y = M^(-1/2) DFT_-(x);
 C(k_u) = Re[ exp(-alpha k_u)/(s pi) * exp(-i v0 k_u) * sqrt(M) * y_u ], s = 2 (rectangle)

@@ -1,7 +1,7 @@
 """Pricing surrogate: a multilayer perceptron from (kappa, theta, sigma_v, rho, v0, T, k) to
 C/S0 (k = ln(K/S0)), trained on batched SFFT prices by the library's own forward, backward
 and Adam kernels, and gated by its training box plus a no-arbitrage residual, with the
-SFFT path as fallback and as the judge of its error. A project addition: the paper has no
+SFFT path as fallback and as the reference for its error. A project addition: the paper has no
 learned component.
 
 Marshalling and orchestration only: data generation is cm_build_qtt .. cm_readout_prices,
@@ -132,7 +132,7 @@ def widen(lo, hi, frac: float) -> Tuple[np.ndarray, np.ndarray]:
 class Surrogate:
     """Gated surrogate over the trusted box [lo, hi] of (kappa, theta, sigma_v, rho, v0, T, k),
     k = ln(K/S0), for S0 and r fixed; SFFT prices (Simpson rule, n-point grids, alpha
-    damping, complex64 contraction, tolerance tol) train and judge it and price what the
+    damping, complex64 contraction, tolerance tol) train and check it and price what the
     gate rejects.
 
     The network is trained on a box `train_lo`/`train_hi` wider than the trusted one (by

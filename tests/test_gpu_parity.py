@@ -1,6 +1,6 @@
 """Parity of the HIP path (through the C ABI) with the CPU oracle.
 
-Tolerances (written here, derived in the design doc): FP64 paths <= 1e-6 S0 max abs price
+Tolerances: FP64 paths <= 1e-6 S0 max abs price
 error, complex64 paths <= 1e-4 S0, on the strike sets named in each test."""
 import math
 import sys

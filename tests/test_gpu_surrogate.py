@@ -191,7 +191,7 @@ def test_query_prices_shifted_grid_vs_oracle():
 
 def test_surrogate_trains_gates_and_beats_sfft():
     """A short training run on SFFT prices: the loss falls by 50x, in-box held-out
-    queries land within 2e-2 S0 of the SFFT judge (a short run; the full-size training
+    queries land within 2e-2 S0 of the SFFT reference (a short run; the full-size training
     and its 1e-3 target are measured by bench.py), out-of-box queries go to the fallback
     (whose prices are the SFFT's), and the network answers the same queries more than 10x
     faster than batched SFFT pricing of them."""
@@ -208,17 +208,17 @@ def test_surrogate_trains_gates_and_beats_sfft():
     outside = np.any((q_out < lo) | (q_out > hi), axis=1)
     q = np.concatenate([q_in, q_out[outside][:50]])
     res = s.price(q)
-    judge, st = s.query_prices(q)
+    ref_prices, st = s.query_prices(q)
     n_in = len(q_in)
     acc = res["accept"]
     assert acc[:n_in].mean() > 0.95
     assert not acc[n_in:].any()
     ok = acc & (st == cm.CM_OK)
-    err = np.abs(res["price"][ok] - judge[ok]).max()
+    err = np.abs(res["price"][ok] - ref_prices[ok]).max()
     say("  max err in gate", err, "accept rate", acc[:n_in].mean())
     assert err < 2e-2
     fb = (~acc) & (st == cm.CM_OK)
-    assert np.allclose(res["price"][fb], judge[fb], rtol=0, atol=1e-12)
+    assert np.allclose(res["price"][fb], ref_prices[fb], rtol=0, atol=1e-12)
     # speed: network vs batched SFFT on the same in-box queries
     qd = torch.from_numpy(q_in.astype(np.float32)).cuda()
     s.predict(qd)
