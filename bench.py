@@ -392,11 +392,11 @@ FFT_SOURCES = ["paper_2607_28435_amd/csrc/cm_fft.hip", "paper_2607_28435_amd/csr
                "paper_2607_28435_amd/csrc/cm_internal.h", "include/cm.h"]
 SAMPLE_SOURCES = ["paper_2607_28435_amd/csrc/cm_sample.hip", "paper_2607_28435_amd/csrc/cm_internal.h", "include/cm.h"]
 PROFILED_TRAFFIC = {
-    "k_zipup": {"sha": "b46cb358d81bc64c", "bytes": (996898.8 * 2.0 + 1006205.4) * 1024,
+    "k_zipup": {"sha": "deea597dd99177d6", "bytes": (996924.3 * 2.0 + 1006184.7) * 1024,
                 "per": "launch (4096 instances, n=24, 1536 workgroups)"},
-    "dense": {"sha": "669353a82288c8a3", "bytes": ((156.2 + 65630.0) * 2.0 + 131075.2 + 65536.0) * 1024,
+    "dense": {"sha": "c9d4c6c6155acbcc", "bytes": ((156.1 + 65630.0) * 2.0 + 131075.8 + 65536.0) * 1024,
               "per": "grid (k_fft_first + k_fft_next, n=24)"},
-    "k_sample": {"sha": "fc851dbe9b56783f", "bytes": (3780884.4 * 2.0 + 131072.0) * 1024,
+    "k_sample": {"sha": "766aaa9ffdc474f6", "bytes": (3780882.2 * 2.0 + 131072.0) * 1024,
                  "per": "launch (4096 instances x 4096 shots, n=24)"},
 }
 
