@@ -172,27 +172,34 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
 enum { W_NK = 0, W_KN = 1 };
 constexpr int WSP = NW + 8;   // LDS row pitch of Ws (bf16): 528 bytes, 16-byte aligned
 
+// Up to WS_TILES row tiles are in flight per workgroup: wave w computes columns
+// 64 (w % 4) .. +63 of tiles blockIdx.x + (w / 4 + WS_TILES i) gridDim.x, so the LDS copy of the
+// weights serves 4 WS_TILES waves (four per SIMD) on large batches, while small batches still
+// spread one tile per workgroup over the CUs.
+constexpr int WS_TILES = 4;
+constexpr int WS_THREADS = 256 * WS_TILES;
+
 template <int WL, int AF, int EPI>
-__global__ __launch_bounds__(256) void k_gemm_ws(const float *__restrict__ A, const uint16_t *__restrict__ W, int M,
-                                                 float *__restrict__ C, const float *__restrict__ bias,
-                                                 const float *__restrict__ Z) {
+__global__ __launch_bounds__(WS_THREADS) void k_gemm_ws(const float *__restrict__ A, const uint16_t *__restrict__ W,
+                                                        int M, float *__restrict__ C, const float *__restrict__ bias,
+                                                        const float *__restrict__ Z) {
   extern __shared__ __align__(16) uint16_t Ws[];   // [NW][WSP]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (WL == W_NK) {
-    for (int e = tid; e < NW * NW / 8; e += 256) {
+    for (int e = tid; e < NW * NW / 8; e += WS_THREADS) {
       const int n = e / (NW / 8), k8 = (e % (NW / 8)) * 8;
       *(uint4 *)&Ws[n * WSP + k8] = *(const uint4 *)&W[n * NW + k8];
     }
   } else {
-    for (int e = tid; e < NW * NW; e += 256) {
+    for (int e = tid; e < NW * NW; e += WS_THREADS) {
       const int k = e / NW, n = e % NW;
       Ws[n * WSP + k] = W[e];
     }
   }
   __syncthreads();
   const int ntiles = (M + 31) / 32;
-  const int col0 = wave * 64;
-  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+  const int col0 = (wave & 3) * 64;
+  for (int t = blockIdx.x + (wave >> 2) * gridDim.x; t < ntiles; t += gridDim.x * WS_TILES) {
     const int row = t * 32 + (lane & 31);
     const bool rok = row < M;
     f32x16 acc0, acc1;
@@ -405,7 +412,7 @@ extern "C" cm_status cm_mlp_sync_bf16(const cm_mlp *net, void *stream) {
   return CM_OK;
 }
 
-// persistent workgroups for the weight-stationary layers: one per CU (132 KB of LDS each)
+// persistent workgroups for the weight-stationary layers: at most one per CU (132 KB of LDS each)
 static int ws_grid(int M) {
   static int cus = 0;
   if (cus == 0) {
@@ -434,7 +441,7 @@ extern "C" cm_status cm_mlp_forward(const cm_mlp *net, const float *x, int B, fl
   hipLaunchKernelGGL(k_mlp_in, dim3(grid_for((int64_t)B * NW, 256)), dim3(256), 0, s, x, B, net->params, *net, Z[0]);
   CM_LAUNCH_CHECK();
   for (int l = 2; l <= 4; ++l) {
-    hipLaunchKernelGGL((k_gemm_ws<W_NK, F_SILU, E_BIAS_STORE>), dim3(ws_grid(B)), dim3(256), WS_LDS, s, Z[l - 2],
+    hipLaunchKernelGGL((k_gemm_ws<W_NK, F_SILU, E_BIAS_STORE>), dim3(ws_grid(B)), dim3(WS_THREADS), WS_LDS, s, Z[l - 2],
                        net->w_bf16 + (int64_t)(l - 2) * NW * NW, B, Z[l - 1], net->params + off_b(l),
                        (const float *)nullptr);
     CM_LAUNCH_CHECK();
@@ -480,7 +487,7 @@ extern "C" cm_status cm_mlp_backward(const cm_mlp *net, const float *x, const fl
     hipLaunchKernelGGL(k_colsum<F_NONE>, dim3(chunks), dim3(NW), 0, s, dl, (const float *)nullptr, B, rows_per,
                        grad + off_b(l));
     // delta_{l-1}[b][n] = (sum_k delta_l[b][k] W_l[k][n]) silu'(Z_{l-1}[b][n])
-    hipLaunchKernelGGL((k_gemm_ws<W_KN, F_NONE, E_DSILU_STORE>), dim3(ws_grid(B)), dim3(256), WS_LDS, s, dl,
+    hipLaunchKernelGGL((k_gemm_ws<W_KN, F_NONE, E_DSILU_STORE>), dim3(ws_grid(B)), dim3(WS_THREADS), WS_LDS, s, dl,
                        net->w_bf16 + (int64_t)(l - 2) * NW * NW, B, D[cur ^ 1], (const float *)nullptr, Z[l - 2]);
     CM_LAUNCH_CHECK();
     cur ^= 1;
