@@ -27,6 +27,12 @@ __host__ __device__ constexpr int off_b(int l) { return l == 2 ? 67584 : l == 3 
 static_assert(OFF_B5 + 1 == CM_MLP_NPARAMS, "parameter layout");
 
 __device__ __forceinline__ float silu_f(float z) { return z / (1.0f + expf(-z)); }
+// SiLU from the hardware exp2 and reciprocal (a few ulps): for the activation operand of the
+// layer GEMMs, whose hi + lo BF16 split keeps about 2^-16 of it anyway. Large |z| behave:
+// exp2 overflows to inf and the reciprocal to 0 (z -> -inf), or exp2 goes to 0 (z -> +inf).
+__device__ __forceinline__ float silu_fast(float z) {
+  return z * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.4426950408889634f * z));
+}
 __device__ __forceinline__ float silu_grad_f(float z) {
   const float s = 1.0f / (1.0f + expf(-z));
   return s * (1.0f + z * (1.0f - s));
@@ -220,10 +226,12 @@ __global__ __launch_bounds__(WS_THREADS) void k_gemm_ws(const float *__restrict_
       s16x8 ah, al;
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
-        const float v = (AF == F_SILU) ? silu_f(a[i]) : a[i];
-        const uint16_t h = f2bf(v);
+        // hi + lo BF16 parts by the hardware conversion (v_cvt_pk_bf16_f32); the split only
+        // has to represent v, so its rounding mode does not matter
+        const float v = (AF == F_SILU) ? silu_fast(a[i]) : a[i];
+        const uint16_t h = __builtin_bit_cast(uint16_t, (__bf16)v);
         ah[i] = (short)h;
-        al[i] = (short)f2bf(v - bf2f(h));
+        al[i] = (short)__builtin_bit_cast(uint16_t, (__bf16)(v - bf2f(h)));
       }
       const s16x8 b0 = *(const s16x8 *)&Ws[(col0 + (lane & 31)) * WSP + kq];
       const s16x8 b1 = *(const s16x8 *)&Ws[(col0 + 32 + (lane & 31)) * WSP + kq];
