@@ -179,11 +179,12 @@ enum { W_NK = 0, W_KN = 1 };
 constexpr int WSP = NW + 8;   // LDS row pitch of Ws (bf16): 528 bytes, 16-byte aligned
 
 // Up to WS_TILES row tiles are in flight per workgroup: wave w computes columns
-// 64 (w % 4) .. +63 of tiles blockIdx.x + (w / 4 + WS_TILES i) gridDim.x, so the LDS copy of the
-// weights serves 4 WS_TILES waves (four per SIMD) on large batches, while small batches still
-// spread one tile per workgroup over the CUs.
-constexpr int WS_TILES = 4;
-constexpr int WS_THREADS = 256 * WS_TILES;
+// 128 (w % 2) .. +127 of tiles blockIdx.x + (w / 2 + WS_TILES i) gridDim.x, so the LDS copy of
+// the weights serves 16 waves (four per SIMD) on large batches while small batches still
+// spread one tile per workgroup over the CUs; each activation element is transformed
+// (SiLU, hi/lo split) by the two waves of its tile.
+constexpr int WS_TILES = 8;
+constexpr int WS_THREADS = 1024;
 
 template <int WL, int AF, int EPI>
 __global__ __launch_bounds__(WS_THREADS) void k_gemm_ws(const float *__restrict__ A, const uint16_t *__restrict__ W,
@@ -204,15 +205,17 @@ __global__ __launch_bounds__(WS_THREADS) void k_gemm_ws(const float *__restrict_
   }
   __syncthreads();
   const int ntiles = (M + 31) / 32;
-  const int col0 = (wave & 3) * 64;
-  for (int t = blockIdx.x + (wave >> 2) * gridDim.x; t < ntiles; t += gridDim.x * WS_TILES) {
+  const int col0 = (wave & 1) * 128;
+  for (int t = blockIdx.x + (wave >> 1) * gridDim.x; t < ntiles; t += gridDim.x * WS_TILES) {
     const int row = t * 32 + (lane & 31);
     const bool rok = row < M;
-    f32x16 acc0, acc1;
+    f32x16 acc[4];
 #pragma unroll
-    for (int v = 0; v < 16; ++v) { acc0[v] = 0.0f; acc1[v] = 0.0f; }
+    for (int h = 0; h < 4; ++h)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[h][v] = 0.0f;
     const float *arow = A + (int64_t)(rok ? row : 0) * NW;
-#pragma unroll 4
+#pragma unroll 2
     for (int kk = 0; kk < NW; kk += 16) {
       const int kq = kk + 8 * (lane >> 5);
       float a[8];
@@ -233,22 +236,22 @@ __global__ __launch_bounds__(WS_THREADS) void k_gemm_ws(const float *__restrict_
         ah[i] = (short)h;
         al[i] = (short)__builtin_bit_cast(uint16_t, (__bf16)(v - bf2f(h)));
       }
-      const s16x8 b0 = *(const s16x8 *)&Ws[(col0 + (lane & 31)) * WSP + kq];
-      const s16x8 b1 = *(const s16x8 *)&Ws[(col0 + 32 + (lane & 31)) * WSP + kq];
       const bf16x8 AH = __builtin_bit_cast(bf16x8, ah), AL = __builtin_bit_cast(bf16x8, al);
-      acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(AH, __builtin_bit_cast(bf16x8, b0), acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(AH, __builtin_bit_cast(bf16x8, b1), acc1, 0, 0, 0);
-      acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(AL, __builtin_bit_cast(bf16x8, b0), acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(AL, __builtin_bit_cast(bf16x8, b1), acc1, 0, 0, 0);
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        const s16x8 b = *(const s16x8 *)&Ws[(col0 + 32 * h + (lane & 31)) * WSP + kq];
+        acc[h] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(AH, __builtin_bit_cast(bf16x8, b), acc[h], 0, 0, 0);
+        acc[h] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(AL, __builtin_bit_cast(bf16x8, b), acc[h], 0, 0, 0);
+      }
     }
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const int m = t * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
       if (m < M) {
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
+        for (int h = 0; h < 4; ++h) {
           const int n = col0 + 32 * h + (lane & 31);
-          const float val = h ? acc1[v] : acc0[v];
+          const float val = acc[h][v];
           float *c = C + (int64_t)m * NW + n;
           if (EPI == E_BIAS_STORE) *c = val + bias[n];
           else *c = val * silu_grad_f(Z[(int64_t)m * NW + n]);
