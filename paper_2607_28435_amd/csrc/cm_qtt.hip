@@ -26,8 +26,8 @@
 
 namespace {
 
-constexpr int QP = 16;          // Chebyshev nodes per polynomial leaf
-constexpr int QNC = 64;         // max candidate intervals per depth
+constexpr int QP = 10;          // Chebyshev nodes per polynomial leaf
+constexpr int QNC = 96;         // max candidate intervals per depth
 constexpr int QI = QNC / 2;     // max split intervals per depth
 constexpr int QNPT = 2 * QP - 1;
 constexpr int PRE_CAP = QI + QP + 1;   // bond bound before rounding (<= 64)
@@ -240,8 +240,7 @@ __global__ __launch_bounds__(CM_WG, 2) void k_build_qtt(const cm_problem *__rest
       }
       __syncthreads();
       const double eps = eps_rel * hscale * exp2(-0.5 * m);
-      if (tid < NC) {
-        const int ci = tid;
+      for (int ci = tid; ci < NC; ci += CM_WG) {
         const int64_t c = T[d - 1].int_a[ci >> 1] + ((int64_t)(ci & 1) << m);
         const bool forced = simpson && c == 0;
         int kind;
