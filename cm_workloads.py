@@ -99,8 +99,7 @@ def vg_batch(count: int, seed: int = 31, n: int = 20) -> List[Problem]:
     """Seeded Variance Gamma draws: sigma ~ U(0.08, 0.3), nu ~ U(0.05, 0.5),
     theta ~ U(-0.3, 0.05), T ~ U(0.1, 1.5), kept when the damping moment condition holds
     for alpha = 1.5 with margin and T >= nu (the characteristic function then decays at
-    least like |v|^-2; shorter gamma clocks decay more slowly than the QTT build's partition
-    supports, which it reports as CM_E_NOCONV)."""
+    least like |v|^-2; shorter clocks are covered by vg_short_clock)."""
     g = _rng(seed)
     out = []
     while len(out) < count:
@@ -113,10 +112,17 @@ def vg_batch(count: int, seed: int = 31, n: int = 20) -> List[Problem]:
     return out
 
 
-def vg_slow_decay() -> Problem:
-    """A Variance Gamma instance with a short gamma clock (T/nu = 0.38): its characteristic
-    function decays like |v|^-0.76."""
-    return Problem("vg", "simpson1", 24, 100.0, 0.03, 0.0, 0.105, 1.5, eta_rule(24), (0.1854, 0.276, -0.1228))
+def vg_short_clock(n: int = 20) -> Problem:
+    """A Variance Gamma instance with a short gamma clock (T = 0.05, T/nu = 0.18): its
+    characteristic function decays only like |v|^-0.36, so x has no negligible tail."""
+    return Problem("vg", "simpson1", n, 100.0, 0.03, 0.0, 0.05, 1.5, eta_rule(n), (0.1854, 0.276, -0.1228))
+
+
+def merton_oscillating() -> Problem:
+    """Merton with near-deterministic jumps (lam_J = 2, mu_J = 0.5, delta_J = 0.001) and
+    almost no diffusion (sigma = 0.01), n = 24: the characteristic function keeps
+    oscillating with period 2 pi / mu_J out to |v| of order 1 / delta_J."""
+    return Problem("merton", "simpson1", 24, 100.0, 0.02, 0.0, 1.0, 1.5, eta_rule(24), (0.01, 2.0, 0.5, 0.001))
 
 
 def paper_bs_grid(n: int) -> Problem:

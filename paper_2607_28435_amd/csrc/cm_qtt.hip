@@ -12,7 +12,7 @@
 //   - a polynomial leaf if the degree P-1 Chebyshev interpolant matches h at P-1 check
 //     points to eps(m),
 //   - exact if 2^m <= P (values at all points), otherwise it is split in two.
-// eps(m) = 0.1 tol |h(0)| 2^(-m/2) bounds each leaf's contribution to ||x||_2.
+// eps(m) = tol |h(0)| 2^(-m/2) bounds each leaf's contribution to ||x||_2.
 // Polynomials in the remaining suffix share one P-dimensional bond space (values at the
 // suffix interval's Chebyshev nodes; Lagrange cores pass them down exactly), so the bond
 // dimension before rounding is (#split intervals at that depth) + min(P, 2^m). The train is
@@ -204,7 +204,7 @@ __global__ __launch_bounds__(CM_WG, 2) void k_build_qtt(const cm_problem *__rest
     const int64_t jpeak = simpson ? 0 : ((int64_t)1 << (n - 1));
     const double2 hpk = [&] { cx<double> z = h_centered<double>(cm, v0 + (double)jpeak * eta); return cmk(z.x, z.y); }();
     const double hscale = sqrt(cabs2(hpk));
-    const double eps_rel = 0.1 * tol;
+    const double eps_rel = tol;
 
     // ---------------- tree
     TreeDepth *T = W.tree;

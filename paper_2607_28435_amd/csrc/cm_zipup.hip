@@ -174,7 +174,10 @@ __device__ __forceinline__ int zip_site(char *arena, const SiteDims &sd, const T
 // barrier-free with eight lanes per column, from the reflectors kept in LDS.
 constexpr int PW = CM_WG / 64;    // waves per workgroup
 constexpr int MR = 48;            // rows: m = 2 chi <= 48
-constexpr int SM = MR / 2;        // register slots per lane
+constexpr int SM = MR / 2;        // register slots per lane at the largest m
+// The pivot loop is compiled for 8, 12, 16 and 24 slots (m <= 16, 24, 32, 48), each site
+// taking the smallest that holds it: fewer slots leave the loop's addresses and scalars in
+// registers instead of spilling them across the barrier.
 constexpr int CP = CM_WG / 2;     // columns: p <= 128
 struct CandInfo {
   double best, sum;
@@ -277,7 +280,7 @@ __device__ __forceinline__ House householder(double n2, double2 alpha) {
   return H;
 }
 
-template <typename T>
+template <typename T, int SMX>
 __device__ __forceinline__ int zip_site_pair(char *arena, const SiteDims &sd, const T *__restrict__ Wl,
                                              const T *__restrict__ Al, double2 *C, T *Yout, double delta2,
                                              int kcap, int *code) {
@@ -321,13 +324,17 @@ __device__ __forceinline__ int zip_site_pair(char *arena, const SiteDims &sd, co
   // with D[ch][w0][j][r1] = sum_r C[ch][w0][r] A[r][j][r1], both in the storage precision,
   // four ch at a time; D chunks alternate between two buffers, one barrier per chunk
   const bool cok = c < p;
-  double2 t[SM];
+  // waves whose 32 columns all lie beyond p (most waves at typical ranks) hold no column of
+  // T: they skip the contraction's second product, the pivot search and the column updates,
+  // and only take part in the barriers and the row writes
+  const bool wcols = 32 * wv < p;
+  double2 t[SMX];
 #pragma unroll
-  for (int sl = 0; sl < SM; ++sl) t[sl] = cmk(0.0, 0.0);
+  for (int sl = 0; sl < SMX; ++sl) t[sl] = cmk(0.0, 0.0);
   {
     const int wp = cok ? c / r1 : 0, rp = cok ? c - (c / r1) * r1 : 0;
 #pragma unroll
-    for (int ch0 = 0; ch0 < SM; ch0 += 4) {
+    for (int ch0 = 0; ch0 < SMX; ch0 += 4) {
       if (ch0 < chi) {
         T *Db = Dch + ((ch0 / 4) & 1) * dchunk;
         __syncthreads();   // staging done (first chunk) / this buffer's previous readers done
@@ -341,19 +348,21 @@ __device__ __forceinline__ int zip_site_pair(char *arena, const SiteDims &sd, co
           Db[e] = acc;
         }
         __syncthreads();
-        typename A::type acc[4];
+        if (wcols) {
+          typename A::type acc[4];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) acc[e] = A::zero();
-        for (int ww = 0; ww < w0; ++ww)
-          for (int j = 0; j < 2; ++j) {
-            const T wvv = Wc[(ww * 4 + 2 * g + j) * w1 + wp];
-            const T *dd = Db + (ww * 2 + j) * r1 + rp;
+          for (int e = 0; e < 4; ++e) acc[e] = A::zero();
+          for (int ww = 0; ww < w0; ++ww)
+            for (int j = 0; j < 2; ++j) {
+              const T wvv = Wc[(ww * 4 + 2 * g + j) * w1 + wp];
+              const T *dd = Db + (ww * 2 + j) * r1 + rp;
 #pragma unroll
-            for (int cc = 0; cc < 4; ++cc) A::fma_(acc[cc], dd[cc * w0 * 2 * r1], wvv);
-          }
+              for (int cc = 0; cc < 4; ++cc) A::fma_(acc[cc], dd[cc * w0 * 2 * r1], wvv);
+            }
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
-          if (cok && ch0 + e < chi) t[ch0 + e] = A::to(acc[e]);
+          for (int e = 0; e < 4; ++e)
+            if (cok && ch0 + e < chi) t[ch0 + e] = A::to(acc[e]);
+        }
       }
     }
   }
@@ -363,7 +372,7 @@ __device__ __forceinline__ int zip_site_pair(char *arena, const SiteDims &sd, co
   {
     double nz[2] = {0.0, 0.0};
 #pragma unroll
-    for (int sl = 0; sl < SM; ++sl) nz[sl & 1] += cabs2(t[sl]);
+    for (int sl = 0; sl < SMX; ++sl) nz[sl & 1] += cabs2(t[sl]);
     nrm = pair_sum(nz[0] + nz[1]);
   }
   const int kmax = m < p ? m : p;
@@ -380,7 +389,7 @@ __device__ __forceinline__ int zip_site_pair(char *arena, const SiteDims &sd, co
     const int b = i & 1, j = i >> 1;
     double best = act ? nrm : -1.0, sum = (act && g == 0) ? nrm : 0.0;
     int bi = act ? c : 0x7fffffff;
-    wave_argmax_sum_uni(best, bi, sum);
+    if (__ballot(act) != 0) wave_argmax_sum_uni(best, bi, sum);   // else already the reduction's result
     double2 *mine = cand + (b * PW + wv) * MR;
     CandInfo *inf = info + b * PW + wv;
     if (c == bi) {
@@ -398,7 +407,7 @@ __device__ __forceinline__ int zip_site_pair(char *arena, const SiteDims &sd, co
       }
       mine[g] = v0;
 #pragma unroll
-      for (int sl = 1; sl < SM; ++sl) mine[2 * sl + g] = t[sl];
+      for (int sl = 1; sl < SMX; ++sl) mine[2 * sl + g] = t[sl];
     }
     if (bi == 0x7fffffff && lane == 0) {   // no candidate left in this wave
       CandInfo ci;
@@ -406,13 +415,25 @@ __device__ __forceinline__ int zip_site_pair(char *arena, const SiteDims &sd, co
       *inf = ci;
     }
     __syncthreads();
+    // every wave's record is loaded before any is compared, so that one LDS latency covers
+    // all four, and the choice is made with selects
+    double cb[PW], cs[PW];
+    int cx[PW];
+#pragma unroll
+    for (int q = 0; q < PW; ++q) {
+      cb[q] = info[b * PW + q].best;
+      cs[q] = info[b * PW + q].sum;
+      cx[q] = info[b * PW + q].idx;
+    }
     double gbest = -1.0, tail = 0.0;
     int gidx = 0x7fffffff, gw = 0;
 #pragma unroll
     for (int q = 0; q < PW; ++q) {
-      const CandInfo ci = info[b * PW + q];
-      tail += ci.sum;
-      if (ci.best > gbest || (ci.best == gbest && ci.idx < gidx)) { gbest = ci.best; gidx = ci.idx; gw = q; }
+      tail += cs[q];
+      const bool better = (cb[q] > gbest) | ((cb[q] == gbest) & (cx[q] < gidx));
+      gbest = better ? cb[q] : gbest;
+      gidx = better ? cx[q] : gidx;
+      gw = better ? q : gw;
     }
     if (!(tail == tail) || isinf(tail)) {
       if (tid == 0 && *code == CM_OK) *code = CM_E_NONFINITE;
@@ -438,17 +459,32 @@ __device__ __forceinline__ int zip_site_pair(char *arena, const SiteDims &sd, co
   bool stop = select(0);
   while (!stop) {
     const int j = i >> 1;
-    const int live = hrows - j;   // slots holding rows >= i (and possibly one finished row)
+    // slots holding rows >= i (and possibly one finished row); none in a wave with no
+    // candidate column left, whose entries are not read again (it only writes its zeros of
+    // row i of R)
+    const int live = __ballot(act) != 0 ? hrows - j : 0;
     const double2 *Xg = X + g;
+    // this lane's rows of the pivot column: with up to 12 slots all are loaded at once (one
+    // LDS latency) and kept for the update; above that they are read per group of four
+    constexpr bool XPRE = SMX <= 12;
+    double2 xv[XPRE ? SMX : 1];
+    if constexpr (XPRE) {
+#pragma unroll
+      for (int sl = 0; sl < SMX; ++sl) xv[sl] = Xg[2 * sl];
+    }
+    auto xat = [&](int sl) -> double2 {
+      if constexpr (XPRE) return xv[sl];
+      else return Xg[2 * sl];
+    };
     // w_c = conj(tau) sum_r conj(v_r) T[r, c] with v = x scal, summed over the pair
     double2 pz[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) pz[e] = cmk(0.0, 0.0);
 #pragma unroll
-    for (int q4 = 0; q4 < SM / 4; ++q4)
+    for (int q4 = 0; q4 < SMX / 4; ++q4)
       if (4 * q4 < live) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) ccfma(pz[e], Xg[2 * (4 * q4 + e)], t[4 * q4 + e]);
+        for (int e = 0; e < 4; ++e) ccfma(pz[e], xat(4 * q4 + e), t[4 * q4 + e]);
       }
     double2 pw = cadd(cadd(pz[0], pz[1]), cadd(pz[2], pz[3]));
     pw.x = pair_sum(pw.x);
@@ -456,7 +492,7 @@ __device__ __forceinline__ int zip_site_pair(char *arena, const SiteDims &sd, co
     const double2 ws = cmul(cscale(ctau, cabs2(scal)), pw);   // scal w_c
     // row i of R, from slot 0 of lane i % 2
     {
-      const double2 x0 = Xg[0];
+      const double2 x0 = xat(0);
       double2 r0v = t[0];
       r0v.x -= x0.x * ws.x - x0.y * ws.y;
       r0v.y -= x0.x * ws.y + x0.y * ws.x;
@@ -467,12 +503,12 @@ __device__ __forceinline__ int zip_site_pair(char *arena, const SiteDims &sd, co
     double nz[2] = {0.0, 0.0};
     const bool skip0 = (i & 1) || g == 0;
 #pragma unroll
-    for (int q4 = 0; q4 < SM / 4; ++q4)
+    for (int q4 = 0; q4 < SMX / 4; ++q4)
       if (4 * q4 < live) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const int sl = 4 * q4 + e;
-          const double2 x = Xg[2 * sl];
+          const double2 x = xat(sl);
           double2 y = t[sl];
           y.x -= x.x * ws.x - x.y * ws.y;
           y.y -= x.x * ws.y + x.y * ws.x;
@@ -484,8 +520,8 @@ __device__ __forceinline__ int zip_site_pair(char *arena, const SiteDims &sd, co
     // bounded by the live count would become a memmove that keeps T out of registers)
     if (i & 1) {
 #pragma unroll
-      for (int sl = 0; sl + 1 < SM; ++sl) t[sl] = t[sl + 1];
-      t[SM - 1] = cmk(0.0, 0.0);
+      for (int sl = 0; sl + 1 < SMX; ++sl) t[sl] = t[sl + 1];
+      t[SMX - 1] = cmk(0.0, 0.0);
     }
     nrm = pair_sum(nz[0] + nz[1]);
     if (c == pc) act = false;
@@ -493,7 +529,7 @@ __device__ __forceinline__ int zip_site_pair(char *arena, const SiteDims &sd, co
     if (tid < MR) {
       double2 v = cmk(0.0, 0.0);
       if (tid == i) v = cmk(1.0, 0.0);
-      else if (tid > i) v = cmul(X[tid - 2 * j], scal);
+      else if (tid > i && tid < m) v = cmul(X[tid - 2 * j], scal);
       V[i * MR + tid] = v;
     }
     ++i;
@@ -600,7 +636,10 @@ __global__ __launch_bounds__(CM_WG, 3) void k_zipup(TTView w, int w_slots, TTVie
       T *Yout = Yc + y.coff(b, l);
       int k;
       if (!last && pair_site_fits<T>(sd, chicap, zlds_bytes<T>()))
-        k = zip_site_pair<T>(lds_arena, sd, Wl, Al, C, Yout, delta2, chicap, &code_sh);
+        k = m <= 16   ? zip_site_pair<T, 8>(lds_arena, sd, Wl, Al, C, Yout, delta2, chicap, &code_sh)
+            : m <= 24 ? zip_site_pair<T, 12>(lds_arena, sd, Wl, Al, C, Yout, delta2, chicap, &code_sh)
+            : m <= 32 ? zip_site_pair<T, 16>(lds_arena, sd, Wl, Al, C, Yout, delta2, chicap, &code_sh)
+                      : zip_site_pair<T, SM>(lds_arena, sd, Wl, Al, C, Yout, delta2, chicap, &code_sh);
       else if (need <= (size_t)zlds_bytes<T>())
         k = zip_site<T>(lds_arena, sd, Wl, Al, C, D, Yout, last, delta2, chicap, sh, &code_sh);
       else

@@ -416,15 +416,35 @@ def test_vg_status_codes():
     assert dst.cpu().numpy().tolist() == [cm.CM_OK, cm.CM_E_INVALID, cm.CM_E_MOMENT]
 
 
-def test_vg_slow_decay_reports_noconv():
-    """A Variance Gamma draw whose characteristic function decays too slowly for the QTT
-    build's partition is reported per instance (CM_E_NOCONV; its train is left as the zero
-    train) without disturbing its neighbour in the batch."""
-    say("vg slow decay")
+@pytest.mark.parametrize("dtype,tol,gate", [(cm.CM_C128, 1e-10, FP64_TOL), (cm.CM_C64, 1e-8, C64_TOL)],
+                         ids=["c128", "c64"])
+def test_vg_short_clock_prices(dtype, tol, gate):
+    """A Variance Gamma instance whose gamma clock is short (T/nu = 0.18, so x decays only
+    like |v|^-0.36 and has no negligible tail) builds without error; its prices match the
+    oracle's direct sum and the gamma mixture of Black–Scholes prices."""
+    say("vg short clock", dtype)
+    p = W.vg_short_clock(20)
+    u = W.near_money(p, 64)
+    pr = cm.SfftPricer([p], dtype, tol=tol, cap=32)
+    got = pr.run(_strikes_dev([u])).cpu().numpy()[0]
+    for k, v in pr.statuses().items():
+        assert np.all(v == cm.CM_OK), (k, v)
+    sel = u[::4]
+    assert np.abs(got[::4] - O.prices_direct(p, sel)).max() / p.S0 < gate
+    mix = O.vg_call_gamma_mixture(p, O.strike_of(p, u[::8]))
+    assert np.abs(got[::8] - mix).max() / p.S0 < gate
+
+
+def test_unresolved_structure_reports_noconv():
+    """An instance whose characteristic function has more structure than the QTT build's
+    per-depth interval limits resolve (Merton with near-deterministic jumps and almost no
+    diffusion) is reported per instance (CM_E_NOCONV; its train is left as the zero train)
+    without disturbing its neighbour in the batch."""
+    say("unresolved structure")
     good = W.vg_n20().replace(n=24, eta=W.eta_rule(24))
-    slow = W.vg_slow_decay()
-    pr = cm.SfftPricer([good, slow], cm.CM_C64, tol=1e-8, cap=32)
-    u = np.stack([W.near_money(good, 64), W.near_money(slow, 64)])
+    bad = W.merton_oscillating()
+    pr = cm.SfftPricer([good, bad], cm.CM_C64, tol=1e-8, cap=32)
+    u = np.stack([W.near_money(good, 64), W.near_money(bad, 64)])
     got = pr.run(torch.from_numpy(u).cuda()).cpu().numpy()
     st = pr.statuses()
     assert st["build"].tolist() == [cm.CM_OK, cm.CM_E_NOCONV]
