@@ -537,30 +537,43 @@ __device__ __forceinline__ int zip_site_pair(char *arena, const SiteDims &sd, co
   }
   const int k = i;
   // Q = H_0 ... H_{k-1} [I_k; 0], barrier-free: column cq of Q on lanes 8 cq .. 8 cq + 7,
-  // lane h of the eight holding rows 8 s + h; the dot products are summed with DPP
+  // lane h of the eight holding rows 8 s + h (s < SMX / 4, as m <= 2 SMX); the dot products
+  // are summed with DPP. Reflector jj - 1 and its tau are loaded while reflector jj is
+  // applied, so the LDS latency overlaps the arithmetic.
   {
+    constexpr int QS = SMX / 4;
     const int cq = tid >> 3, h = tid & 7;
     if (cq < k) {   // uniform over each group of eight lanes
-      double2 qv[MR / 8];
+      double2 qv[QS], vc[QS], vn[QS];
 #pragma unroll
-      for (int sl = 0; sl < MR / 8; ++sl) qv[sl] = cmk(8 * sl + h == cq ? 1.0 : 0.0, 0.0);
+      for (int sl = 0; sl < QS; ++sl) qv[sl] = cmk(8 * sl + h == cq ? 1.0 : 0.0, 0.0);
+      double2 tc = taus[k - 1], tn = cmk(0.0, 0.0);
+#pragma unroll
+      for (int sl = 0; sl < QS; ++sl) vc[sl] = V[(k - 1) * MR + 8 * sl + h];
       for (int jj = k - 1; jj >= 0; --jj) {
-        const double2 tj = taus[jj];
-        if (tj.x == 0.0 && tj.y == 0.0) continue;
-        const double2 *Vj = V + jj * MR + h;
-        double2 d = cmk(0.0, 0.0);
+        if (jj > 0) {
+          tn = taus[jj - 1];
 #pragma unroll
-        for (int sl = 0; sl < MR / 8; ++sl)
-          if (8 * sl + 7 >= jj && 8 * sl < m) ccfma(d, Vj[8 * sl], qv[sl]);   // V[jj][r] = 0 for r < jj, r >= m
-        d.x = la::grp_sum(d.x, 8);
-        d.y = la::grp_sum(d.y, 8);
-        const double2 wq = cmul(tj, d);
+          for (int sl = 0; sl < QS; ++sl) vn[sl] = V[(jj - 1) * MR + 8 * sl + h];
+        }
+        if (tc.x != 0.0 || tc.y != 0.0) {
+          double2 d = cmk(0.0, 0.0);
 #pragma unroll
-        for (int sl = 0; sl < MR / 8; ++sl)
-          if (8 * sl + 7 >= jj && 8 * sl < m) qv[sl] = csub(qv[sl], cmul(Vj[8 * sl], wq));
+          for (int sl = 0; sl < QS; ++sl)
+            if (8 * sl + 7 >= jj && 8 * sl < m) ccfma(d, vc[sl], qv[sl]);   // V[jj][r] = 0 for r < jj, r >= m
+          d.x = la::grp_sum(d.x, 8);
+          d.y = la::grp_sum(d.y, 8);
+          const double2 wq = cmul(tc, d);
+#pragma unroll
+          for (int sl = 0; sl < QS; ++sl)
+            if (8 * sl + 7 >= jj && 8 * sl < m) qv[sl] = csub(qv[sl], cmul(vc[sl], wq));
+        }
+        tc = tn;
+#pragma unroll
+        for (int sl = 0; sl < QS; ++sl) vc[sl] = vn[sl];
       }
 #pragma unroll
-      for (int sl = 0; sl < MR / 8; ++sl)
+      for (int sl = 0; sl < QS; ++sl)
         if (8 * sl + h < m) cstore<T>::st(Yout, (int64_t)(8 * sl + h) * k + cq, qv[sl]);
     }
   }
