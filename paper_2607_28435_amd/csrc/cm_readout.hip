@@ -73,7 +73,11 @@ __device__ __forceinline__ double read_price(const ReadConst &c, int64_t u, doub
 
 constexpr int RD_WG = 256;
 constexpr int RD_SPT = 16;                // strikes per lane
-constexpr int RD_LDS = 64 * 1024;         // core staging arena and prefix tree (two workgroups per CU)
+// core staging arena and prefix tree: 48 KB for complex64 (three workgroups per CU, as many
+// as the registers allow), 64 KB for complex128 (two)
+template <typename T> constexpr int rd_lds();
+template <> constexpr int rd_lds<float2>() { return 48 * 1024; }
+template <> constexpr int rd_lds<double2>() { return 64 * 1024; }
 // Prefix tree for strikes that share their high bits (a contiguous block of a workgroup's
 // 4096 strikes spans at most two values of u >> 12): y_u = Lo[u mod 32] . MR[u >> 12][(u >> 5)
 // mod 128], where Lo holds the 32 row vectors of cores 0..4, R[h] the right vectors of cores
@@ -200,7 +204,7 @@ __global__ __launch_bounds__(RD_WG) void k_readout(TTView y, const cm_problem *_
     }
     s_rk[n] = rk[n];
     s_off[n] = o;
-    s_ok = (size_t)o * sizeof(T) <= (size_t)RD_LDS;
+    s_ok = (size_t)o * sizeof(T) <= (size_t)rd_lds<T>();
   }
   __syncthreads();
   const bool in_lds = s_ok != 0;
@@ -232,12 +236,17 @@ __global__ __launch_bounds__(RD_WG) void k_readout(TTView y, const cm_problem *_
   const ReadConst rc = read_const(pr, n);
   const int64_t M = (int64_t)1 << n;
   const int s0 = blockIdx.x * RD_WG * RD_SPT;
-  // this workgroup's strikes; the range of their high parts decides the prefix tree
+  // this workgroup's strikes; the range of their high parts decides the prefix tree. Each
+  // lane reduces its strikes, the wave reduces by shuffles, and one lane per wave updates
+  // the workgroup's range: atomics from every lane to one LDS word serialise and cost more
+  // than the rest of the read-out.
   __shared__ long long s_hmin, s_hmax;
   __shared__ int s_bad;
   if (threadIdx.x == 0) { s_hmin = LLONG_MAX; s_hmax = -1; s_bad = 0; }
   __syncthreads();
   int64_t uu[RD_SPT];
+  long long hlo = LLONG_MAX, hhi = -1;
+  int bad = 0;
 #pragma unroll
   for (int t = 0; t < RD_SPT; ++t) {
     const int s = s0 + t * RD_WG + (int)threadIdx.x;
@@ -245,15 +254,32 @@ __global__ __launch_bounds__(RD_WG) void k_readout(TTView y, const cm_problem *_
     if (s < nk) {
       const int64_t u = strike_idx[(int64_t)b * nk + s];
       uu[t] = u;
-      if (u < 0 || u >= M) atomicOr(&s_bad, 1);
-      else { atomicMin(&s_hmin, (long long)(u >> TB_H)); atomicMax(&s_hmax, (long long)(u >> TB_H)); }
+      if (u < 0 || u >= M) {
+        bad = 1;
+      } else {
+        const long long h = (long long)(u >> TB_H);
+        hlo = h < hlo ? h : hlo;
+        hhi = h > hhi ? h : hhi;
+      }
     }
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const long long a = __shfl_xor(hlo, o), c = __shfl_xor(hhi, o);
+    hlo = a < hlo ? a : hlo;
+    hhi = c > hhi ? c : hhi;
+    bad |= __shfl_xor(bad, o);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicMin(&s_hmin, hlo);
+    atomicMax(&s_hmax, hhi);
+    if (bad) atomicOr(&s_bad, 1);
   }
   __syncthreads();
   const int r5 = (n > TB_H) ? s_rk[TB_LO] : 0, r10 = (n > TB_H) ? s_rk[TB_H] : 0;
   const int tree_elems = TB_K * r10 + (32 + TB_K * TB_MID) * r5;
   const bool tree = in_lds && n > TB_H && pr.n == n && s_bad == 0 && s_hmax >= s_hmin &&
-                    s_hmax - s_hmin < TB_K && (size_t)(s_off[n] + tree_elems) * sizeof(T) <= (size_t)RD_LDS;
+                    s_hmax - s_hmin < TB_K && (size_t)(s_off[n] + tree_elems) * sizeof(T) <= (size_t)rd_lds<T>();
   if (tree) {
     const int64_t hmin = s_hmin;
     const int nh = (int)(s_hmax - s_hmin) + 1;
@@ -393,26 +419,28 @@ static cm_status readout(const cm_tt_batch *y, const cm_problem *prob, const int
   // the rest
   int fast_max;
   if (y->dtype == CM_C64) {
-    CM_HIP_CHECK(cm_allow_lds(k_readout<float2, 8>, RD_LDS));
-    CM_HIP_CHECK(cm_allow_lds(k_readout<float2, 16>, RD_LDS));
-    CM_HIP_CHECK(cm_allow_lds(k_readout<float2, 32>, RD_LDS));
-    hipLaunchKernelGGL((k_readout<float2, 8>), grid, dim3(RD_WG), RD_LDS, s, v, prob, strike_idx, nk, prices, status,
-                       0, absval);
+    constexpr int L = rd_lds<float2>();
+    CM_HIP_CHECK(cm_allow_lds(k_readout<float2, 8>, L));
+    CM_HIP_CHECK(cm_allow_lds(k_readout<float2, 16>, L));
+    CM_HIP_CHECK(cm_allow_lds(k_readout<float2, 32>, L));
+    hipLaunchKernelGGL((k_readout<float2, 8>), grid, dim3(RD_WG), L, s, v, prob, strike_idx, nk, prices, status, 0,
+                       absval);
     if (cap > 8)
-      hipLaunchKernelGGL((k_readout<float2, 16>), grid, dim3(RD_WG), RD_LDS, s, v, prob, strike_idx, nk, prices,
-                         status, 8, absval);
+      hipLaunchKernelGGL((k_readout<float2, 16>), grid, dim3(RD_WG), L, s, v, prob, strike_idx, nk, prices, status, 8,
+                         absval);
     if (cap > 16)
-      hipLaunchKernelGGL((k_readout<float2, 32>), grid, dim3(RD_WG), RD_LDS, s, v, prob, strike_idx, nk, prices,
-                         status, 16, absval);
+      hipLaunchKernelGGL((k_readout<float2, 32>), grid, dim3(RD_WG), L, s, v, prob, strike_idx, nk, prices, status, 16,
+                         absval);
     fast_max = 32;
   } else {
-    CM_HIP_CHECK(cm_allow_lds(k_readout<double2, 8>, RD_LDS));
-    CM_HIP_CHECK(cm_allow_lds(k_readout<double2, 16>, RD_LDS));
-    hipLaunchKernelGGL((k_readout<double2, 8>), grid, dim3(RD_WG), RD_LDS, s, v, prob, strike_idx, nk, prices,
-                       status, 0, absval);
+    constexpr int L = rd_lds<double2>();
+    CM_HIP_CHECK(cm_allow_lds(k_readout<double2, 8>, L));
+    CM_HIP_CHECK(cm_allow_lds(k_readout<double2, 16>, L));
+    hipLaunchKernelGGL((k_readout<double2, 8>), grid, dim3(RD_WG), L, s, v, prob, strike_idx, nk, prices, status, 0,
+                       absval);
     if (cap > 8)
-      hipLaunchKernelGGL((k_readout<double2, 16>), grid, dim3(RD_WG), RD_LDS, s, v, prob, strike_idx, nk, prices,
-                         status, 8, absval);
+      hipLaunchKernelGGL((k_readout<double2, 16>), grid, dim3(RD_WG), L, s, v, prob, strike_idx, nk, prices, status, 8,
+                         absval);
     fast_max = 16;
   }
   CM_LAUNCH_CHECK();
