@@ -416,6 +416,36 @@ def test_vg_status_codes():
     assert dst.cpu().numpy().tolist() == [cm.CM_OK, cm.CM_E_INVALID, cm.CM_E_MOMENT]
 
 
+@pytest.mark.parametrize("name", ["heston20_tol1e-12", "bs12rect_tol1e-13"])
+def test_zipup_site_paths_fp64(name):
+    """The zip-up compiles its register-resident pivot loop for 8, 12, 16 and 24 slots per
+    lane (2 chi <= 16, 24, 32, 48) and takes an LDS path above that. Heston at n = 20 and
+    tol 1e-12 carries bonds from 1 to 24 (every register loop); the rectangle-rule
+    Black–Scholes grid at tol 1e-13 reaches bonds above 24 (the LDS path). Prices through the
+    whole chain against the oracle."""
+    say("zip-up site paths", name)
+    p, tol = {"heston20_tol1e-12": (W.heston_n24().replace(n=20, eta=W.eta_rule(20)), 1e-12),
+              "bs12rect_tol1e-13": (W.bs_rect_n12(), 1e-13)}[name]
+    pr = cm.SfftPricer([p], cm.CM_C128, tol=tol, cap=48)
+    pr.build()
+    pr.apply()
+    torch.cuda.synchronize()
+    chi = pr.y.ranks[0, : p.n].cpu().numpy()   # carried bond entering each site
+    if name.startswith("heston"):
+        for lo, hi in ((1, 8), (9, 12), (13, 16), (17, 24)):
+            assert np.any((chi >= lo) & (chi <= hi)), (lo, hi, chi)
+    else:
+        assert chi.max() > 24, chi
+    pr.round()
+    u = W.near_money(p, 256)
+    prices = torch.empty((1, len(u)), dtype=torch.float64, device="cuda")
+    pr.read(_strikes_dev([u]), prices)
+    for k, v in pr.statuses().items():
+        assert np.all(v == cm.CM_OK), (k, v)
+    ref = O.prices_direct(p, u)
+    assert np.abs(prices.cpu().numpy()[0] - ref).max() / p.S0 < FP64_TOL
+
+
 @pytest.mark.parametrize("dtype,tol,gate", [(cm.CM_C128, 1e-10, FP64_TOL), (cm.CM_C64, 1e-8, C64_TOL)],
                          ids=["c128", "c64"])
 def test_vg_short_clock_prices(dtype, tol, gate):
