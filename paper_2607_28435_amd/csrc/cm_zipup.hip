@@ -494,8 +494,8 @@ __device__ __forceinline__ int zip_site_pair(char *arena, const SiteDims &sd, co
     {
       const double2 x0 = xat(0);
       double2 r0v = t[0];
-      r0v.x -= x0.x * ws.x - x0.y * ws.y;
-      r0v.y -= x0.x * ws.y + x0.y * ws.x;
+      r0v.x = fma(x0.y, ws.y, fma(-x0.x, ws.x, r0v.x));
+      r0v.y = fma(-x0.y, ws.x, fma(-x0.x, ws.y, r0v.y));
       if (cok && g == (i & 1)) C[(int64_t)i * p + c] = (c == pc) ? cmk(beta, 0.0) : (act ? r0v : cmk(0.0, 0.0));
     }
     // T <- H^H T; slot 0 holds row i (lane i % 2) or, after an even step, the row finished
@@ -510,10 +510,11 @@ __device__ __forceinline__ int zip_site_pair(char *arena, const SiteDims &sd, co
           const int sl = 4 * q4 + e;
           const double2 x = xat(sl);
           double2 y = t[sl];
-          y.x -= x.x * ws.x - x.y * ws.y;
-          y.y -= x.x * ws.y + x.y * ws.x;
+          // y -= x ws and the remaining norm, as chained FMAs (two per component)
+          y.x = fma(x.y, ws.y, fma(-x.x, ws.x, y.x));
+          y.y = fma(-x.y, ws.x, fma(-x.x, ws.y, y.y));
           t[sl] = y;
-          if (sl > 0 || !skip0) nz[e & 1] += cabs2(y);
+          if (sl > 0 || !skip0) nz[e & 1] = fma(y.y, y.y, fma(y.x, y.x, nz[e & 1]));
         }
       }
     // after an odd step both lanes move their slots down by one (every slot moves: a copy
@@ -566,7 +567,10 @@ __device__ __forceinline__ int zip_site_pair(char *arena, const SiteDims &sd, co
           const double2 wq = cmul(tc, d);
 #pragma unroll
           for (int sl = 0; sl < QS; ++sl)
-            if (8 * sl + 7 >= jj && 8 * sl < m) qv[sl] = csub(qv[sl], cmul(vc[sl], wq));
+            if (8 * sl + 7 >= jj && 8 * sl < m) {   // qv -= v wq, as chained FMAs
+              qv[sl].x = fma(vc[sl].y, wq.y, fma(-vc[sl].x, wq.x, qv[sl].x));
+              qv[sl].y = fma(-vc[sl].y, wq.x, fma(-vc[sl].x, wq.y, qv[sl].y));
+            }
         }
         tc = tn;
 #pragma unroll
