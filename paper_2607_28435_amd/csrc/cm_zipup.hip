@@ -157,17 +157,18 @@ __device__ __forceinline__ int zip_site(char *arena, const SiteDims &sd, const T
   return k;
 }
 
-// ---- pair-resident site -----------------------------------------------------------------
-// T (m x p, FP64) is held in registers for the whole pivoted QR. Column c lives on the lane
-// pair 2c, 2c + 1; at step i (j = i / 2 pair shifts done) lane g of the pair holds row
-// 2 (s + j) + g in register slot s. Both lanes move their slots down by one after every odd
-// step, so row i always sits in slot 0 of lane i % 2 and every register index is static;
-// the row finished at the even step before is then in slot 0 of lane 0 and takes no part
-// (its reflector entries are zero). A dot product is lane-local plus one DPP exchange
-// within the pair. A pivot step needs one workgroup barrier, at which each wave publishes
-// its best candidate column (norm, index, the sum of its columns' norms, its entry alpha in
-// row i and its rows from i on, with the Householder data it would give) and all waves
-// then take the same global choice. Column
+// ---- register-resident site ------------------------------------------------------------
+// T (m x p, FP64) is held in registers for the whole pivoted QR. Column c lives on the G
+// lanes G c .. G c + G - 1 (G = 8 for sites with p <= 32 and G = 4 for p <= 64, so that
+// all four waves hold columns, else G = 2); at step i (j = i / G shifts done) lane g of the group holds row G (s + j) + g
+// in register slot s. All lanes of a group move their slots down by one after every step i
+// with i % G = G - 1, so row i always sits in slot 0 of lane i % G and every register index
+// is static; rows finished before i in the same group of G sit in slot 0 of the lanes below
+// and take no part (their reflector entries are zero). A dot product is lane-local plus
+// log2 G DPP exchanges within the group. A pivot step needs one workgroup barrier, at which
+// each wave publishes its best candidate column (norm, index, the sum of its columns'
+// norms, its entry alpha in row i and its rows from i on, with the Householder data it
+// would give) and all waves then take the same global choice. Column
 // norms are recomputed exactly from the updated entries at every step. Rows of
 // B = R P^T are emitted as they are finished, straight into the carry buffer in the
 // [k][w'][r'] order the next site reads. Q = H_0 ... H_{k-1} [I_k; 0] is then accumulated
@@ -175,9 +176,11 @@ __device__ __forceinline__ int zip_site(char *arena, const SiteDims &sd, const T
 constexpr int PW = CM_WG / 64;    // waves per workgroup
 constexpr int MR = 48;            // rows: m = 2 chi <= 48
 constexpr int SM = MR / 2;        // register slots per lane at the largest m
-// The pivot loop is compiled for 8, 12, 16 and 24 slots (m <= 16, 24, 32, 48), each site
-// taking the smallest that holds it: fewer slots leave the loop's addresses and scalars in
-// registers instead of spilling them across the barrier.
+// The pivot loop is compiled for G = 2 lanes per column with 8, 12, 16 and 24 slots
+// (m <= 16, 24, 32, 48), G = 4 with 8 and 12 slots (p <= 64, m <= 32, 48) and G = 8 with 4
+// slots (p <= 32, m <= 32); each site takes the widest G and then the fewest slots that hold
+// it. Fewer slots leave the loop's addresses and scalars in registers instead of spilling
+// them across the barrier, and a wider G spreads a step's column work over more waves.
 constexpr int CP = CM_WG / 2;     // columns: p <= 128
 struct CandInfo {
   double best, sum;
@@ -215,8 +218,6 @@ __device__ __forceinline__ double lane_d(double x, int l) {
   return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), l),
                           __builtin_amdgcn_readlane(__double2loint(x), l));
 }
-// sum over the lane pair (l, l ^ 1)
-__device__ __forceinline__ double pair_sum(double v) { return v + la::dpp_d<la::DPP_XOR1>(v); }
 
 // Over the 64 lanes of a wave: the largest `best` (ties to the smaller index) and the sum
 // of `sum`, returned wave-uniform. DPP inside rows of 16 lanes, then the four row results
@@ -280,7 +281,7 @@ __device__ __forceinline__ House householder(double n2, double2 alpha) {
   return H;
 }
 
-template <typename T, int SMX>
+template <typename T, int SMX, int G>
 __device__ __forceinline__ int zip_site_pair(char *arena, const SiteDims &sd, const T *__restrict__ Wl,
                                              const T *__restrict__ Al, double2 *C, T *Yout, double delta2,
                                              int kcap, int *code) {
@@ -289,7 +290,10 @@ __device__ __forceinline__ int zip_site_pair(char *arena, const SiteDims &sd, co
   const int wv = uni_i(tid >> 6);   // wave index, known to the compiler as wave-uniform
   const int chi = sd.chi, w0 = sd.w0, w1 = sd.w1, r0 = sd.r0, r1 = sd.r1;
   const int m = 2 * chi, p = w1 * r1;
-  const int c = tid >> 1, g = tid & 1;   // this lane's column and its half of the rows
+  static_assert(G == 2 || G == 4 || G == 8, "lanes per column");
+  static_assert(G * SMX <= MR, "a column's slots fit the candidate buffer");
+  const int c = tid / G, g = tid % G;   // this lane's column and its share of the rows
+  const int u = g & 1, gh = g >> 1;     // its rows are 2 ch + u with ch = gh (mod G / 2)
   double2 *cand = (double2 *)(arena + PL_CAND);
   CandInfo *info = (CandInfo *)(arena + PL_INFO);
   House *hinf = (House *)(arena + PL_HOUSE);
@@ -324,17 +328,17 @@ __device__ __forceinline__ int zip_site_pair(char *arena, const SiteDims &sd, co
   // with D[ch][w0][j][r1] = sum_r C[ch][w0][r] A[r][j][r1], both in the storage precision,
   // four ch at a time; D chunks alternate between two buffers, one barrier per chunk
   const bool cok = c < p;
-  // waves whose 32 columns all lie beyond p (most waves at typical ranks) hold no column of
-  // T: they skip the contraction's second product, the pivot search and the column updates,
-  // and only take part in the barriers and the row writes
-  const bool wcols = 32 * wv < p;
+  // waves whose 64 / G columns all lie beyond p hold no column of T: they skip the
+  // contraction's second product, the pivot search and the column updates, and only take
+  // part in the barriers and the row writes
+  const bool wcols = (64 / G) * wv < p;
   double2 t[SMX];
 #pragma unroll
   for (int sl = 0; sl < SMX; ++sl) t[sl] = cmk(0.0, 0.0);
   {
     const int wp = cok ? c / r1 : 0, rp = cok ? c - (c / r1) * r1 : 0;
 #pragma unroll
-    for (int ch0 = 0; ch0 < SMX; ch0 += 4) {
+    for (int ch0 = 0; ch0 < SMX * G / 2; ch0 += 4) {
       if (ch0 < chi) {
         T *Db = Dch + ((ch0 / 4) & 1) * dchunk;
         __syncthreads();   // staging done (first chunk) / this buffer's previous readers done
@@ -349,19 +353,21 @@ __device__ __forceinline__ int zip_site_pair(char *arena, const SiteDims &sd, co
         }
         __syncthreads();
         if (wcols) {
-          typename A::type acc[4];
+          // this lane's rows in the chunk: ch = ch0 + gh + (G / 2) e, in slot ch / (G / 2)
+          constexpr int NE = 8 / G;
+          typename A::type acc[NE];
 #pragma unroll
-          for (int e = 0; e < 4; ++e) acc[e] = A::zero();
+          for (int e = 0; e < NE; ++e) acc[e] = A::zero();
           for (int ww = 0; ww < w0; ++ww)
             for (int j = 0; j < 2; ++j) {
-              const T wvv = Wc[(ww * 4 + 2 * g + j) * w1 + wp];
+              const T wvv = Wc[(ww * 4 + 2 * u + j) * w1 + wp];
               const T *dd = Db + (ww * 2 + j) * r1 + rp;
 #pragma unroll
-              for (int cc = 0; cc < 4; ++cc) A::fma_(acc[cc], dd[cc * w0 * 2 * r1], wvv);
+              for (int e = 0; e < NE; ++e) A::fma_(acc[e], dd[(gh + (G / 2) * e) * w0 * 2 * r1], wvv);
             }
 #pragma unroll
-          for (int e = 0; e < 4; ++e)
-            if (cok && ch0 + e < chi) t[ch0 + e] = A::to(acc[e]);
+          for (int e = 0; e < NE; ++e)
+            if (cok && ch0 + gh + (G / 2) * e < chi) t[ch0 / (G / 2) + e] = A::to(acc[e]);
         }
       }
     }
@@ -373,10 +379,10 @@ __device__ __forceinline__ int zip_site_pair(char *arena, const SiteDims &sd, co
     double nz[2] = {0.0, 0.0};
 #pragma unroll
     for (int sl = 0; sl < SMX; ++sl) nz[sl & 1] += cabs2(t[sl]);
-    nrm = pair_sum(nz[0] + nz[1]);
+    nrm = la::grp_sum(nz[0] + nz[1], G);
   }
   const int kmax = m < p ? m : p;
-  const int hrows = (m + 1) >> 1;   // slots in use before any shift
+  const int hrows = (m + G - 1) / G;   // slots in use before any shift
 
   // Pivot choice for step i: publishes this wave's candidate, waits for the other waves',
   // and returns true when the factorisation stops at rank i (the same decision in every
@@ -386,15 +392,15 @@ __device__ __forceinline__ int zip_site_pair(char *arena, const SiteDims &sd, co
   double2 am = cmk(0.0, 0.0), scal = cmk(0.0, 0.0), ctau = cmk(0.0, 0.0);
   const double2 *X = cand;
   auto select = [&](int i) -> bool {
-    const int b = i & 1, j = i >> 1;
+    const int b = i & 1, j = i / G;
     double best = act ? nrm : -1.0, sum = (act && g == 0) ? nrm : 0.0;
     int bi = act ? c : 0x7fffffff;
     if (__ballot(act) != 0) wave_argmax_sum_uni(best, bi, sum);   // else already the reduction's result
     double2 *mine = cand + (b * PW + wv) * MR;
     CandInfo *inf = info + b * PW + wv;
     if (c == bi) {
-      // slot 0 is row 2 j + g: finished (zero), row i (x_i = alpha - beta) or the next row
-      const int r0w = 2 * j + g;
+      // slot 0 is row G j + g: finished (zero), row i (x_i = alpha - beta) or a later row
+      const int r0w = G * j + g;
       double2 v0 = t[0];
       if (r0w < i) v0 = cmk(0.0, 0.0);
       if (r0w == i) {
@@ -407,7 +413,7 @@ __device__ __forceinline__ int zip_site_pair(char *arena, const SiteDims &sd, co
       }
       mine[g] = v0;
 #pragma unroll
-      for (int sl = 1; sl < SMX; ++sl) mine[2 * sl + g] = t[sl];
+      for (int sl = 1; sl < SMX; ++sl) mine[G * sl + g] = t[sl];
     }
     if (bi == 0x7fffffff && lane == 0) {   // no candidate left in this wave
       CandInfo ci;
@@ -458,7 +464,7 @@ __device__ __forceinline__ int zip_site_pair(char *arena, const SiteDims &sd, co
   int i = 0;
   bool stop = select(0);
   while (!stop) {
-    const int j = i >> 1;
+    const int j = i / G;
     // slots holding rows >= i (and possibly one finished row); none in a wave with no
     // candidate column left, whose entries are not read again (it only writes its zeros of
     // row i of R)
@@ -470,11 +476,11 @@ __device__ __forceinline__ int zip_site_pair(char *arena, const SiteDims &sd, co
     double2 xv[XPRE ? SMX : 1];
     if constexpr (XPRE) {
 #pragma unroll
-      for (int sl = 0; sl < SMX; ++sl) xv[sl] = Xg[2 * sl];
+      for (int sl = 0; sl < SMX; ++sl) xv[sl] = Xg[G * sl];
     }
     auto xat = [&](int sl) -> double2 {
       if constexpr (XPRE) return xv[sl];
-      else return Xg[2 * sl];
+      else return Xg[G * sl];
     };
     // w_c = conj(tau) sum_r conj(v_r) T[r, c] with v = x scal, summed over the pair
     double2 pz[4];
@@ -487,21 +493,21 @@ __device__ __forceinline__ int zip_site_pair(char *arena, const SiteDims &sd, co
         for (int e = 0; e < 4; ++e) ccfma(pz[e], xat(4 * q4 + e), t[4 * q4 + e]);
       }
     double2 pw = cadd(cadd(pz[0], pz[1]), cadd(pz[2], pz[3]));
-    pw.x = pair_sum(pw.x);
-    pw.y = pair_sum(pw.y);
+    pw.x = la::grp_sum(pw.x, G);
+    pw.y = la::grp_sum(pw.y, G);
     const double2 ws = cmul(cscale(ctau, cabs2(scal)), pw);   // scal w_c
-    // row i of R, from slot 0 of lane i % 2
+    // row i of R, from slot 0 of lane i % G
     {
       const double2 x0 = xat(0);
       double2 r0v = t[0];
       r0v.x = fma(x0.y, ws.y, fma(-x0.x, ws.x, r0v.x));
       r0v.y = fma(-x0.y, ws.x, fma(-x0.x, ws.y, r0v.y));
-      if (cok && g == (i & 1)) C[(int64_t)i * p + c] = (c == pc) ? cmk(beta, 0.0) : (act ? r0v : cmk(0.0, 0.0));
+      if (cok && g == i % G) C[(int64_t)i * p + c] = (c == pc) ? cmk(beta, 0.0) : (act ? r0v : cmk(0.0, 0.0));
     }
-    // T <- H^H T; slot 0 holds row i (lane i % 2) or, after an even step, the row finished
-    // then (lane 0), neither of which counts towards the remaining norms
+    // T <- H^H T; slot 0 of lane g holds row G j + g: row i (g = i % G) or a row finished
+    // before it (g < i % G), neither of which counts towards the remaining norms
     double nz[2] = {0.0, 0.0};
-    const bool skip0 = (i & 1) || g == 0;
+    const bool skip0 = g <= i % G;
 #pragma unroll
     for (int q4 = 0; q4 < SMX / 4; ++q4)
       if (4 * q4 < live) {
@@ -517,20 +523,21 @@ __device__ __forceinline__ int zip_site_pair(char *arena, const SiteDims &sd, co
           if (sl > 0 || !skip0) nz[e & 1] = fma(y.y, y.y, fma(y.x, y.x, nz[e & 1]));
         }
       }
-    // after an odd step both lanes move their slots down by one (every slot moves: a copy
-    // bounded by the live count would become a memmove that keeps T out of registers)
-    if (i & 1) {
+    // after the last step of a group of G, every lane moves its slots down by one (every
+    // slot moves: a copy bounded by the live count would become a memmove that keeps T out
+    // of registers)
+    if (i % G == G - 1) {
 #pragma unroll
       for (int sl = 0; sl + 1 < SMX; ++sl) t[sl] = t[sl + 1];
       t[SMX - 1] = cmk(0.0, 0.0);
     }
-    nrm = pair_sum(nz[0] + nz[1]);
+    nrm = la::grp_sum(nz[0] + nz[1], G);
     if (c == pc) act = false;
     // reflector i for the Q accumulation: V[i][r] = v_r (zero above row i and below row m)
     if (tid < MR) {
       double2 v = cmk(0.0, 0.0);
       if (tid == i) v = cmk(1.0, 0.0);
-      else if (tid > i && tid < m) v = cmul(X[tid - 2 * j], scal);
+      else if (tid > i && tid < m) v = cmul(X[tid - G * j], scal);
       V[i * MR + tid] = v;
     }
     ++i;
@@ -542,7 +549,7 @@ __device__ __forceinline__ int zip_site_pair(char *arena, const SiteDims &sd, co
   // are summed with DPP. Reflector jj - 1 and its tau are loaded while reflector jj is
   // applied, so the LDS latency overlaps the arithmetic.
   {
-    constexpr int QS = SMX / 4;
+    constexpr int QS = (G * SMX / 8 < MR / 8) ? G * SMX / 8 : MR / 8;
     const int cq = tid >> 3, h = tid & 7;
     if (cq < k) {   // uniform over each group of eight lanes
       double2 qv[QS], vc[QS], vn[QS];
@@ -653,10 +660,13 @@ __global__ __launch_bounds__(CM_WG, 3) void k_zipup(TTView w, int w_slots, TTVie
       T *Yout = Yc + y.coff(b, l);
       int k;
       if (!last && pair_site_fits<T>(sd, chicap, zlds_bytes<T>()))
-        k = m <= 16   ? zip_site_pair<T, 8>(lds_arena, sd, Wl, Al, C, Yout, delta2, chicap, &code_sh)
-            : m <= 24 ? zip_site_pair<T, 12>(lds_arena, sd, Wl, Al, C, Yout, delta2, chicap, &code_sh)
-            : m <= 32 ? zip_site_pair<T, 16>(lds_arena, sd, Wl, Al, C, Yout, delta2, chicap, &code_sh)
-                      : zip_site_pair<T, SM>(lds_arena, sd, Wl, Al, C, Yout, delta2, chicap, &code_sh);
+        k = (p <= 32 && m <= 32) ? zip_site_pair<T, 4, 8>(lds_arena, sd, Wl, Al, C, Yout, delta2, chicap, &code_sh)
+            : (p <= 64 && m <= 32) ? zip_site_pair<T, 8, 4>(lds_arena, sd, Wl, Al, C, Yout, delta2, chicap, &code_sh)
+            : p <= 64            ? zip_site_pair<T, 12, 4>(lds_arena, sd, Wl, Al, C, Yout, delta2, chicap, &code_sh)
+            : m <= 16            ? zip_site_pair<T, 8, 2>(lds_arena, sd, Wl, Al, C, Yout, delta2, chicap, &code_sh)
+            : m <= 24            ? zip_site_pair<T, 12, 2>(lds_arena, sd, Wl, Al, C, Yout, delta2, chicap, &code_sh)
+            : m <= 32            ? zip_site_pair<T, 16, 2>(lds_arena, sd, Wl, Al, C, Yout, delta2, chicap, &code_sh)
+                                 : zip_site_pair<T, SM, 2>(lds_arena, sd, Wl, Al, C, Yout, delta2, chicap, &code_sh);
       else if (need <= (size_t)zlds_bytes<T>())
         k = zip_site<T>(lds_arena, sd, Wl, Al, C, D, Yout, last, delta2, chicap, sh, &code_sh);
       else

@@ -418,11 +418,13 @@ def test_vg_status_codes():
 
 @pytest.mark.parametrize("name", ["heston20_tol1e-12", "bs12rect_tol1e-13"])
 def test_zipup_site_paths_fp64(name):
-    """The zip-up compiles its register-resident pivot loop for 8, 12, 16 and 24 slots per
-    lane (2 chi <= 16, 24, 32, 48) and takes an LDS path above that. Heston at n = 20 and
-    tol 1e-12 carries bonds from 1 to 24 (every register loop); the rectangle-rule
-    Black–Scholes grid at tol 1e-13 reaches bonds above 24 (the LDS path). Prices through the
-    whole chain against the oracle."""
+    """The zip-up compiles its register-resident pivot loop with two lanes per column for 8,
+    12, 16 and 24 slots per lane (2 chi <= 16, 24, 32, 48), with four or eight lanes per
+    column for sites with w' r' <= 64 or <= 32, and takes an LDS path above 2 chi = 48.
+    Heston at n = 20 and tol 1e-12 carries bonds from 1 to 24 (the narrow sites take the wide
+    groups, the rest every two-lane loop); the rectangle-rule Black–Scholes grid at tol 1e-13
+    reaches bonds above 24 (the LDS path). Prices through the whole chain against the
+    oracle; the complex64 batch tests cover the wide groups at typical ranks."""
     say("zip-up site paths", name)
     p, tol = {"heston20_tol1e-12": (W.heston_n24().replace(n=20, eta=W.eta_rule(20)), 1e-12),
               "bs12rect_tol1e-13": (W.bs_rect_n12(), 1e-13)}[name]
