@@ -12,8 +12,8 @@
 // truncation is accurate; the following cm_tt_round makes the ranks optimal with SVDs.
 // The contraction runs in the storage precision (FP32 complex for CM_C64); the pivoted QR
 // runs in FP64. Sites with 2 chi <= 48 and w' r' <= 128 (the bulk of a pricing chain) keep
-// T in registers for the whole factorisation, each column on a pair of lanes
-// (zip_site_pair); other sites stage their matrices in LDS when they fit, otherwise in the
+// T in registers for the whole factorisation, each column on a group of two, four or eight
+// lanes (zip_site_pair); other sites stage their matrices in LDS when they fit, otherwise in the
 // workgroup's global slab.
 #include "cm_tt.h"
 
