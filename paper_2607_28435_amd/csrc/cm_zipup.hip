@@ -221,11 +221,16 @@ __device__ __forceinline__ double lane_d(double x, int l) {
 
 // Over the 64 lanes of a wave: the largest `best` (ties to the smaller index) and the sum
 // of `sum`, returned wave-uniform. DPP inside rows of 16 lanes, then the four row results
-// combined in a fixed order.
+// combined in a fixed order. `best` and `bi` are already equal on the G lanes of an aligned
+// group, so the stages inside a group exchange only `sum`.
+template <int G>
 __device__ __forceinline__ void wave_argmax_sum_uni(double &best, int &bi, double &sum) {
-  la::argmax_sum_step<la::DPP_XOR1>(best, bi, sum);
-  la::argmax_sum_step<la::DPP_XOR2>(best, bi, sum);
-  la::argmax_sum_step<la::DPP_HALF_MIRROR>(best, bi, sum);
+  if (G > 1) sum += la::dpp_d<la::DPP_XOR1>(sum);
+  else la::argmax_sum_step<la::DPP_XOR1>(best, bi, sum);
+  if (G > 2) sum += la::dpp_d<la::DPP_XOR2>(sum);
+  else la::argmax_sum_step<la::DPP_XOR2>(best, bi, sum);
+  if (G > 4) sum += la::dpp_d<la::DPP_HALF_MIRROR>(sum);
+  else la::argmax_sum_step<la::DPP_HALF_MIRROR>(best, bi, sum);
   la::argmax_sum_step<la::DPP_MIRROR>(best, bi, sum);
   double b = lane_d(best, 0), s = lane_d(sum, 0);
   int ix = __builtin_amdgcn_readlane(bi, 0);
@@ -395,7 +400,7 @@ __device__ __forceinline__ int zip_site_pair(char *arena, const SiteDims &sd, co
     const int b = i & 1, j = i / G;
     double best = act ? nrm : -1.0, sum = (act && g == 0) ? nrm : 0.0;
     int bi = act ? c : 0x7fffffff;
-    if (__ballot(act) != 0) wave_argmax_sum_uni(best, bi, sum);   // else already the reduction's result
+    if (__ballot(act) != 0) wave_argmax_sum_uni<G>(best, bi, sum);   // else already the reduction's result
     double2 *mine = cand + (b * PW + wv) * MR;
     CandInfo *inf = info + b * PW + wv;
     if (c == bi) {
