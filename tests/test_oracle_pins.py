@@ -356,10 +356,22 @@ def test_vg_moment_condition():
     assert not O.vg_moment_ok(p.replace(params=(0.3, 0.9, 0.5)), 2.5)
 
 
-def test_direct_truncated_dft_matches_full_fft():
-    p = W.heston_n24().replace(n=18)
+@pytest.mark.parametrize("name", ["heston18", "heston22_shortT", "bs16_rect", "merton20", "vg18"])
+def test_direct_truncated_dft_matches_full_fft(name):
+    """The truncated direct sum (the support of x found by doubling, Section 2.1's sum cut
+    where the tail is negligible) against numpy's FFT of the full vector: one-sided
+    (Simpson) and two-sided (rectangle) supports, the batched box's shortest maturity
+    (slowest decay of psi), jumps and a gamma clock long enough (T/nu = 12) for psi to
+    decay within the grid."""
+    p = {"heston18": W.heston_n24().replace(n=18),
+         "heston22_shortT": W.heston_batch(1, seed=3, n=22)[0].replace(T=0.1),
+         "bs16_rect": W.bs_rect_n12().replace(n=16, eta=W.eta_rule(16)),
+         "merton20": W.merton_big(20),
+         "vg18": W.vg_n20().replace(n=18, eta=W.eta_rule(18), T=2.0)}[name]
     u = W.window_strided(p, 300)
-    assert np.abs(O.prices_direct(p, u) - O.prices_dense(p)[u]).max() / p.S0 < 1e-12
+    full = O.prices_dense(p)[u]
+    assert len(O.support(p)) < 2 ** p.n   # the sum really is truncated
+    assert np.abs(O.prices_direct(p, u) - full).max() / p.S0 < 1e-12
 
 
 def test_heston_explosion_time_matches_riccati_blowup():
@@ -378,3 +390,47 @@ def test_heston_explosion_time_matches_riccati_blowup():
     assert abs(sol.t_events[0][0] - Ts) < 1e-5 * Ts
     # the whole batched-Heston parameter box keeps E[S^2.5] finite up to T = 2
     assert Ts > 2.0
+
+
+def _moment_riccati(kappa, sv, rho, om, t_end):
+    """Integrates dB/dt = sigma^2 B^2/2 + (rho sigma omega - kappa) B + omega(omega-1)/2,
+    B(0) = 0 (the log-moment coefficient of E[S_T^omega] under Heston); returns the
+    solution object, stopped where B passes 1e8 (the moment's blow-up)."""
+    def rhs(t, y):
+        return [0.5 * sv * sv * y[0] ** 2 + (rho * sv * om - kappa) * y[0] + 0.5 * om * (om - 1)]
+
+    ev = lambda t, y: y[0] - 1e8
+    ev.terminal = True
+    return integrate.solve_ivp(rhs, (0, t_end), [0.0], events=ev, rtol=1e-11, atol=1e-12)
+
+
+@pytest.mark.parametrize("kappa,sv,rho", [(0.5, 0.8, 0.5), (0.05, 0.3, 0.99)],
+                         ids=["D<0,k>0", "D>=0,k>0"])
+def test_heston_explosion_time_positive_correlation_branches(kappa, sv, rho):
+    """The explosion-time branches that positive correlation reaches (k = rho sigma omega -
+    kappa > 0): complex roots of the Riccati right-hand side (D < 0, the arctangent form
+    without the pi shift) and real roots (D >= 0, the logarithmic form), each against the
+    blow-up time of the moment ODE."""
+    om = 2.5
+    k = rho * sv * om - kappa
+    D = k * k - sv * sv * om * (om - 1.0)
+    assert k > 0 and ((D < 0) if rho == 0.5 else (D >= 0))
+    Ts = O.heston_explosion_time(kappa, sv, rho, om)
+    sol = _moment_riccati(kappa, sv, rho, om, 50.0)
+    assert len(sol.t_events[0]) == 1
+    assert abs(sol.t_events[0][0] - Ts) < 1e-5 * Ts
+
+
+def test_heston_explosion_time_infinite_branch():
+    """Strong mean reversion and negative correlation (D >= 0, k < 0): the moment ODE
+    settles on its stable root -(k + sqrt(D))/sigma^2 and never blows up, so T* is
+    infinite."""
+    kappa, sv, rho, om = 4.0, 0.1, -0.5, 2.5
+    k = rho * sv * om - kappa
+    D = k * k - sv * sv * om * (om - 1.0)
+    assert D >= 0 and k < 0
+    assert math.isinf(O.heston_explosion_time(kappa, sv, rho, om))
+    sol = _moment_riccati(kappa, sv, rho, om, 200.0)
+    assert len(sol.t_events[0]) == 0
+    root = (-k - math.sqrt(D)) / (sv * sv)
+    assert abs(sol.y[0, -1] - root) < 1e-8 * abs(root)
