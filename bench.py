@@ -221,7 +221,7 @@ def sampler_flops(rk, n, shots, ones):
 
 
 def qft_run(cm, torch, pr, strikes, shots, steps):
-    """The QFT-observable arm (Section 3.4) emulated on the output trains of the main
+    """The QFT-observable arm (Section 2.2) emulated on the output trains of the main
     workload: `shots` measurement outcomes per instance (uniforms drawn on the device
     from a seeded generator), outcome counts at the read-out strikes and the observable
     prices from them, next to the exact-probability observable read-out. The error of the
@@ -309,7 +309,7 @@ def paper_curves(cm, torch, n_lo, n_hi, dense_max, tol=1e-10, reps=3, shots=4096
         2^n complex array;
       - nrmse: over the grid strikes with 0.5 <= K/S0 <= 1.5 (at most 2^16 of them, evenly
         strided) against the Black–Scholes formula (Eq. error_measure);
-      - qft: the observable arm (Section 3.4) from the same y train: the statevector NRMSE
+      - qft: the observable arm (Section 2.2) from the same y train: the statevector NRMSE
         (exact probabilities, Eq. qft_observable_price with p_hat = p) and the NRMSE of the
         shot estimator with `shots` outcomes (seeded uniforms)."""
     rows = []

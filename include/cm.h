@@ -164,13 +164,18 @@ cm_status cm_build_qtt(const cm_problem *prob, int batch, double tol, int cap_ra
                        cm_tt_batch *x, int32_t *status, void *ws, size_t ws_bytes, void *stream);
 
 /* SFFT step (Section 3.2-3.3, Eq. complexity_TTO): y_b = Q_n x_b for every train b,
- * computed by a left-to-right zip-up contraction with truncated SVDs (relative tolerance
- * tol per bond, bonds <= cap_rank). w_by_n holds one operator per chain length: train n
- * of w_by_n is Q_n (so w_by_n->batch > n_max), built by cm_qft_mpo with cores 1..n-1
- * right-orthonormal; x must have cores 1..n-1 right-orthonormal (cm_build_qtt and
- * cm_tt_round leave them so). Contractions run in the storage precision (x->dtype ==
- * y->dtype == w_by_n->dtype); Householder QR and Jacobi SVD run in FP64.
- * y: trains with y->n[b] == x->n[b], d_out = 2, d_in = 1. status: device [batch].
+ * computed by a left-to-right zip-up contraction. At each site the contracted block
+ * T[(chi, u)][(w', r')] is factored by Householder QR with column pivoting, stopped at the
+ * first rank k whose exact remaining Frobenius tail is at most tol ||x|| / sqrt(n-1); Q_k
+ * becomes output core l (left-orthonormal) and R_k P^T the carry into site l+1. Bonds are
+ * at most min(cap_rank, 48); a site that would need more sets CM_E_RANKCAP (result still
+ * written). The SVD-optimal ranks come from the cm_tt_round that follows. w_by_n holds one
+ * operator per chain length: train n of w_by_n is Q_n (so w_by_n->batch > n_max), built by
+ * cm_qft_mpo with cores 1..n-1 right-orthonormal and bonds <= 24; x must have cores 1..n-1
+ * right-orthonormal (cm_build_qtt and cm_tt_round leave them so). Contractions run in the
+ * storage precision (x->dtype == y->dtype == w_by_n->dtype); the pivoted QR runs in FP64.
+ * y: trains with y->n[b] == x->n[b], d_out = 2, d_in = 1; on return y->flags =
+ * CM_TT_LEFT_ORTHO. status: device [batch].
  * Workspace: cm_workspace_bytes(CM_OP_SFFT_APPLY, batch, x->n_max, cap_rank, dtype). */
 cm_status cm_sfft_apply(const cm_tt_batch *w_by_n, const cm_tt_batch *x, double tol, int cap_rank,
                         cm_tt_batch *y, int32_t *status, void *ws, size_t ws_bytes, void *stream);
@@ -194,7 +199,7 @@ cm_status cm_tt_round(cm_tt_batch *t, double tol, int cap_rank, double *err_out,
 cm_status cm_readout_prices(const cm_tt_batch *y, const cm_problem *prob, const int64_t *strike_idx,
                             int nk, double *prices, int32_t *status, void *stream);
 
-/* Observable read-out with exact probabilities (Section 3.4, Eqs. qft_probabilities and
+/* Observable read-out with exact probabilities (Section 2.2, Eqs. qft_probabilities and
  * qft_observable_price with p_hat = p): the QFT measurement gives p_u = |y_u|^2 / ||x||^2,
  * which loses the phase of y_u, so the price is
  *   C_hat(k_u) = exp(-alpha k_u)/(s pi) * sqrt(M) * |y_u|,
@@ -203,7 +208,7 @@ cm_status cm_readout_prices(const cm_tt_batch *y, const cm_problem *prob, const 
 cm_status cm_readout_observable(const cm_tt_batch *y, const cm_problem *prob, const int64_t *strike_idx,
                                 int nk, double *prices, int32_t *status, void *stream);
 
-/* Emulated measurement of the QFT register (Section 3.4, Eq. qft_probabilities): R outcomes
+/* Emulated measurement of the QFT register (Section 2.2, Eq. qft_probabilities): R outcomes
  * per train b drawn from p_u = |y_u|^2 / ||y||^2 without forming the 2^n amplitudes, by
  * exact sequential conditional sampling from bit 0 (weight 1) upward: with the low t bits
  * fixed and q_0, q_1 the masses of the two continuations, bit t is 1 iff U_t (q_0 + q_1) >= q_0.

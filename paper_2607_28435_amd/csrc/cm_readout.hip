@@ -11,7 +11,7 @@
 // The price is
 //   C(k_u) = Re[ exp(-alpha k_u)/(s pi) * exp(-i v0 k_u) * sqrt(M) * y_u ],
 // with exp(-i v0 k_u) = exp(-i v0 k0) (-1)^u for the symmetric rule and 1 for Simpson.
-// The observable mode (the measurement read-out of Section 3.4 with exact probabilities)
+// The observable mode (the measurement read-out of Section 2.2 with exact probabilities)
 // drops the phase: C(k_u) = exp(-alpha k_u)/(s pi) * sqrt(M) * |y_u|.
 #include <climits>
 

@@ -1,4 +1,4 @@
-// cm_sample_outcomes: measurement outcomes of the QFT register (Section 3.4, Eq.
+// cm_sample_outcomes: measurement outcomes of the QFT register (Section 2.2, Eq.
 // qft_probabilities) drawn from an SFFT output train without forming its 2^n amplitudes.
 //
 // Output core l carries outcome bit 2^l, so the probability mass of the outcomes whose low

@@ -254,18 +254,6 @@ struct House {
   double beta, pad;
 };
 static_assert(sizeof(House) == 64, "House layout");
-__device__ __forceinline__ double rcp_nr(double a) {
-  double y = __builtin_amdgcn_rcp(a);
-#pragma unroll
-  for (int it = 0; it < 2; ++it) y = fma(y, fma(-a, y, 1.0), y);
-  return y;
-}
-__device__ __forceinline__ double rsq_nr(double a) {
-  double y = __builtin_amdgcn_rsq(a);
-#pragma unroll
-  for (int it = 0; it < 2; ++it) y = fma(y, fma(-0.5 * a * y, y, 0.5), y);   // y (3 - a y^2) / 2
-  return y;
-}
 __device__ __forceinline__ House householder(double n2, double2 alpha) {
   House H;
   H.beta = 0.0;
@@ -274,12 +262,12 @@ __device__ __forceinline__ House householder(double n2, double2 alpha) {
   H.tau = cmk(0.0, 0.0);
   H.scal = cmk(0.0, 0.0);
   if (n2 > 0.0) {
-    const double rs = rsq_nr(n2);
+    const double rs = la::rsq_nr(n2);
     const double sg = alpha.x >= 0.0 ? 1.0 : -1.0;
     H.beta = -sg * (n2 * rs);
     const double ib = -sg * rs;   // 1 / beta
     H.am.x = alpha.x - H.beta;
-    const double id = rcp_nr(cabs2(H.am));
+    const double id = la::rcp_nr(cabs2(H.am));
     H.tau = cmk(1.0 - alpha.x * ib, -alpha.y * ib);
     H.scal = cmk(H.am.x * id, -H.am.y * id);
   }
@@ -549,14 +537,15 @@ __device__ __forceinline__ int zip_site_pair(char *arena, const SiteDims &sd, co
     stop = select(i);
   }
   const int k = i;
-  // Q = H_0 ... H_{k-1} [I_k; 0], barrier-free: column cq of Q on lanes 8 cq .. 8 cq + 7,
-  // lane h of the eight holding rows 8 s + h (s < SMX / 4, as m <= 2 SMX); the dot products
-  // are summed with DPP. Reflector jj - 1 and its tau are loaded while reflector jj is
-  // applied, so the LDS latency overlaps the arithmetic.
+  // Q = H_0 ... H_{k-1} [I_k; 0], barrier-free: column cq of Q on the eight lanes
+  // 8 (cq mod 32) .. 8 (cq mod 32) + 7 (a workgroup's 32 groups of eight take columns cq,
+  // cq + 32, ... up to k <= 48), lane h of the eight holding rows 8 s + h (s < SMX / 4, as
+  // m <= 2 SMX); the dot products are summed with DPP. Reflector jj - 1 and its tau are
+  // loaded while reflector jj is applied, so the LDS latency overlaps the arithmetic.
   {
     constexpr int QS = (G * SMX / 8 < MR / 8) ? G * SMX / 8 : MR / 8;
-    const int cq = tid >> 3, h = tid & 7;
-    if (cq < k) {   // uniform over each group of eight lanes
+    const int h = tid & 7;
+    for (int cq = tid >> 3; cq < k; cq += CM_WG / 8) {   // uniform over each group of eight lanes
       double2 qv[QS], vc[QS], vn[QS];
 #pragma unroll
       for (int sl = 0; sl < QS; ++sl) qv[sl] = cmk(8 * sl + h == cq ? 1.0 : 0.0, 0.0);

@@ -71,7 +71,7 @@ class SfftPricer:
     tol       : zip-up and rounding tolerance (relative Frobenius)
     build_tol : QTT construction tolerance (default tol/10)
     mpo_tol   : operator rounding tolerance (default tol/10)
-    cap       : bond capacity of x and y (zip-up bonds are limited to min(cap, 32))
+    cap       : bond capacity of x and y (zip-up bonds are limited to min(cap, 48))
     slots     : persistent workgroups per sweep op ({"build": s, "apply": s, "round": s});
                 None entries take the library default (see `autotune_slots`)
 
@@ -187,7 +187,7 @@ class SfftPricer:
         out.index_copy_(0, self._perm, rows)
         return out
 
-    # -- the QFT-observable arm (Section 3.4)
+    # -- the QFT-observable arm (Section 2.2)
     def observable(self, strikes):
         """Observable prices with exact probabilities, exp(-alpha k)/(s pi) sqrt(M) |y_u|, for
         device int64 strikes [batch, nk] (caller's order); returns float64 [batch, nk]."""

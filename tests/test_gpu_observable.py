@@ -1,4 +1,4 @@
-"""The QFT-observable arm on the GPU (Section 3.4), through the C ABI, against the oracle.
+"""The QFT-observable arm on the GPU (Section 2.2), through the C ABI, against the oracle.
 
 - cm_readout_observable: exp(-alpha k)/(s pi) sqrt(M) |y_u| against the oracle's
   exact-probability observable price (FP64 <= 1e-6 S0, complex64 <= 1e-4 S0), and the

@@ -341,6 +341,76 @@ def test_batched_heston_ragged_c64():
         assert np.abs(got[b] - ref).max() / p.S0 < C64_TOL, (b, p)
 
 
+def _oracle_rows(probs, strikes):
+    """The oracle's direct-sum prices of every instance (threads over instances: the sums
+    are vectorised numpy, which releases the interpreter lock)."""
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(8) as ex:
+        return list(ex.map(lambda a: O.prices_direct(a[0], a[1]), zip(probs, strikes)))
+
+
+def test_batched_heston_ragged_c64_every_n_16_to_28():
+    """The batched configuration's whole range of chain lengths in one ragged batch: two
+    seeded draws from the Heston box at every n in 16..28 (complex64 contraction, FP64
+    factorisations, tol 1e-8, bond cap 64), 256 near-money strikes each, every price within
+    1e-4 S0 of the oracle's FP64 direct sum. Cost grows linearly in n (Eq. complexity_TTO),
+    so n = 28 is the configuration's hardest chain."""
+    probs = []
+    for n in range(16, 29):
+        probs += W.heston_batch(2, seed=700 + n, n=n)
+    u = [W.near_money(p, 256) for p in probs]
+    say("ragged n=16..28:", len(probs), "instances")
+    pr = cm.SfftPricer(probs, cm.CM_C64, tol=1e-8, cap=64)
+    got = pr.run(_strikes_dev(u)).cpu().numpy()
+    for k, v in pr.statuses().items():
+        assert np.all(v == cm.CM_OK), (k, v)
+    refs = _oracle_rows(probs, u)
+    worst = 0.0
+    for b, p in enumerate(probs):
+        e = np.abs(got[b] - refs[b]).max() / p.S0
+        worst = max(worst, e)
+        assert e < C64_TOL, (b, p.n, e)
+    say("  worst error / S0", worst)
+
+
+def test_dense_c64_merton_n30_vs_series():
+    """The dense complex64 Stockham path on the 2^30-point Merton grid (8 GiB per pass
+    buffer, three passes), gathered at 4096 near-money strikes, against the Merton series."""
+    say("dense merton n30")
+    p = W.merton_big(30)
+    u = W.near_money(p, 4096)
+    got, st = cm.dense_prices([p], cm.CM_C64, strikes=_strikes_dev([u]))
+    assert st.cpu().numpy()[0] == cm.CM_OK
+    ref = O.merton_call(p, O.strike_of(p, u))
+    e = np.abs(got.double().cpu().numpy()[0] - ref).max() / p.S0
+    say("  max error / S0", e)
+    assert e < C64_TOL
+
+
+@pytest.mark.parametrize("kappa,sv,rho", [(0.5, 0.8, 0.5), (0.05, 0.3, 0.99), (4.0, 0.1, -0.5)],
+                         ids=["D<0,k>0", "D>=0,k>0", "D>=0,k<0"])
+def test_heston_moment_status_every_branch(kappa, sv, rho):
+    """The device's moment check (Eq. damping_moment_condition via the explosion time)
+    agrees with the oracle's T* on every branch: instances at 0.5 T* and 0.95 T* price (the
+    first against the oracle), one at 1.05 T* reports CM_E_MOMENT; with an infinite T*
+    every maturity prices. Both the SFFT build and the dense path."""
+    om = 2.5
+    Ts = O.heston_explosion_time(kappa, sv, rho, om)
+    Tm = [0.5 * Ts, 0.95 * Ts, 1.05 * Ts] if math.isfinite(Ts) else [0.5, 5.0, 30.0]
+    want = [cm.CM_OK, cm.CM_OK, cm.CM_E_MOMENT] if math.isfinite(Ts) else [cm.CM_OK] * 3
+    base = W.Problem("heston", "simpson1", 12, 100.0, 0.03, 0.0, 1.0, 1.5, 0.25, (kappa, 0.04, sv, rho, 0.04))
+    probs = [base.replace(T=float(T)) for T in Tm]
+    say("T* =", Ts, "maturities", Tm)
+    pr = cm.SfftPricer(probs, cm.CM_C128, tol=1e-10, cap=32)
+    u = np.stack([W.near_money(base, 16)] * 3)
+    got = pr.run(torch.from_numpy(u).cuda()).cpu().numpy()
+    assert pr.statuses()["build"].tolist() == want
+    _, dst = cm.dense_prices(probs, cm.CM_C128)
+    assert dst.cpu().numpy().tolist() == want
+    ref = O.prices_direct(probs[0], u[0])
+    assert np.abs(got[0] - ref).max() / base.S0 < FP64_TOL
+
+
 @pytest.mark.parametrize("n", [30, 40])
 def test_merton_large_grid_vs_series(n):
     """Merton, n = 30 and 40 (the 2^40 grid is never materialised): SFFT complex64 prices at
