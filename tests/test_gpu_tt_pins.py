@@ -88,13 +88,17 @@ def test_zipup_register_site_with_output_bond_above_32(dtype):
     assert err < (1e-10 if dtype == cm.CM_C128 else 1e-5)
 
 
-@pytest.mark.parametrize("dtype,n,tol", [(cm.CM_C128, 12, 1e-10), (cm.CM_C128, 20, 1e-10), (cm.CM_C64, 24, 1e-6)],
+@pytest.mark.parametrize("dtype,n,tol,round_tol", [(cm.CM_C128, 12, 1e-10, 1e-10), (cm.CM_C128, 20, 1e-10, 1e-10),
+                                                   (cm.CM_C64, 24, 1e-6, 1e-4)],
                          ids=["c128-n12", "c128-n20", "c64-n24"])
-def test_plane_wave_goes_to_rank_one_delta(dtype, n, tol):
+def test_plane_wave_goes_to_rank_one_delta(dtype, n, tol, round_tol):
     """A plane wave x_j = exp(2 pi i j m / M) is an exact rank-1 train (core l carries the
     factor exp(2 pi i m 2^(n-1-l) / M) for bit 1); its transform is sqrt(M) delta_{u,m}, again
     of rank 1, found by the output train at the bit-reversed position of m (Section 3.2:
-    Q_n omits the bit reversal)."""
+    Q_n omits the bit reversal). In complex64 the operator's truncation error (relative
+    Frobenius 1e-7, which for a single Fourier mode need not spread evenly) and FP32
+    rounding leave second singular values just above a 1e-6 rounding threshold, so the rank
+    is checked after rounding at the complex64 tolerance class (1e-4)."""
     M = 2 ** n
     rng = np.random.default_rng(n)
     ms = [int(rng.integers(0, M)) for _ in range(3)] + [0, M - 1]
@@ -111,7 +115,7 @@ def test_plane_wave_goes_to_rank_one_delta(dtype, n, tol):
     assert np.all(st == cm.CM_OK), st
     err = torch.zeros(len(xs), dtype=torch.float64, device="cuda")
     rst = torch.zeros(len(xs), dtype=torch.int32, device="cuda")
-    cm.cm_tt_round(y, tol, 32, err, rst, cm.Workspace())
+    cm.cm_tt_round(y, round_tol, 32, err, rst, cm.Workspace())
     torch.cuda.synchronize()
     assert np.all(rst.cpu().numpy() == cm.CM_OK)
     rk = y.ranks.cpu().numpy()[:, : n + 1]
