@@ -180,6 +180,26 @@ cm_status cm_build_qtt(const cm_problem *prob, int batch, double tol, int cap_ra
 cm_status cm_sfft_apply(const cm_tt_batch *w_by_n, const cm_tt_batch *x, double tol, int cap_rank,
                         cm_tt_batch *y, int32_t *status, void *ws, size_t ws_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): cm_sfft_apply without a workspace
+ * argument. The zip-up's per-workgroup slabs live in a fixed device array of
+ * cm_sfft_apply_noalloc_scratch_bytes() = 256 MiB that the library holds on every device
+ * it runs on until the process ends; the call allocates nothing (no hipMalloc, hipFree or
+ * allocating library routine). It runs min(batch, 256 MiB / slab) persistent workgroups,
+ * with slab = cm_workspace_bytes(CM_OP_SFFT_APPLY, 1, n_max, cap_rank, dtype) (about
+ * 2.5 MB at cap_rank 32, 7.4 MB at 64), so any batch size is accepted; a cap_rank whose
+ * single slab exceeds the array returns CM_E_UNSUPPORTED. Arguments, results and status
+ * codes are those of cm_sfft_apply, and the output equals its output bit for bit. Every
+ * call on a device shares that device's array: calls that overlap on one device (on
+ * different streams, or from different host threads) race and must be serialised by the
+ * caller. The first call on a device looks up the array's address there (a one-time
+ * hipGetSymbolAddress). */
+cm_status cm_sfft_apply_noalloc(const cm_tt_batch *w_by_n, const cm_tt_batch *x, double tol, int cap_rank,
+                                cm_tt_batch *y, int32_t *status, void *stream);
+
+/* Size in bytes of the fixed device array cm_sfft_apply_noalloc uses. */
+size_t cm_sfft_apply_noalloc_scratch_bytes(void);
+
 /* TT rounding (Oseledets 2011; the recompression of Section 3.1) in place: a QR sweep
  * left to right, then truncated SVDs right to left with per-bond threshold
  * tol * ||t|| / sqrt(n-1), bonds <= cap_rank. Afterwards cores 1..n-1 are

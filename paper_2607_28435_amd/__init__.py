@@ -77,6 +77,8 @@ def lib() -> C.CDLL:
         "cm_qft_mpo_table": (C.c_int, [C.c_int, C.c_int, f64, C.c_int, pb, vp, sz, vp]),
         "cm_build_qtt": (C.c_int, [vp, C.c_int, f64, C.c_int, pb, vp, vp, sz, vp]),
         "cm_sfft_apply": (C.c_int, [pb, pb, f64, C.c_int, pb, vp, vp, sz, vp]),
+        "cm_sfft_apply_noalloc": (C.c_int, [pb, pb, f64, C.c_int, pb, vp, vp]),
+        "cm_sfft_apply_noalloc_scratch_bytes": (sz, []),
         "cm_tt_round": (C.c_int, [pb, f64, C.c_int, vp, vp, vp, sz, vp]),
         "cm_readout_prices": (C.c_int, [pb, vp, vp, C.c_int, vp, vp, vp]),
         "cm_readout_observable": (C.c_int, [pb, vp, vp, C.c_int, vp, vp, vp]),
@@ -104,7 +106,8 @@ def lib() -> C.CDLL:
 
 def exported_symbols() -> List[str]:
     return ["cm_tt_layout", "cm_workspace_bytes", "cm_qft_mpo", "cm_qft_mpo_table", "cm_build_qtt", "cm_sfft_apply",
-            "cm_tt_round", "cm_readout_prices", "cm_readout_observable", "cm_sample_outcomes",
+            "cm_sfft_apply_noalloc", "cm_sfft_apply_noalloc_scratch_bytes", "cm_tt_round", "cm_readout_prices",
+            "cm_readout_observable", "cm_sample_outcomes",
             "cm_shot_prices", "cm_fft_price", "cm_mlp_act_bytes", "cm_mlp_sync_bf16",
             "cm_mlp_forward", "cm_mlp_backward", "cm_mlp_mse", "cm_adam_step", "cm_surrogate_gate",
             "cm_status_str", "cm_version"]
@@ -326,6 +329,19 @@ def cm_sfft_apply(w_by_n: TTBatch, x: TTBatch, tol: float, cap_rank: int, y: TTB
     code = lib().cm_sfft_apply(C.byref(w_by_n.struct), C.byref(x.struct), tol, cap_rank, C.byref(y.struct),
                                _ptr(status), _ptr(buf), need, _stream_ptr(stream))
     return _check(code, "cm_sfft_apply")
+
+
+def cm_sfft_apply_noalloc(w_by_n: TTBatch, x: TTBatch, tol: float, cap_rank: int, y: TTBatch, status,
+                          stream=None) -> int:
+    """cm_sfft_apply with the library's fixed device scratch array instead of a workspace
+    (the call allocates nothing)."""
+    code = lib().cm_sfft_apply_noalloc(C.byref(w_by_n.struct), C.byref(x.struct), tol, cap_rank, C.byref(y.struct),
+                                       _ptr(status), _stream_ptr(stream))
+    return _check(code, "cm_sfft_apply_noalloc")
+
+
+def cm_sfft_apply_noalloc_scratch_bytes() -> int:
+    return int(lib().cm_sfft_apply_noalloc_scratch_bytes())
 
 
 def cm_tt_round(t: TTBatch, tol: float, cap_rank: int, err_out, status, ws: Workspace, stream=None,

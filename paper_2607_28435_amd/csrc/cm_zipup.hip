@@ -15,6 +15,8 @@
 // T in registers for the whole factorisation, each column on a group of two, four or eight
 // lanes (zip_site_pair); other sites stage their matrices in LDS when they fit, otherwise in the
 // workgroup's global slab.
+#include <mutex>
+
 #include "cm_tt.h"
 
 namespace {
@@ -685,8 +687,10 @@ extern "C" size_t cm_zip_slab_bytes(int cap) {
 
 extern "C" int cm_slots_for_ws(int op, int batch, int n_max, int cap_rank, int dtype, size_t ws_bytes);
 
-extern "C" cm_status cm_sfft_apply(const cm_tt_batch *w_by_n, const cm_tt_batch *x, double tol, int cap_rank,
-                                   cm_tt_batch *y, int32_t *status, void *ws, size_t ws_bytes, void *stream) {
+// Validates the arguments of cm_sfft_apply and launches the zip-up over `ws` (one persistent
+// workgroup per slab of cm_zip_slab_bytes(cap_rank) bytes, at most one per instance).
+static cm_status zip_apply(const cm_tt_batch *w_by_n, const cm_tt_batch *x, double tol, int cap_rank, cm_tt_batch *y,
+                           int32_t *status, void *ws, size_t ws_bytes, void *stream) {
   if (!w_by_n || !x || !y || !(tol > 0.0) || cap_rank < 1 || cap_rank > 64) return CM_E_INVALID;
   if (x->batch < 0 || y->batch < x->batch) return CM_E_INVALID;
   if (x->batch == 0) return CM_OK;
@@ -715,4 +719,53 @@ extern "C" cm_status cm_sfft_apply(const cm_tt_batch *w_by_n, const cm_tt_batch 
   CM_LAUNCH_CHECK();
   y->flags = CM_TT_LEFT_ORTHO;
   return CM_OK;
+}
+
+extern "C" cm_status cm_sfft_apply(const cm_tt_batch *w_by_n, const cm_tt_batch *x, double tol, int cap_rank,
+                                   cm_tt_batch *y, int32_t *status, void *ws, size_t ws_bytes, void *stream) {
+  return zip_apply(w_by_n, x, tol, cap_rank, y, status, ws, ws_bytes, stream);
+}
+
+// ---- allocation-free variant -----------------------------------------------------------
+// The zip-up's per-workgroup slabs come from a fixed device array instead of a caller
+// workspace. In host code `scratch` names a host-side stand-in, not device memory: its
+// device address is looked up once per device with hipGetSymbolAddress (each device holds
+// its own copy of the array) and only that address is passed to kernels. The kernel writes
+// every slab word it reads for an instance before reading it, so nothing needs clearing
+// between calls; calls that overlap on one device share the array and race.
+constexpr size_t ZIP_NOALLOC_BYTES = (size_t)256 << 20;
+static __device__ __align__(256) char scratch[ZIP_NOALLOC_BYTES];
+
+namespace {
+constexpr int ZIP_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[ZIP_MAX_DEVICES] = {};
+
+cm_status zip_scratch(void **out) {
+  int dev = 0;
+  CM_HIP_CHECK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= ZIP_MAX_DEVICES) return CM_E_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void *p = nullptr;
+    CM_HIP_CHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (p == nullptr) return CM_E_HIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return CM_OK;
+}
+}  // namespace
+
+extern "C" size_t cm_sfft_apply_noalloc_scratch_bytes(void) { return ZIP_NOALLOC_BYTES; }
+
+extern "C" cm_status cm_sfft_apply_noalloc(const cm_tt_batch *w_by_n, const cm_tt_batch *x, double tol, int cap_rank,
+                                           cm_tt_batch *y, int32_t *status, void *stream) {
+  if (cap_rank < 1 || cap_rank > 64) return CM_E_INVALID;
+  if (cm_zip_slab_bytes(cap_rank) > ZIP_NOALLOC_BYTES) return CM_E_UNSUPPORTED;
+  if (x && x->batch == 0) return zip_apply(w_by_n, x, tol, cap_rank, y, status, nullptr, 0, stream);
+  void *ptr = nullptr;
+  const cm_status e = zip_scratch(&ptr);
+  if (e != CM_OK) return e;
+  return zip_apply(w_by_n, x, tol, cap_rank, y, status, ptr, ZIP_NOALLOC_BYTES, stream);
 }
