@@ -428,6 +428,9 @@ def surrogate_run(cm, torch, steps):
     torch.cuda.synchronize()
     gen_s = time.perf_counter() - t0
     info = s.fit(X, Y, steps=steps, batch=8192, lr=2e-3, log_every=max(1, steps // 20))
+    t0 = time.perf_counter()
+    cal = s.calibrate(2 ** 15, seed=4001)
+    cal["seconds"] = time.perf_counter() - t0
     nq = 2 ** 20
     q = np.concatenate([W.surrogate_queries(nq - nq // 10, 5001), W.surrogate_queries(nq // 10, 5002, enlarge=0.2)])
     torch.cuda.synchronize()
@@ -455,7 +458,7 @@ def surrogate_run(cm, torch, steps):
     executed = flops + 2.0 * 3 * 65536 * nq   # the activation split runs the 256x256 layers twice
     ach = flops / net_s / 1e12
     return {"train_samples": int(len(Y)), "train_steps": info["steps"], "train_s": info["seconds"],
-            "data_gen_s": gen_s, "final_train_loss": info["final_loss"],
+            "data_gen_s": gen_s, "final_train_loss": info["final_loss"], "gate_calibration": cal,
             "eval_queries": nq, "accept_rate": float(acc.mean()), "in_box_accept_rate": float(acc[:nq - nq // 10].mean()),
             "in_gate_max_abs_err_over_S0": float(err[ok].max()), "in_gate_p999_abs_err_over_S0":
                 float(np.quantile(err[ok], 0.999)), "sfft_reference_failures": int((st != 0).sum()),

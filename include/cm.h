@@ -332,12 +332,19 @@ cm_status cm_adam_step(const cm_mlp *net, const float *grad, float *m, float *v,
 /* Surrogate decode and gate. The network output z[b] decodes to the price
  * y[b] = C/S0 = e^{z[b]} - out_eps when out_eps > 0 (a network trained on log(C/S0 + out_eps))
  * and y[b] = z[b] when out_eps == 0; y goes to price (device float [B], may be NULL).
- * accept[b] = 1 if every raw input x[b][i] lies in [lo[i], hi[i]] (host arrays of 7: the
- * trusted box) and y[b] violates the static no-arbitrage bounds
- * max(0, 1 - e^{k - r T}) <= C/S0 <= 1 by at most res_tol; else 0 (the caller prices those
- * queries with the SFFT path). */
+ * accept[b] = 1 iff all of:
+ *   - every raw input x[b][i] lies in [lo[i], hi[i]] (host arrays of 7: the trusted box);
+ *   - y[b] violates the static no-arbitrage bounds max(0, 1 - e^{k - r T}) <= C/S0 <= 1 by at
+ *     most res_tol;
+ *   - if cell_err is not NULL: the calibrated error of the query's cell is at most err_tol.
+ *     cell_err is a device float [nT][nk] table over the box's (T, k) rectangle (cell
+ *     iT = floor((T - lo[5]) / (hi[5] - lo[5]) nT), ik likewise from k = x[b][6], clamped to
+ *     the grid), holding the largest |network - SFFT| / S0 the caller measured on validation
+ *     queries in that cell; NULL skips this check.
+ * Otherwise accept[b] = 0 (the caller prices those queries with the SFFT path). */
 cm_status cm_surrogate_gate(const float *x, const float *z, int B, const float *lo, const float *hi, float r,
-                            float res_tol, float out_eps, float *price, int32_t *accept, void *stream);
+                            float res_tol, float out_eps, const float *cell_err, int nT, int nk, float err_tol,
+                            float *price, int32_t *accept, void *stream);
 
 /* Short English text for a status code (static storage). */
 const char *cm_status_str(cm_status s);

@@ -92,7 +92,8 @@ def lib() -> C.CDLL:
         "cm_mlp_mse": (C.c_int, [vp, vp, C.c_int, vp, vp, vp]),
         "cm_adam_step": (C.c_int, [C.POINTER(CmMlp), vp, vp, vp, C.c_int, C.c_float, C.c_float, C.c_float,
                                    C.c_float, vp]),
-        "cm_surrogate_gate": (C.c_int, [vp, vp, C.c_int, vp, vp, C.c_float, C.c_float, C.c_float, vp, vp, vp]),
+        "cm_surrogate_gate": (C.c_int, [vp, vp, C.c_int, vp, vp, C.c_float, C.c_float, C.c_float, vp, C.c_int,
+                                        C.c_int, C.c_float, vp, vp, vp]),
         "cm_status_str": (C.c_char_p, [C.c_int]),
         "cm_version": (C.c_char_p, []),
     }
@@ -425,12 +426,14 @@ def cm_adam_step(net: CmMlp, grad, m, v, step: int, lr: float, beta1: float = 0.
 
 
 def cm_surrogate_gate(x, z, B: int, lo: Sequence[float], hi: Sequence[float], r: float, res_tol: float, accept,
-                      out_eps: float = 0.0, price=None, stream=None) -> int:
+                      out_eps: float = 0.0, price=None, cell_err=None, err_tol: float = 0.0, stream=None) -> int:
+    """cell_err: optional device float32 [nT, nk] calibrated error table over (T, k)."""
     lo_a = (C.c_float * 7)(*[float(v) for v in lo])
     hi_a = (C.c_float * 7)(*[float(v) for v in hi])
+    nT, nk = (int(cell_err.shape[0]), int(cell_err.shape[1])) if cell_err is not None else (0, 0)
     code = lib().cm_surrogate_gate(_ptr(x), _ptr(z), int(B), C.cast(lo_a, C.c_void_p), C.cast(hi_a, C.c_void_p),
-                                   float(r), float(res_tol), float(out_eps), _ptr(price), _ptr(accept),
-                                   _stream_ptr(stream))
+                                   float(r), float(res_tol), float(out_eps), _ptr(cell_err), nT, nk, float(err_tol),
+                                   _ptr(price), _ptr(accept), _stream_ptr(stream))
     return _check(code, "cm_surrogate_gate")
 
 

@@ -390,8 +390,17 @@ struct GateBox {
   float lo[NIN], hi[NIN];
 };
 
+// Validation error table of the gate: cell (iT, ik) of an nT x nk grid over the trusted
+// box's (T, k) rectangle holds the largest |network - SFFT| / S0 seen there.
+struct GateCells {
+  const float *err;
+  int nT, nk;
+  float tol;
+};
+
 __global__ void k_gate(const float *__restrict__ x, const float *__restrict__ z, int B, GateBox box, float r,
-                       float tol, float out_eps, float *__restrict__ price, int32_t *__restrict__ accept) {
+                       float tol, float out_eps, GateCells cells, float *__restrict__ price,
+                       int32_t *__restrict__ accept) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= B) return;
   bool ok = true;
@@ -404,6 +413,13 @@ __global__ void k_gate(const float *__restrict__ x, const float *__restrict__ z,
   const float lower = fmaxf(0.0f, 1.0f - expf(k - r * T));
   const float yb = out_eps > 0.0f ? expf(z[b]) - out_eps : z[b];
   const float res = fmaxf(fmaxf(lower - yb, yb - 1.0f), 0.0f);
+  if (ok && cells.err) {
+    // the query's (T, k) cell; in-box queries map into [0, n) (the upper edges clamp)
+    const float fT = (T - box.lo[5]) / (box.hi[5] - box.lo[5]), fk = (k - box.lo[6]) / (box.hi[6] - box.lo[6]);
+    const int iT = min(cells.nT - 1, max(0, (int)(fT * (float)cells.nT)));
+    const int ik = min(cells.nk - 1, max(0, (int)(fk * (float)cells.nk)));
+    ok = cells.err[iT * cells.nk + ik] <= cells.tol;
+  }
   if (price) price[b] = yb;
   accept[b] = (ok && res <= tol && yb == yb) ? 1 : 0;
 }
@@ -529,14 +545,20 @@ extern "C" cm_status cm_adam_step(const cm_mlp *net, const float *grad, float *m
 }
 
 extern "C" cm_status cm_surrogate_gate(const float *x, const float *z, int B, const float *lo, const float *hi,
-                                       float r, float res_tol, float out_eps, float *price, int32_t *accept,
-                                       void *stream) {
+                                       float r, float res_tol, float out_eps, const float *cell_err, int nT, int nk,
+                                       float err_tol, float *price, int32_t *accept, void *stream) {
   if (!x || !z || !lo || !hi || !accept || B < 0 || !(out_eps >= 0.0f)) return CM_E_INVALID;
+  if (cell_err && (nT < 1 || nk < 1 || nT > 4096 || nk > 4096 || !(err_tol >= 0.0f))) return CM_E_INVALID;
   if (B == 0) return CM_OK;
   GateBox box;
-  for (int i = 0; i < NIN; ++i) { box.lo[i] = lo[i]; box.hi[i] = hi[i]; }
+  for (int i = 0; i < NIN; ++i) {
+    box.lo[i] = lo[i];
+    box.hi[i] = hi[i];
+  }
+  if (cell_err && !(box.hi[5] > box.lo[5] && box.hi[6] > box.lo[6])) return CM_E_INVALID;
+  GateCells cells{cell_err, nT, nk, err_tol};
   hipLaunchKernelGGL(k_gate, dim3(grid_for(B, 256)), dim3(256), 0, (hipStream_t)stream, x, z, B, box, r, res_tol,
-                     out_eps, price, accept);
+                     out_eps, cells, price, accept);
   CM_LAUNCH_CHECK();
   return CM_OK;
 }

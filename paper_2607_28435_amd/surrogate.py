@@ -133,7 +133,9 @@ class Surrogate:
     """Gated surrogate over the trusted box [lo, hi] of (kappa, theta, sigma_v, rho, v0, T, k),
     k = ln(K/S0), for S0 and r fixed; SFFT prices (Simpson rule, n-point grids, alpha
     damping, complex64 contraction, tolerance tol) train and check it and price what the
-    gate rejects.
+    gate rejects. The gate accepts a query inside the box whose decoded price keeps the
+    no-arbitrage bounds and, once `calibrate` has run, whose (T, k) cell showed a
+    validation error within err_tol.
 
     The network is trained on a box `train_lo`/`train_hi` wider than the trusted one (by
     default 20 % of each width, clipped where the model stops being defined), so that no
@@ -153,6 +155,8 @@ class Surrogate:
         self.net = MlpNet(self.train_lo, self.train_hi, seed=seed, device=device)
         self._mpo = None
         self.history = []
+        self.cell_err = None      # calibrated (T, k) error table (device float32), see calibrate()
+        self.err_tol = 0.0
 
     def encode(self, price_over_s0: np.ndarray) -> np.ndarray:
         """Training target for C/S0 (the inverse of the gate's decoding)."""
@@ -273,6 +277,49 @@ class Surrogate:
         return {"steps": done, "seconds": time.perf_counter() - t0,
                 "final_loss": self.history[-1][1] if self.history else float("nan")}
 
+    # -- calibration of the gate
+    def cell_index(self, T: np.ndarray, k: np.ndarray, nT: int, nk: int) -> Tuple[np.ndarray, np.ndarray]:
+        """(T, k) cell of each query on an nT x nk grid over the trusted box, formed in
+        float32 exactly as the gate kernel forms it."""
+        f = np.float32
+        lo, hi = self.lo.astype(f), self.hi.astype(f)
+        fT = (np.asarray(T, dtype=f) - lo[5]) / (hi[5] - lo[5])
+        fk = (np.asarray(k, dtype=f) - lo[6]) / (hi[6] - lo[6])
+        iT = np.clip((fT * f(nT)).astype(np.int64), 0, nT - 1)
+        ik = np.clip((fk * f(nk)).astype(np.int64), 0, nk - 1)
+        return iT, ik
+
+    def calibrate(self, n_val: int = 2 ** 15, seed: int = 4001, err_tol: float = 5e-4,
+                  cells: Tuple[int, int] = (16, 16)) -> Dict[str, float]:
+        """Residual calibration of the gate on a validation split: n_val queries uniform in
+        the trusted box (a Philox stream of its own) are priced by the network and by the
+        SFFT path; the largest |network - SFFT| / S0 in each (T, k) cell becomes the cell's
+        error, and the gate then sends every query whose cell exceeds err_tol (by default
+        half the 1e-3 S0 target, a margin for points the validation did not see) to the
+        SFFT fallback. Cells without a validated query count as failed."""
+        torch = _torch()
+        nT, nk = cells
+        g = np.random.Generator(np.random.Philox(seed))
+        q = self.lo + (self.hi - self.lo) * g.random((n_val, 7))
+        q32 = q.astype(np.float32)
+        ref, st = self.query_prices(q32.astype(np.float64))
+        qd = torch.from_numpy(q32).to(self.device)
+        z = self.net.forward(qd)
+        y = torch.exp(z.double()) - self.out_eps if self.out_eps > 0 else z.double()
+        err = np.abs(y.cpu().numpy() - ref)
+        err = np.where((st == CM_OK) & np.isfinite(err), err, np.inf)
+        iT, ik = self.cell_index(q32[:, 5], q32[:, 6], nT, nk)
+        table = np.full((nT, nk), np.inf)
+        seen = np.zeros((nT, nk), dtype=bool)
+        seen[iT, ik] = True
+        table[seen] = 0.0
+        np.maximum.at(table, (iT, ik), err)
+        self.cell_err = torch.from_numpy(table.astype(np.float32)).to(self.device)
+        self.err_tol = float(err_tol)
+        return {"validation_queries": n_val, "cells": nT * nk, "cells_rejected": int((table > err_tol).sum()),
+                "validation_max_err": float(err[np.isfinite(err)].max()),
+                "validation_reference_failures": int((st != CM_OK).sum())}
+
     # -- inference
     def predict(self, queries_dev):
         """Decoded network price and gate for device float32 queries [B, 7]:
@@ -283,7 +330,7 @@ class Surrogate:
         price = torch.empty(B, dtype=torch.float32, device=queries_dev.device)
         acc = torch.empty(B, dtype=torch.int32, device=queries_dev.device)
         cm_surrogate_gate(queries_dev, z, B, self.lo.tolist(), self.hi.tolist(), self.r, self.res_tol, acc,
-                          out_eps=self.out_eps, price=price)
+                          out_eps=self.out_eps, price=price, cell_err=self.cell_err, err_tol=self.err_tol)
         return price, acc
 
     def price(self, queries: np.ndarray) -> Dict[str, np.ndarray]:

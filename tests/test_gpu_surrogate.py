@@ -3,9 +3,13 @@ against the CPU FP64 reference (oracle/mlp.py), and the gated surrogate end to e
 
 Tolerances: the 256 x 256 layers multiply BF16 weights (the reference uses the same
 BF16-rounded weights) by activations split into two BF16 parts (relative rounding about
-2^-17) with FP32 accumulation, so the forward pass matches to ~1e-5 relative; the weight
-gradients multiply single-BF16 activations (relative 2^-9 per product), so gradient blocks
-match to 1e-2 in relative Frobenius norm."""
+2^-17) with FP32 accumulation, so the forward pass matches to ~1e-5 relative. The weight
+gradients g_ij = sum_b delta_i[b] a_j[b] multiply the split delta (2^-17) by single-BF16
+activations (round to nearest: relative 2^-9), so every element is checked against
+|g - g_ref| <= 2^-8 sum_b |delta_i[b]| |a_j[b]|: the 2^-9 of the activation operand plus
+about as much again for the FP32 accumulation over the batch and the ~2^-12 relative
+error delta and a carry from the chain (both measured on the reference's own delta and
+a)."""
 import math
 import sys
 import time
@@ -84,8 +88,27 @@ def test_mlp_forward_keep_matches_inference():
     assert torch.equal(y1, y2)
 
 
+def _abs_products(theta, xn, zs, dy):
+    """sum_b |delta_i[b]| |a_j[b]| for every weight block and sum_b |delta_i[b]| for every
+    bias, from the reference's own per-sample deltas (dL/dz of each layer) and activations:
+    the scale the elementwise bound of each gradient entry is relative to."""
+    p = R.unpack(theta)
+    acts = [np.asarray(xn, dtype=np.float64)] + [R.silu(z) for z in zs]
+    dy = np.asarray(dy, dtype=np.float64).reshape(-1, 1)
+    out = {"W5": np.abs(dy).T @ np.abs(acts[4]), "b5": np.abs(dy).sum(axis=0)}
+    delta = (dy @ p["W5"]) * R.silu_grad(zs[3])
+    for l in range(4, 0, -1):
+        out[f"W{l}"] = np.abs(delta).T @ np.abs(acts[l - 1])
+        out[f"b{l}"] = np.abs(delta).sum(axis=0)
+        if l >= 2:
+            delta = (delta @ p[f"W{l}"]) * R.silu_grad(zs[l - 2])
+    return out
+
+
 @pytest.mark.parametrize("B", [64, 1000])
 def test_mlp_backward_matches_reference(B):
+    """Every gradient entry against the FP64 reference within 2^-8 of its absolute-product
+    scale (module docstring); each block as a whole within 2^-8 relative (Frobenius)."""
     say("mlp backward", B)
     net, xd, theta, xn = _net_and_inputs(B, seed=5, scale_hidden=3.0)
     rng = np.random.default_rng(B)
@@ -100,11 +123,15 @@ def test_mlp_backward_matches_reference(B):
     cm.cm_mlp_backward(net.struct, xd, acts, dyd, B, grad, ws, nb // 2)
     g = R.unpack(grad.double().cpu().numpy())
     _, zs = R.forward(theta, xn)
-    ref = R.unpack(R.backward(theta, xn, zs, dy.astype(np.float32).astype(np.float64)))
+    dy64 = dy.astype(np.float32).astype(np.float64)
+    ref = R.unpack(R.backward(theta, xn, zs, dy64))
+    scale = _abs_products(theta, xn, zs, dy64)
     for name, _shape in R._SHAPES:
+        ratio = np.abs(g[name] - ref[name]) / np.maximum(scale[name], 1e-300)
         e = np.linalg.norm(g[name] - ref[name]) / max(1e-30, np.linalg.norm(ref[name]))
-        say("  ", name, "rel", e)
-        assert e < 1e-2, name
+        say("  ", name, "max err / scale", ratio.max(), "(bound 2^-8 = 3.9e-3), relative norm", e)
+        assert ratio.max() <= 2.0 ** -8, name
+        assert e < 2.0 ** -8, name
 
 
 def test_mse_and_adam_match_reference():
@@ -171,6 +198,40 @@ def test_gate_box_and_bounds():
     assert acc.cpu().numpy().astype(bool).tolist() == want
 
 
+def test_gate_calibrated_cell_table():
+    """The calibrated residual check: a query is sent to the fallback when the validation
+    error of its (T, k) cell exceeds err_tol, wherever else it stands; cells index the
+    trusted box's (T, k) rectangle, with the upper edges clamped into the last cell."""
+    lo, hi = W.surrogate_box()
+    r = 0.03
+    nT, nk = 4, 8
+    table = np.full((nT, nk), 1e-4, dtype=np.float32)
+    table[1, 6] = 2e-3          # one cell above err_tol
+    table[3, 7] = np.inf        # one cell without validation data
+    mid = (lo + hi) / 2
+
+    def at(fT, fk):
+        x = mid.copy()
+        x[5] = lo[5] + fT * (hi[5] - lo[5])
+        x[6] = lo[6] + fk * (hi[6] - lo[6])
+        return x
+    rows = [at(0.3, 0.8), at(0.3, 0.7), at(0.1, 0.8), at(1.0, 1.0), at(0.9, 0.9), at(0.0, 0.0), at(0.6, 0.2)]
+    want = [False, True, True, False, False, True, True]
+    xs = np.array(rows, dtype=np.float32)
+    lower = np.maximum(0.0, 1 - np.exp(xs[:, 6].astype(np.float64) - r * xs[:, 5]))
+    ys = (lower + 0.02).astype(np.float32)      # inside the no-arbitrage band
+    xd = torch.from_numpy(xs).cuda()
+    yd = torch.from_numpy(ys).cuda()
+    acc = torch.empty(len(rows), dtype=torch.int32, device="cuda")
+    cells = torch.from_numpy(table).cuda()
+    cm.cm_surrogate_gate(xd, yd, len(rows), lo.astype(np.float32).tolist(), hi.astype(np.float32).tolist(), r, 1e-3,
+                         acc, cell_err=cells, err_tol=5e-4)
+    assert acc.cpu().numpy().astype(bool).tolist() == want
+    cm.cm_surrogate_gate(xd, yd, len(rows), lo.astype(np.float32).tolist(), hi.astype(np.float32).tolist(), r, 1e-3,
+                         acc)   # without the table every row is accepted
+    assert acc.cpu().numpy().all()
+
+
 def test_query_prices_shifted_grid_vs_oracle():
     """The fallback prices each query at exactly its k by shifting k0 so that strike index
     M/2 is k: checked against the oracle's direct DFT on the same shifted grids."""
@@ -190,33 +251,37 @@ def test_query_prices_shifted_grid_vs_oracle():
 
 
 def test_surrogate_trains_gates_and_beats_sfft():
-    """A short training run on SFFT prices: the loss falls by 50x, in-box held-out
-    queries land within 2e-2 S0 of the SFFT reference (a short run; the full-size training
-    and its 1e-3 target are measured by bench.py), out-of-box queries go to the fallback
-    (whose prices are the SFFT's), and the network answers the same queries more than 10x
-    faster than batched SFFT pricing of them."""
+    """The surrogate's recipe end to end on the GPU's own kernels: 2^22 SFFT training samples
+    (2^16 parameter draws over the widened box x 64 log-moneyness values), 60 000 Adam
+    steps, the gate calibrated on 2^15 validation queries (cells above 5e-4 S0 fall back).
+    On 2^16 held-out queries in the trusted box every accepted price lies within 1e-3 S0
+    of the SFFT reference (the target), at least 90 % are accepted; out-of-box queries go
+    to the fallback, whose prices are the SFFT's; the network answers the in-box queries
+    more than 10x faster than batched SFFT pricing of them."""
     say("surrogate train")
     lo, hi = W.surrogate_box()
     s = Surrogate(lo, hi, seed=0)
-    X, Y = s.training_set(4096, 32, seed=5)
-    info = s.fit(X, Y, steps=6000, batch=4096, lr=2e-3, log_every=500)
+    X, Y = s.training_set(2 ** 16, 64, seed=1001)
+    info = s.fit(X, Y, steps=60000, batch=8192, lr=2e-3, log_every=5000)
     h = s.history
     say("  loss", h[0][1], "->", h[-1][1], info)
     assert h[-1][1] < h[0][1] / 50
-    q_in = W.surrogate_queries(2000, 77)
-    q_out = W.surrogate_queries(200, 78, enlarge=0.4)
+    cal = s.calibrate(2 ** 15, seed=4001)
+    say("  calibration", cal)
+    q_in = W.surrogate_queries(2 ** 16, 5001)
+    q_out = W.surrogate_queries(2000, 78, enlarge=0.4)
     outside = np.any((q_out < lo) | (q_out > hi), axis=1)
-    q = np.concatenate([q_in, q_out[outside][:50]])
+    q = np.concatenate([q_in, q_out[outside][:500]])
     res = s.price(q)
     ref_prices, st = s.query_prices(q)
     n_in = len(q_in)
     acc = res["accept"]
-    assert acc[:n_in].mean() > 0.95
-    assert not acc[n_in:].any()
     ok = acc & (st == cm.CM_OK)
     err = np.abs(res["price"][ok] - ref_prices[ok]).max()
     say("  max err in gate", err, "accept rate", acc[:n_in].mean())
-    assert err < 2e-2
+    assert acc[:n_in].mean() > 0.9
+    assert not acc[n_in:].any()
+    assert err <= 1e-3
     fb = (~acc) & (st == cm.CM_OK)
     assert np.allclose(res["price"][fb], ref_prices[fb], rtol=0, atol=1e-12)
     # speed: network vs batched SFFT on the same in-box queries
