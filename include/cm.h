@@ -268,7 +268,10 @@ cm_status cm_shot_prices(const cm_problem *prob, int batch, const double *norm2,
  * otherwise strike_idx is device int64 [batch][nk] and prices is [batch][nk] (gathered).
  * prices holds float for CM_C64 and double for CM_C128. status: device [batch] (may be
  * NULL); a problem that fails its checks gets its code there and NaN prices.
- * Workspace: cm_workspace_bytes(CM_OP_FFT_PRICE, batch, n, 0, dtype). */
+ * Workspace: cm_workspace_bytes(CM_OP_FFT_PRICE, batch, n, 0, dtype). Instances run in launch
+ * groups whose pass buffers live in the workspace (one instance per group from n = 22 up,
+ * 2^(22-n) below); a larger workspace widens the groups to the largest instance count whose
+ * buffers fit (the results are the same). */
 cm_status cm_fft_price(const cm_problem *prob, int batch, int n, int dtype, const int64_t *strike_idx,
                        int nk, void *prices, int32_t *status, void *ws, size_t ws_bytes, void *stream);
 

@@ -621,13 +621,26 @@ extern "C" size_t cm_fft_ws_bytes(int batch, int n, int dtype, int gather) {
   return fft_ws_bytes(p, dtype, gather != 0, batch);
 }
 
+// The plan for a workspace of ws_bytes: the default launch group, widened to the largest
+// instance count (at most the batch and MAX_CHUNK) whose pass buffers still fit.
+__host__ inline FftPlan plan_for_ws(int n, int dtype, int batch, bool gather, size_t ws_bytes) {
+  FftPlan p = make_plan(n, dtype, batch);
+  while (p.chunk < batch && p.chunk < MAX_CHUNK) {
+    FftPlan q = p;
+    q.chunk = p.chunk + 1;
+    if (fft_ws_bytes(q, dtype, gather, batch) > ws_bytes) break;
+    p = q;
+  }
+  return p;
+}
+
 template <typename T>
 static cm_status fft_run(const cm_problem *prob, int batch, int n, const int64_t *strike_idx, int nk, void *prices,
-                         int32_t *status, void *ws, hipStream_t s) {
+                         int32_t *status, void *ws, size_t ws_bytes, hipStream_t s) {
   using P = typename price_t<T>::type;
   const int dtype = sizeof(T) == 8 ? CM_C64 : CM_C128;
-  FftPlan p = make_plan(n, dtype, batch);
   const bool gather = strike_idx != nullptr;
+  FftPlan p = plan_for_ws(n, dtype, batch, gather, ws_bytes);
   const int64_t M = (int64_t)1 << n;
   char *w = (char *)ws;
   DenseProb<T> *dp = (DenseProb<T> *)w;
@@ -696,6 +709,6 @@ extern "C" cm_status cm_fft_price(const cm_problem *prob, int batch, int n, int 
       if (((int64_t)1 << (n - p.logr[ps])) < FFT_COLS) return CM_E_UNSUPPORTED;
   }
   hipStream_t s = (hipStream_t)stream;
-  if (dtype == CM_C64) return fft_run<float2>(prob, batch, n, strike_idx, nk, prices, status, ws, s);
-  return fft_run<double2>(prob, batch, n, strike_idx, nk, prices, status, ws, s);
+  if (dtype == CM_C64) return fft_run<float2>(prob, batch, n, strike_idx, nk, prices, status, ws, ws_bytes, s);
+  return fft_run<double2>(prob, batch, n, strike_idx, nk, prices, status, ws, ws_bytes, s);
 }
