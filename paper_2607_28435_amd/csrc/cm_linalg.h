@@ -125,11 +125,11 @@ struct Sh {
   double err2;
   double sig2[64];
   int perm[64];
-  double2 tau[128];
+  double2 tau[64];
 };
 
 // In-place Householder QR of the first s columns of Y (m rows, ntot >= s columns,
-// lda >= m, s <= min(m, 128)); the reflectors are also applied to columns s..ntot-1.
+// lda >= m, s <= min(m, 64)); the reflectors are also applied to columns s..ntot-1.
 // R lies on and above the diagonal (real diagonal), reflector tails below it, tau[c] in
 // sh.tau. Reflector H_c = I - tau_c v v^H with v = (0..0, 1, Y[c+1:, c]);
 // Q = H_0 H_1 ... H_{s-1}.
@@ -212,6 +212,67 @@ __device__ __forceinline__ void qr_apply_q(const double2 *Y, int lda, int m, int
     }
     __syncthreads();
   }
+}
+
+// Qk (m x k, ld m) = H_0 ... H_{k-1} [I_k; 0] from the reflector tails below the diagonal of T
+// (ld m, read only) and sh.tau, without barriers: column j of Qk lives in the registers of a
+// group of G lanes (lane g holding rows g, g + G, ..., NR of them; G the smallest power of two
+// with G NR >= m, and at least group_for(k)), which applies the k reflectors from the last to
+// the first, summing each inner product over the group with DPP; the 64 / G groups take the
+// columns in passes. Needs m <= 64 NR.
+template <int NR>
+__device__ __forceinline__ void qr_form_q_reg(const double2 *T, int m, int k, const Sh &sh, double2 *Qk) {
+  const int tid = threadIdx.x;
+  int G = group_for(k);
+  while (G * NR < m) G *= 2;
+  const int groups = CM_WG / G, g = tid % G;
+  for (int jb = 0; jb < k; jb += groups) {   // uniform
+    const int j = jb + tid / G;
+    const bool ok = j < k;   // uniform over each group
+    double2 q[NR];
+#pragma unroll
+    for (int s = 0; s < NR; ++s) q[s] = cmk((ok && g + G * s == j) ? 1.0 : 0.0, 0.0);
+    for (int c = k - 1; c >= 0; --c) {
+      const double2 tc = sh.tau[c];
+      if (tc.x == 0.0 && tc.y == 0.0) continue;   // uniform
+      // v_r = T[r, c] below the diagonal, 1 on it, 0 above
+      double2 v[NR];
+      double2 w = cmk(0.0, 0.0);
+#pragma unroll
+      for (int s = 0; s < NR; ++s) {
+        const int r = g + G * s;
+        v[s] = (r > c && r < m) ? T[r + (int64_t)m * c] : cmk(r == c ? 1.0 : 0.0, 0.0);
+        ccfma(w, v[s], q[s]);
+      }
+      w.x = grp_sum(w.x, G);
+      w.y = grp_sum(w.y, G);
+      w = cmul(tc, w);
+#pragma unroll
+      for (int s = 0; s < NR; ++s) q[s] = csub(q[s], cmul(v[s], w));
+    }
+    if (ok) {
+#pragma unroll
+      for (int s = 0; s < NR; ++s) {
+        const int r = g + G * s;
+        if (r < m) Qk[r + (int64_t)m * j] = q[s];
+      }
+    }
+  }
+}
+
+// Qk = H_0 ... H_{k-1} [I_k; 0] (see qr_form_q_reg); identity plus qr_apply_q beyond 256 rows.
+__device__ __forceinline__ void qr_form_q(const double2 *T, int m, int k, const Sh &sh, double2 *Qk) {
+  if (m <= CM_WG * 4) {
+    qr_form_q_reg<4>(T, m, k, sh, Qk);
+  } else {
+    for (int e = threadIdx.x; e < m * k; e += CM_WG) {
+      const int r = e % m, c = e / m;
+      Qk[e] = cmk(r == c ? 1.0 : 0.0, 0.0);
+    }
+    __syncthreads();
+    qr_apply_q(T, m, m, k, sh, Qk, m, k);
+  }
+  __syncthreads();
 }
 
 // One-sided Jacobi on the s columns of S (m x s, column-major, ld m, in LDS; s <= 64),
@@ -366,12 +427,8 @@ __device__ __forceinline__ int qr_thin(double2 *Y, int m, int p, double2 *Qout, 
     const int i = e % kq, j = e / kq;
     Rout[e] = (i <= j) ? Y[i + (int64_t)m * j] : cmk(0.0, 0.0);
   }
-  for (int e = tid; e < m * kq; e += CM_WG) {
-    const int i = e % m, j = e / m;
-    Qout[e] = cmk(i == j ? 1.0 : 0.0, 0.0);
-  }
   __syncthreads();
-  qr_apply_q(Y, m, m, kq, sh, Qout, m, kq);
+  qr_form_q(Y, m, kq, sh, Qout);
   return kq;
 }
 
@@ -511,12 +568,8 @@ __device__ __forceinline__ int cpqr_trunc(double2 *T, int m, int p, double delta
     B[r + (int64_t)k * perm[c]] = (r <= c) ? T[r + (int64_t)m * c] : cmk(0.0, 0.0);
   }
   // Qk = H_0 ... H_{k-1} [I_k; 0]
-  for (int e = tid; e < m * k; e += CM_WG) {
-    const int r = e % m, c = e / m;
-    Qk[e] = cmk(r == c ? 1.0 : 0.0, 0.0);
-  }
   __syncthreads();
-  qr_apply_q(T, m, m, k, sh, Qk, m, k);
+  qr_form_q(T, m, k, sh, Qk);
   return k;
 }
 

@@ -392,7 +392,7 @@ __global__ __launch_bounds__(CM_WG, 2) void k_build_qtt(const cm_problem *__rest
 // Rounds the pre-rounding train of slab g (if k_build_qtt marked one) into x, with cores
 // 1..n-1 right-orthonormal, and writes the instance's status.
 template <typename OutT>
-__global__ __launch_bounds__(CM_WG) void k_build_round(const cm_problem *__restrict__ prob, double tol, int cap,
+__global__ __launch_bounds__(CM_WG, 4) void k_build_round(const cm_problem *__restrict__ prob, double tol, int cap,
                                                        TTView x, int32_t *__restrict__ status,
                                                        char *__restrict__ ws, size_t slab_bytes, int n_max) {
   extern __shared__ __align__(16) char lds_arena[];

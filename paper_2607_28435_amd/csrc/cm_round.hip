@@ -20,7 +20,7 @@ __host__ __device__ inline size_t round_slab_bytes(int n_max, int d, int cap) {
 }  // namespace
 
 template <typename T>
-__global__ __launch_bounds__(CM_WG) void k_tt_round(TTView t, int batch, double tol, int cap, int incap,
+__global__ __launch_bounds__(CM_WG, 4) void k_tt_round(TTView t, int batch, double tol, int cap, int incap,
                                                     double *__restrict__ err_out, int32_t *__restrict__ status,
                                                     char *__restrict__ ws, size_t slab_bytes, int n_max, int dtype,
                                                     int skip_a) {

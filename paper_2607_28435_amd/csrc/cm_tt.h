@@ -61,7 +61,33 @@ struct CoreSrc {
     if (dtype == CM_C64) return cstore<float2>::ld((const float2 *)cores, off[l] + e);
     return ((const double2 *)cores)[off[l] + e];
   }
+  // element e of the core whose offset `base` = off[l] the caller has already read
+  __device__ __forceinline__ double2 at(int64_t base, int64_t e) const {
+    if (dtype == CM_C64) return cstore<float2>::ld((const float2 *)cores, base + e);
+    return ((const double2 *)cores)[base + e];
+  }
 };
+
+// sum_{t < K} a(t) b(t) for complex FP64 operands read through the functors, four terms at
+// a time: the four pairs of loads are issued before any is used, so one memory latency
+// covers four terms instead of one.
+template <typename FA, typename FB>
+__device__ __forceinline__ double2 dot4(int K, FA a, FB b) {
+  double2 acc = cmk(0.0, 0.0);
+  for (int t0 = 0; t0 < K; t0 += 4) {
+    double2 x[4], y[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int t = t0 + u < K ? t0 + u : K - 1;
+      x[u] = a(t);
+      y[u] = b(t);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (t0 + u < K) cfma(acc, x[u], y[u]);
+  }
+  return acc;
+}
 
 __device__ __forceinline__ void merge_flags(const la::Sh &sh, int *code) {
   if (threadIdx.x == 0) {
@@ -108,13 +134,13 @@ __device__ __forceinline__ double round_train(int n, int d, const CoreSrc &src, 
     // small dependent steps)
     const bool in_lds = lds != nullptr && l < n - 1 && rows * rr + rows * kq <= lds_elems;
     double2 *Yw = in_lds ? lds : w.Y;
+    const int64_t base = src.off[l];
+    const double2 *Cg = w.C;
     for (int e = tid; e < rows * rr; e += CM_WG) {
       const int i = e % rows, j = e / rows;
       const int a = i / d, ph = i % d;
-      double2 acc = cmk(0.0, 0.0);
-      for (int t = 0; t < rl; ++t)
-        cfma(acc, w.C[a + kprev * t], src.get(l, ((int64_t)t * d + ph) * rr + j));
-      Yw[e] = acc;
+      Yw[e] = dot4(rl, [&](int t) { return Cg[a + kprev * t]; },
+                   [&](int t) { return src.at(base, ((int64_t)t * d + ph) * rr + j); });
     }
     __syncthreads();
     double2 *core = w.tt + (int64_t)l * w.core_cap;
@@ -153,16 +179,20 @@ __device__ __forceinline__ double round_train(int n, int d, const CoreSrc &src, 
     const int kl = rk[l], kr = rk[l + 1];
     const double2 *core = w.tt + (int64_t)l * w.core_cap;  // column-major (kl*d) x kr
     const int b = d * rpp;
+    const int64_t base = src.off[l];
+    const double2 *Cg = w.C;
     for (int e = tid; e < kl * b; e += CM_WG) {
       const int i = e % kl, c = e / kl;
       const int ph = c / rpp, j = c % rpp;
-      double2 acc = cmk(0.0, 0.0);
+      const double2 *cj = Cg + kr * j;
       if (skip_a) {
-        for (int t = 0; t < kr; ++t) cfma(acc, src.get(l, ((int64_t)i * d + ph) * kr + t), w.C[t + kr * j]);
+        const int64_t row = base + ((int64_t)i * d + ph) * kr;
+        w.Y[e] = dot4(kr, [&](int t) { return src.at(row, t); }, [&](int t) { return cj[t]; });
       } else {
-        for (int t = 0; t < kr; ++t) cfma(acc, core[(i * d + ph) + (int64_t)(kl * d) * t], w.C[t + kr * j]);
+        const double2 *row = core + (i * d + ph);
+        const int64_t ld = (int64_t)kl * d;
+        w.Y[e] = dot4(kr, [&](int t) { return row[ld * t]; }, [&](int t) { return cj[t]; });
       }
-      w.Y[e] = acc;
     }
     __syncthreads();
     OutT *out = dst_cores + dst_off[l];
