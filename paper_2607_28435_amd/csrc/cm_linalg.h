@@ -573,31 +573,26 @@ __device__ __forceinline__ int cpqr_trunc(double2 *T, int m, int p, double delta
   return k;
 }
 
-// Truncated factorisation Y ~= L * Rk of Y (a x b, column-major, ld a; destroyed), where
-// Rk (k x b) has orthonormal rows (the top-k right singular vectors) and L = Y Rk^H (a x k),
-// a <= 64. Column-pivoted QR of X = Y^H first drops a tail of squared norm <= delta2/2 and
-// leaves X ~= Q B (Q: b x kc orthonormal, B: kc x a); one-sided Jacobi on the kc columns of
-// B^H (ordered by decreasing norm by the pivoting, which speeds convergence) then yields its
-// SVD, truncated with the rest of the budget. The kept rank k is the smallest whose total
-// dropped squared norm is <= delta2, clipped to cap (sh.rankcap is set if that loses more).
-//   X : scratch of at least a*b complex;  Z : scratch of at least a*b complex
+// Truncated factorisation Y ~= L * Rk of Y (a x b), given as X = Y^H (b x a, column-major,
+// ld b; destroyed), where Rk (k x b) has orthonormal rows (the top-k right singular vectors)
+// and L = Y Rk^H (a x k), a <= 64. Column-pivoted QR of X first drops a tail of squared norm
+// <= delta2/2 and leaves X ~= Q B (Q: b x kc orthonormal, B: kc x a); one-sided Jacobi on the
+// kc columns of B^H (ordered by decreasing norm by the pivoting, which speeds convergence)
+// then yields its SVD, truncated with the rest of the budget. The kept rank k is the smallest
+// whose total dropped squared norm is <= delta2, clipped to cap (sh.rankcap is set if that
+// loses more).
+//   X : the input, in the LDS scratch `lds` (x_lds) or in global memory
+//   Y : scratch of at least a*b complex (receives B);  Z : scratch of at least a*b complex
 //   S, J : at least a*min(a,b) and min(a,b)^2 complex
-//   L (ld a) and R (ld k) : outputs.
-//   lds, lds_elems : optional LDS scratch; X, and then the Jacobi pair, move there for this
-//   call when they fit (the factorisations are latency-bound chains of small steps).
+//   L (ld a) and R (row-major, k x b) : outputs.
+//   lds, lds_elems : optional LDS scratch; the Jacobi pair moves there when it fits (the
+//   factorisations are latency-bound chains of small steps).
 // Returns k (uniform); sh.err2 holds the dropped squared norm.
-__device__ __forceinline__ int svd_trunc_rows(double2 *Y, int a, int b, double delta2, int cap,
-                                              double2 *X, double2 *Z, double2 *S, double2 *J,
+__device__ __forceinline__ int svd_trunc_rows(double2 *X, bool x_lds, int a, int b, double delta2, int cap,
+                                              double2 *Y, double2 *Z, double2 *S, double2 *J,
                                               double2 *L, double2 *R, Sh &sh, double2 *lds = nullptr,
                                               int lds_elems = 0) {
   const int tid = threadIdx.x;
-  const bool x_lds = lds != nullptr && a * b <= lds_elems;
-  double2 *Xw = x_lds ? lds : X;
-  for (int e = tid; e < a * b; e += CM_WG) {
-    const int i = e % b, j = e / b;   // X[i, j] = conj(Y[j, i])
-    Xw[e] = cconj(Y[j + (int64_t)a * i]);
-  }
-  __syncthreads();
   // X P = Q R, truncated: Q -> Z (b x kc), B = R[:kc] P^T -> Y (kc x a, ld kc)
   int kc;
   if (x_lds) kc = cpqr_trunc(lds, b, a, 0.5 * delta2, 64, Z, Y, sh.sig2, sh.perm, sh);
@@ -624,11 +619,11 @@ __device__ __forceinline__ int svd_trunc_rows(double2 *Y, int a, int b, double d
     L[e] = Sw[i + (int64_t)a * sh.perm[j]];
   }
   for (int e = tid; e < k * b; e += CM_WG) {
-    const int i = e % k, c = e / k;
+    const int i = e / b, c = e - i * b;   // lanes run along a row of Rk: Z reads are coalesced
     const double2 *jc = Jw + (int64_t)kc * sh.perm[i];
     double2 acc = cmk(0.0, 0.0);
     for (int t = 0; t < kc; ++t) cfma(acc, Z[c + (int64_t)b * t], jc[t]);
-    R[i + (int64_t)k * c] = cconj(acc);
+    R[e] = cconj(acc);
   }
   __syncthreads();
   if (tid == 0) sh.err2 += err_c;

@@ -12,31 +12,42 @@ __host__ __device__ inline size_t al256r(size_t x) { return (x + 255) & ~(size_t
 // LDS-resident matrices with three workgroups per CU: measured 16.0 -> 7.3 ms for 4096
 // trains at n = 24.
 constexpr int RLDS = 8 * 1024;
+// Workspace of one persistent workgroup: its hot matrices (Y, X, Z, L, R, C of cap d cap
+// elements and the Jacobi pair of cap^2) and, apart from them, the orthogonalised train of the
+// first sweep (n_max cores). The hot blocks of all workgroups sit next to each other at the
+// start of the workspace and the trains after them, so that the thousands of concurrently
+// resident workgroups touch one dense region instead of one scattered slab each (measured:
+// the latency of a bond's product grew from 17 K to 250 K cycles between 256 and 4096
+// resident workgroups with one slab per workgroup).
+__host__ __device__ inline size_t round_hot_bytes(int d, int cap) {
+  const size_t mat = (size_t)cap * d * cap;
+  return al256r(sizeof(double2) * (6 * mat + 2 * (size_t)cap * cap));
+}
+__host__ __device__ inline size_t round_tt_bytes(int n_max, int d, int cap) {
+  return al256r(sizeof(double2) * (size_t)cap * d * cap * n_max);
+}
 __host__ __device__ inline size_t round_slab_bytes(int n_max, int d, int cap) {
-  const size_t core_cap = (size_t)cap * d * cap;
-  return al256r(sizeof(double2) * core_cap * n_max) + al256r(sizeof(double2) * core_cap * 6) +
-         al256r(sizeof(double2) * 2 * 64 * 64);
+  return round_hot_bytes(d, cap) + round_tt_bytes(n_max, d, cap);
 }
 }  // namespace
 
 template <typename T>
 __global__ __launch_bounds__(CM_WG, 4) void k_tt_round(TTView t, int batch, double tol, int cap, int incap,
                                                     double *__restrict__ err_out, int32_t *__restrict__ status,
-                                                    char *__restrict__ ws, size_t slab_bytes, int n_max, int dtype,
-                                                    int skip_a) {
+                                                    char *__restrict__ ws, int n_max, int dtype, int skip_a) {
   extern __shared__ __align__(16) char lds_arena[];
   __shared__ la::Sh sh;
   __shared__ int code_sh;
   const int tid = threadIdx.x;
-  char *slab = ws + (size_t)blockIdx.x * slab_bytes;
+  const size_t hot = round_hot_bytes(t.d, incap);
+  double2 *mats = (double2 *)(ws + (size_t)blockIdx.x * hot);
   RoundScratch rs;
   rs.core_cap = (int64_t)incap * t.d * incap;
-  rs.tt = (double2 *)slab;
-  double2 *mats = (double2 *)(slab + al256r(sizeof(double2) * rs.core_cap * n_max));
+  rs.tt = (double2 *)(ws + (size_t)gridDim.x * hot + (size_t)blockIdx.x * round_tt_bytes(n_max, t.d, incap));
   rs.Y = mats; rs.X = mats + rs.core_cap; rs.Z = mats + 2 * rs.core_cap;
   rs.L = mats + 3 * rs.core_cap; rs.R = mats + 4 * rs.core_cap; rs.C = mats + 5 * rs.core_cap;
-  rs.S = (double2 *)((char *)mats + al256r(sizeof(double2) * rs.core_cap * 6));
-  rs.J = rs.S + 64 * 64;
+  rs.S = mats + 6 * rs.core_cap;
+  rs.J = rs.S + (int64_t)incap * incap;
   for (int b = blockIdx.x; b < batch; b += gridDim.x) {
     const int n = t.n[b];
     if (tid == 0) {
@@ -81,7 +92,6 @@ extern "C" cm_status cm_tt_round(cm_tt_batch *t, double tol, int cap_rank, doubl
   const int slots = cm_slots_for_ws(CM_OP_TT_ROUND, t->batch, t->n_max, t->cap_rank, t->dtype, ws ? ws_bytes : 0);
   if (slots < 1) return CM_E_INVALID;
   const int d = t->d_out * t->d_in;
-  const size_t slab = round_slab_bytes(t->n_max, d, t->cap_rank);
   const size_t lds = RLDS;
   TTView v = tt_view(t);
   hipStream_t s = (hipStream_t)stream;
@@ -90,10 +100,10 @@ extern "C" cm_status cm_tt_round(cm_tt_batch *t, double tol, int cap_rank, doubl
   CM_HIP_CHECK(cm_allow_lds(k_tt_round<double2>, lds));
   if (t->dtype == CM_C64)
     hipLaunchKernelGGL(k_tt_round<float2>, dim3(slots), dim3(CM_WG), lds, s, v, t->batch, tol, cap_rank, t->cap_rank,
-                       err_out, status, (char *)ws, slab, t->n_max, t->dtype, skip);
+                       err_out, status, (char *)ws, t->n_max, t->dtype, skip);
   else
     hipLaunchKernelGGL(k_tt_round<double2>, dim3(slots), dim3(CM_WG), lds, s, v, t->batch, tol, cap_rank, t->cap_rank,
-                       err_out, status, (char *)ws, slab, t->n_max, t->dtype, skip);
+                       err_out, status, (char *)ws, t->n_max, t->dtype, skip);
   CM_LAUNCH_CHECK();
   t->flags = CM_TT_RIGHT_ORTHO;
   return CM_OK;

@@ -61,11 +61,6 @@ struct CoreSrc {
     if (dtype == CM_C64) return cstore<float2>::ld((const float2 *)cores, off[l] + e);
     return ((const double2 *)cores)[off[l] + e];
   }
-  // element e of the core whose offset `base` = off[l] the caller has already read
-  __device__ __forceinline__ double2 at(int64_t base, int64_t e) const {
-    if (dtype == CM_C64) return cstore<float2>::ld((const float2 *)cores, base + e);
-    return ((const double2 *)cores)[base + e];
-  }
 };
 
 // sum_{t < K} a(t) b(t) for complex FP64 operands read through the functors, four terms at
@@ -136,11 +131,19 @@ __device__ __forceinline__ double round_train(int n, int d, const CoreSrc &src, 
     double2 *Yw = in_lds ? lds : w.Y;
     const int64_t base = src.off[l];
     const double2 *Cg = w.C;
-    for (int e = tid; e < rows * rr; e += CM_WG) {
-      const int i = e % rows, j = e / rows;
-      const int a = i / d, ph = i % d;
-      Yw[e] = dot4(rl, [&](int t) { return Cg[a + kprev * t]; },
-                   [&](int t) { return src.at(base, ((int64_t)t * d + ph) * rr + j); });
+    auto yform = [&](auto ld) {
+      for (int e = tid; e < rows * rr; e += CM_WG) {
+        const int i = e % rows, j = e / rows;
+        const int a = i / d, ph = i % d;
+        Yw[e] = dot4(rl, [&](int t) { return Cg[a + kprev * t]; }, [&](int t) { return ld(((int64_t)t * d + ph) * rr + j); });
+      }
+    };
+    if (src.dtype == CM_C64) {
+      const float2 *cs = (const float2 *)src.cores + base;
+      yform([&](int64_t e) { return cstore<float2>::ld(cs, e); });
+    } else {
+      const double2 *cs = (const double2 *)src.cores + base;
+      yform([&](int64_t e) { return cs[e]; });
     }
     __syncthreads();
     double2 *core = w.tt + (int64_t)l * w.core_cap;
@@ -179,39 +182,49 @@ __device__ __forceinline__ double round_train(int n, int d, const CoreSrc &src, 
     const int kl = rk[l], kr = rk[l + 1];
     const double2 *core = w.tt + (int64_t)l * w.core_cap;  // column-major (kl*d) x kr
     const int b = d * rpp;
-    const int64_t base = src.off[l];
     const double2 *Cg = w.C;
-    for (int e = tid; e < kl * b; e += CM_WG) {
-      const int i = e % kl, c = e / kl;
-      const int ph = c / rpp, j = c % rpp;
-      const double2 *cj = Cg + kr * j;
-      if (skip_a) {
-        const int64_t row = base + ((int64_t)i * d + ph) * kr;
-        w.Y[e] = dot4(kr, [&](int t) { return src.at(row, t); }, [&](int t) { return cj[t]; });
-      } else {
-        const double2 *row = core + (i * d + ph);
-        const int64_t ld = (int64_t)kl * d;
-        w.Y[e] = dot4(kr, [&](int t) { return row[ld * t]; }, [&](int t) { return cj[t]; });
+    // X = Y^H (b x kl, ld b) with Y[i][(ph, j)] = sum_t core[i][ph][t] C[t][j], formed in the LDS
+    // scratch when it fits. Lanes run over j fastest, so the lanes of a load share one core row
+    // (and neighbouring lanes' rows are adjacent in memory): a few cache lines per load instead
+    // of one per lane, and X is written contiguously. The source's storage type is resolved
+    // once per bond so that each element's loads are issued together.
+    const bool x_lds = lds != nullptr && kl * b <= lds_elems;
+    double2 *Xw = x_lds ? lds : w.X;
+    auto xform = [&](auto rowld) {
+      for (int e = tid; e < kl * b; e += CM_WG) {
+        const int row = e / rpp, j = e - row * rpp;   // row = i d + ph
+        const int i = row / d, ph = row - i * d;
+        const double2 *cj = Cg + kr * j;
+        Xw[ph * rpp + j + b * i] = cconj(dot4(kr, [&](int t) { return rowld(row, t); }, [&](int t) { return cj[t]; }));
       }
+    };
+    if (skip_a) {
+      const int64_t base = src.off[l];
+      if (src.dtype == CM_C64) {
+        const float2 *cs = (const float2 *)src.cores + base;
+        xform([&](int row, int t) { return cstore<float2>::ld(cs, (int64_t)row * kr + t); });
+      } else {
+        const double2 *cs = (const double2 *)src.cores + base;
+        xform([&](int row, int t) { return cs[(int64_t)row * kr + t]; });
+      }
+    } else {
+      const int64_t ld = (int64_t)kl * d;
+      xform([&](int row, int t) { return core[row + ld * t]; });
     }
     __syncthreads();
     OutT *out = dst_cores + dst_off[l];
     if (l == 0) {
       // kl == 1; core 0 = Y (1 x d*rpp), element (0, ph, j) at ph*rpp + j == column index
-      for (int e = tid; e < b; e += CM_WG) cstore<OutT>::st(out, e, w.Y[e]);
+      for (int e = tid; e < b; e += CM_WG) cstore<OutT>::st(out, e, cconj(Xw[e]));
       if (tid == 0) { dst_ranks[0] = 1; dst_ranks[1] = rpp; }
       __syncthreads();
       break;
     }
-    const int k = la::svd_trunc_rows(w.Y, kl, b, delta2, cap, w.X, w.Z, S, J, w.L, w.R, sh, lds, lds_elems);
+    const int k = la::svd_trunc_rows(Xw, x_lds, kl, b, delta2, cap, w.Y, w.Z, S, J, w.L, w.R, sh, lds, lds_elems);
     merge_flags(sh, code);
     err2 += sh.err2;
-    // core l = Rk (k x b, ld k) as [k][d][rpp]
-    for (int e = tid; e < k * b; e += CM_WG) {
-      const int i = e % k, c = e / k;
-      const int ph = c / rpp, j = c % rpp;
-      cstore<OutT>::st(out, ((int64_t)i * d + ph) * rpp + j, w.R[e]);
-    }
+    // core l = Rk (k x b, row-major) as [k][d][rpp]: the same element order
+    for (int e = tid; e < k * b; e += CM_WG) cstore<OutT>::st(out, e, w.R[e]);
     // carry = L (kl x k, ld kl)
     for (int e = tid; e < kl * k; e += CM_WG) w.C[e] = w.L[e];
     if (tid == 0) { dst_ranks[l + 1] = rpp; }
