@@ -578,7 +578,7 @@ def surrogate_run(cm, torch, steps):
             "in_gate_max_abs_err_over_S0": float(err[ok].max()), "in_gate_p999_abs_err_over_S0":
                 float(np.quantile(err[ok], 0.999)), "sfft_reference_failures": int((st != 0).sum()),
             "queries_per_s": nq / net_s, "sfft_queries_per_s": nq / sfft_s, "speedup_vs_sfft": sfft_s / net_s,
-            "roofline": {"kernel": "k_mlp_in + 3x k_gemm_ws + k_mlp_out + k_gate", "bound": "mfma",
+            "roofline": {"kernel": "k_mlp_fused + k_gate", "bound": "mfma",
                          "achieved": ach, "peak": BF16_DENSE_TFLOPS, "unit": "TFLOP/s",
                          "frac": ach / BF16_DENSE_TFLOPS, "executed_tflops": executed / net_s / 1e12}}
 

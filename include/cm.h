@@ -310,8 +310,10 @@ cm_status cm_mlp_sync_bf16(const cm_mlp *net, void *stream);
 
 /* y[b] = network(x[b]) for b < B. x: device float [B][7] raw inputs; y: device float [B].
  * acts: device buffer of acts_bytes bytes. With acts_bytes >= cm_mlp_act_bytes(B) the
- * pre-activations Z1..Z4 are kept there for cm_mlp_backward; with at least half of that
- * (inference) two of them are ping-ponged; less is CM_E_INVALID. */
+ * pre-activations Z1..Z4 are kept there for cm_mlp_backward (training: one launch per
+ * layer). Otherwise (inference; acts may be NULL) one fused launch runs all five layers with
+ * the activations kept on chip; its outputs equal the training path's to FP32 rounding (the
+ * final 256-term sum is added in another order). */
 cm_status cm_mlp_forward(const cm_mlp *net, const float *x, int B, float *y, float *acts, size_t acts_bytes,
                          void *stream);
 

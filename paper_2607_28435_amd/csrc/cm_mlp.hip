@@ -262,6 +262,211 @@ __global__ __launch_bounds__(WS_THREADS) void k_gemm_ws(const float *__restrict_
 }
 constexpr size_t WS_LDS = sizeof(uint16_t) * NW * WSP;
 
+// ------------------------------------------------------------------ fused inference
+// The whole network for a tile of FM = 64 queries in one workgroup of four waves, with no
+// activation leaving the CU. Each layer is computed transposed, Z^T = W A^T: the weights are
+// the MFMA's A operand (32 output neurons x 16 inputs per fragment, 16-byte loads of W rows
+// from L2, where the three 256 x 256 BF16 matrices stay) and the activations its B operand,
+// read from LDS, where the tile's activations live as their hi and lo BF16 parts (Ah, Al:
+// [query][neuron], 68 KB, two workgroups per CU so that one's VALU epilogue overlaps the
+// other's MFMAs). Wave w computes neurons 64 w .. 64 w + 63 for all 64 queries: four 32 x 32
+// accumulators, K in steps of 16, the A fragments of the next step loaded before the current
+// step's MFMAs, all hi products of a step before the lo products. An accumulator lane holds
+// four consecutive neurons of one query per group, so the epilogue (bias, SiLU, hi / lo split)
+// converts in pairs and stores eight-byte packets. The first layer (7 -> 256, FP32 weights)
+// is three MFMAs per block with both operands split into hi and lo parts
+// (W_hi x_hi + W_hi x_lo + W_lo x_hi: relative error ~2^-16, below the hidden layers' own);
+// the last folds W5 silu(z4) into per-query partial sums.
+constexpr int FM = 64;               // queries per tile
+constexpr int FQB = FM / 32;         // query blocks
+constexpr int FP = NW + 8;           // LDS row pitch (bf16): 528 bytes, 16-byte aligned
+constexpr size_t FUSED_LDS = sizeof(uint16_t) * 2 * FM * FP;
+
+__device__ __forceinline__ void split8(const float *v, s16x8 &hi, s16x8 &lo) {
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const uint16_t h = __builtin_bit_cast(uint16_t, (__bf16)v[i]);
+    hi[i] = (short)h;
+    lo[i] = (short)__builtin_bit_cast(uint16_t, (__bf16)(v[i] - bf2f(h)));
+  }
+}
+
+__global__ __launch_bounds__(256, 2) void k_mlp_fused(const float *__restrict__ x, int B, const float *__restrict__ p,
+                                                   const uint16_t *__restrict__ wbf, cm_mlp net,
+                                                   float *__restrict__ y) {
+  extern __shared__ __align__(16) uint16_t fl[];
+  uint16_t *Ah = fl, *Al = fl + FM * FP;
+  __shared__ float bsh[4][NW];   // b1..b4
+  __shared__ float w5s[NW];
+  __shared__ float ys[4][FM];    // per-wave partial outputs
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int l32 = lane & 31, hi32 = lane >> 5;
+  for (int e = tid; e < NW; e += 256) {
+    bsh[0][e] = p[OFF_B1 + e];
+    bsh[1][e] = p[off_b(2) + e];
+    bsh[2][e] = p[off_b(3) + e];
+    bsh[3][e] = p[off_b(4) + e];
+    w5s[e] = p[OFF_W5 + e];
+  }
+  // first-layer A fragments: W1[n][k], n = 64 w + 32 mb + l32, k = 8 hi32 + i (k < 7; zero
+  // beyond), split into hi and lo
+  bf16x8 w1h[2], w1l[2];
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb) {
+    float v[8];
+    const int n = 64 * w + 32 * mb + l32;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int k = 8 * hi32 + i;
+      v[i] = k < NIN ? p[OFF_W1 + n * NIN + k] : 0.0f;
+    }
+    s16x8 h, l;
+    split8(v, h, l);
+    w1h[mb] = __builtin_bit_cast(bf16x8, h);
+    w1l[mb] = __builtin_bit_cast(bf16x8, l);
+  }
+  __syncthreads();
+  // epilogue of a hidden layer: neurons 64 w + 32 mb + 8 g + 4 hi32 + j (j < 4) of query
+  // 32 qb + l32 are acc[mb][qb][4 g + j]
+  auto store_act = [&](const f32x16 (&acc)[2][FQB], const float *bias) {
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int qb = 0; qb < FQB; ++qb)
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          const int n = 64 * w + 32 * mb + 8 * g + 4 * hi32;
+          float v[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) v[j] = silu_fast(acc[mb][qb][4 * g + j] + bias[n + j]);
+          uint16_t h[4], lo[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            h[j] = __builtin_bit_cast(uint16_t, (__bf16)v[j]);
+            lo[j] = __builtin_bit_cast(uint16_t, (__bf16)(v[j] - bf2f(h[j])));
+          }
+          const int off = (32 * qb + l32) * FP + n;
+          *(uint2 *)&Ah[off] = make_uint2(h[0] | ((uint32_t)h[1] << 16), h[2] | ((uint32_t)h[3] << 16));
+          *(uint2 *)&Al[off] = make_uint2(lo[0] | ((uint32_t)lo[1] << 16), lo[2] | ((uint32_t)lo[3] << 16));
+        }
+  };
+  const int ntiles = (B + FM - 1) / FM;
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int q0 = t * FM;
+    f32x16 acc[2][FQB];
+    // layer 1: B fragments xn[q][k], q = 32 qb + l32, k = 8 hi32 + i
+    {
+      bf16x8 xh[FQB], xl[FQB];
+#pragma unroll
+      for (int qb = 0; qb < FQB; ++qb) {
+        const int q = q0 + 32 * qb + l32;
+        float v[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const int k = 8 * hi32 + i;
+          v[i] = (k < NIN && q < B) ? (x[(int64_t)q * NIN + k] - net.shift[k]) * net.scale[k] : 0.0f;
+        }
+        s16x8 h, l;
+        split8(v, h, l);
+        xh[qb] = __builtin_bit_cast(bf16x8, h);
+        xl[qb] = __builtin_bit_cast(bf16x8, l);
+      }
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int qb = 0; qb < FQB; ++qb) {
+#pragma unroll
+          for (int v = 0; v < 16; ++v) acc[mb][qb][v] = 0.0f;
+          acc[mb][qb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1h[mb], xh[qb], acc[mb][qb], 0, 0, 0);
+          acc[mb][qb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1h[mb], xl[qb], acc[mb][qb], 0, 0, 0);
+          acc[mb][qb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1l[mb], xh[qb], acc[mb][qb], 0, 0, 0);
+        }
+      store_act(acc, bsh[0]);
+    }
+    __syncthreads();
+    float ypart[FQB][16];
+    for (int l = 2; l <= 4; ++l) {
+      const uint16_t *W = wbf + (int64_t)(l - 2) * NW * NW;
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int qb = 0; qb < FQB; ++qb)
+#pragma unroll
+          for (int v = 0; v < 16; ++v) acc[mb][qb][v] = 0.0f;
+      // A fragment of neuron block mb at K step kk: W[n][kk + 8 hi32 .. +7], n = 64 w + 32 mb + l32
+      const uint16_t *wrow0 = W + (int64_t)(64 * w + l32) * NW + 8 * hi32;
+      const uint16_t *wrow1 = wrow0 + (int64_t)32 * NW;
+      s16x8 an0 = *(const s16x8 *)wrow0, an1 = *(const s16x8 *)wrow1;
+      // B fragments of query block qb at K step kk: Ah / Al[q][kk + 8 hi32 .. +7], q = 32 qb + l32
+      const int boff = l32 * FP + 8 * hi32;
+      s16x8 bhn[FQB], bln[FQB];
+#pragma unroll
+      for (int qb = 0; qb < FQB; ++qb) {
+        bhn[qb] = *(const s16x8 *)&Ah[boff + 32 * qb * FP];
+        bln[qb] = *(const s16x8 *)&Al[boff + 32 * qb * FP];
+      }
+      for (int kk = 0; kk < NW; kk += 16) {
+        const bf16x8 A0 = __builtin_bit_cast(bf16x8, an0), A1 = __builtin_bit_cast(bf16x8, an1);
+        s16x8 bh[FQB], bl[FQB];
+#pragma unroll
+        for (int qb = 0; qb < FQB; ++qb) {
+          bh[qb] = bhn[qb];
+          bl[qb] = bln[qb];
+        }
+        if (kk + 16 < NW) {   // next step's operands, in flight during this step's MFMAs
+          an0 = *(const s16x8 *)(wrow0 + kk + 16);
+          an1 = *(const s16x8 *)(wrow1 + kk + 16);
+#pragma unroll
+          for (int qb = 0; qb < FQB; ++qb) {
+            bhn[qb] = *(const s16x8 *)&Ah[boff + 32 * qb * FP + kk + 16];
+            bln[qb] = *(const s16x8 *)&Al[boff + 32 * qb * FP + kk + 16];
+          }
+        }
+#pragma unroll
+        for (int qb = 0; qb < FQB; ++qb) {
+          const bf16x8 BH = __builtin_bit_cast(bf16x8, bh[qb]);
+          acc[0][qb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A0, BH, acc[0][qb], 0, 0, 0);
+          acc[1][qb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A1, BH, acc[1][qb], 0, 0, 0);
+        }
+#pragma unroll
+        for (int qb = 0; qb < FQB; ++qb) {
+          const bf16x8 BL = __builtin_bit_cast(bf16x8, bl[qb]);
+          acc[0][qb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A0, BL, acc[0][qb], 0, 0, 0);
+          acc[1][qb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A1, BL, acc[1][qb], 0, 0, 0);
+        }
+      }
+      __syncthreads();   // every wave has read this layer's input
+      if (l < 4) {
+        store_act(acc, bsh[l - 1]);
+        __syncthreads();
+      } else {
+        // y[q] = b5 + sum_n W5[n] silu(z4[n][q]) over this lane's 32 neurons
+#pragma unroll
+        for (int qb = 0; qb < FQB; ++qb) {
+          float sacc = 0.0f;
+#pragma unroll
+          for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+              const int n = 64 * w + 32 * mb + 8 * (v >> 2) + 4 * hi32 + (v & 3);
+              sacc += w5s[n] * silu_fast(acc[mb][qb][v] + bsh[3][n]);
+            }
+          ypart[qb][0] = sacc;
+        }
+      }
+    }
+    // the two half waves hold the same queries' other neurons; then the four waves
+#pragma unroll
+    for (int qb = 0; qb < FQB; ++qb) {
+      const float s2 = ypart[qb][0] + __shfl_xor(ypart[qb][0], 32, 64);
+      if (hi32 == 0) ys[w][32 * qb + l32] = s2;
+    }
+    __syncthreads();
+    if (tid < FM && q0 + tid < B) y[q0 + tid] = ((ys[0][tid] + ys[1][tid]) + (ys[2][tid] + ys[3][tid])) + p[OFF_B5];
+    __syncthreads();   // ys and the activations are reused by the next tile
+  }
+}
+
 // ------------------------------------------------------------------ small layers
 // Z1[b][n] = b1[n] + sum_i W1[n][i] xn[b][i]
 __global__ void k_mlp_in(const float *__restrict__ x, int B, const float *__restrict__ p, cm_mlp net,
@@ -456,12 +661,24 @@ static int ws_grid(int M) {
 
 extern "C" cm_status cm_mlp_forward(const cm_mlp *net, const float *x, int B, float *y, float *acts,
                                     size_t acts_bytes, void *stream) {
-  if (!net_ok(net) || !x || !y || !acts || B < 0) return CM_E_INVALID;
+  if (!net_ok(net) || !x || !y || B < 0) return CM_E_INVALID;
   if (B == 0) return CM_OK;
   if ((int64_t)B * NW > INT32_MAX) return CM_E_UNSUPPORTED;
-  const bool keep = acts_bytes >= cm_mlp_act_bytes(B);
-  if (!keep && acts_bytes < cm_mlp_act_bytes(B) / 2) return CM_E_INVALID;
+  const bool keep = acts && acts_bytes >= cm_mlp_act_bytes(B);
   hipStream_t s = (hipStream_t)stream;
+  if (!keep) {
+    // inference: the fused kernel, two persistent workgroups per CU at most
+    CM_HIP_CHECK(cm_allow_lds(k_mlp_fused, FUSED_LDS));
+    const int ntiles = (B + FM - 1) / FM;
+    int cus = 0;
+    int dev = 0;
+    CM_HIP_CHECK(hipGetDevice(&dev));
+    CM_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const int grid = ntiles < 2 * cus ? ntiles : 2 * cus;
+    hipLaunchKernelGGL(k_mlp_fused, dim3(grid), dim3(256), FUSED_LDS, s, x, B, net->params, net->w_bf16, *net, y);
+    CM_LAUNCH_CHECK();
+    return CM_OK;
+  }
   float *Z[4];
   for (int l = 0; l < 4; ++l) Z[l] = acts + (int64_t)(keep ? l : (l & 1)) * B * NW;
   CM_HIP_CHECK(cm_allow_lds(k_gemm_ws<W_NK, F_SILU, E_BIAS_STORE>, WS_LDS));
