@@ -67,6 +67,14 @@ def parse():
                     "line per n of the paper's memory / rank / time / NRMSE curves (Section 4)")
     ap.add_argument("--curves-n", type=int, nargs=2, default=(3, 40))
     ap.add_argument("--curves-dense-max", type=int, default=30)
+    ap.add_argument("--curves-tol", type=float, default=1e-10, help="SFFT (zip-up and rounding) tolerance of the curves")
+    ap.add_argument("--curves-mpo-tol", type=float, default=None, help="operator rounding tolerance of the curves "
+                    "(default: a tenth of --curves-tol)")
+    ap.add_argument("--curves-list", type=int, nargs="*", default=None, help="explicit grid exponents instead of "
+                    "the --curves-n range")
+    ap.add_argument("--curves-shots", type=int, default=4096)
+    ap.add_argument("--curves-build-tol", type=float, default=None, help="QTT construction tolerance of the curves "
+                    "(default: a tenth of --curves-tol)")
     return ap.parse_args()
 
 
@@ -414,7 +422,7 @@ def _bs_call(S0, K, r, q, T, sigma):
     return S0 * math.exp(-q * T) * special.ndtr(d1) - K * math.exp(-r * T) * special.ndtr(d1 - sq)
 
 
-def paper_curves(cm, torch, n_lo, n_hi, dense_max, tol=1e-10, reps=3, shots=4096):
+def paper_curves(cm, torch, ns, dense_max, tol=1e-10, mpo_tol=None, reps=3, shots=4096, build_tol=None):
     """Memory, maximal rank, run time and NRMSE against n on the paper's Black–Scholes grid
     (Section 4: S0 = 100, r = 0.05, sigma = 0.3, T = 0.5, alpha = 2.5, N = 2^(n-1),
     Delta_k = N^(-1/2)), FP64 throughout, one instance per run as in the paper:
@@ -428,7 +436,8 @@ def paper_curves(cm, torch, n_lo, n_hi, dense_max, tol=1e-10, reps=3, shots=4096
         (exact probabilities, Eq. qft_observable_price with p_hat = p) and the NRMSE of the
         shot estimator with `shots` outcomes (seeded uniforms)."""
     rows = []
-    for n in range(n_lo, n_hi + 1):
+    mpo_tol = tol / 10 if mpo_tol is None else mpo_tol
+    for n in ns:
         p = W.paper_bs_grid(n)
         M = 2 ** n
         lam = 2.0 * math.pi / (M * p.eta)
@@ -437,7 +446,11 @@ def paper_curves(cm, torch, n_lo, n_hi, dense_max, tol=1e-10, reps=3, shots=4096
         u = np.arange(u_lo, u_hi + 1, dtype=np.int64)
         if len(u) > 65536:
             u = u[np.linspace(0, len(u) - 1, 65536).round().astype(np.int64)]
-        K = np.exp(p.k0 + lam * u.astype(np.float64))
+        # the exact grid strikes k0 + 2 pi u / (M eta), formed in extended precision: the
+        # grid's k0 is ~2^(n/2) from the money, so rounding lambda first would move the strikes
+        two_pi = np.longdouble(2) * np.arccos(np.longdouble(-1))
+        K = np.exp((np.longdouble(p.k0) + two_pi / (np.longdouble(M) * np.longdouble(p.eta))
+                    * u.astype(np.longdouble)).astype(np.float64))
         ref = _bs_call(100.0, K, 0.05, 0.0, 0.5, 0.3)
         sd = torch.from_numpy(u[None, :]).cuda()
 
@@ -452,15 +465,16 @@ def paper_curves(cm, torch, n_lo, n_hi, dense_max, tol=1e-10, reps=3, shots=4096
             return best
 
         box = {}
-        t_op = timed(lambda: box.__setitem__("mpo", cm.MpoCache([n], tol / 10, 64, cm.CM_C128)))
-        pr = cm.SfftPricer([p], cm.CM_C128, tol=tol, cap=64, mpo=box["mpo"])
+        t_op = timed(lambda: box.__setitem__("mpo", cm.MpoCache([n], mpo_tol, 64, cm.CM_C128)))
+        pr = cm.SfftPricer([p], cm.CM_C128, tol=tol, cap=64, mpo=box["mpo"], build_tol=build_tol)
         prices = torch.empty((1, len(u)), dtype=torch.float64, device="cuda")
         t_x = timed(pr.build)
         t_core = timed(lambda: (pr.apply(), pr.round(), pr.read(sd, prices)))
         got = prices.cpu().numpy()[0]
         st = pr.statuses()
         yr = pr.y.ranks[0, : n + 1].cpu().numpy().astype(np.int64)
-        row = {"n": n, "strikes": int(len(u)),
+        row = {"n": n, "strikes": int(len(u)), "tol": tol, "mpo_tol": mpo_tol, "build_tol": pr.build_tol,
+               "mpo_max_rank": int(box["mpo"].w.ranks[n, : n + 1].max().item()),
                "sfft": {"construct_operator_s": t_op, "construct_x_s": t_x, "core_s": t_core,
                         "total_s": t_op + t_x + t_core,
                         "memory_MB": float((yr[:-1] * 2 * yr[1:]).sum() * 16 / 1e6),
@@ -593,7 +607,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.curves:
-        paper_curves(cm, torch, args.curves_n[0], args.curves_n[1], args.curves_dense_max)
+        ns = args.curves_list if args.curves_list else list(range(args.curves_n[0], args.curves_n[1] + 1))
+        paper_curves(cm, torch, ns, args.curves_dense_max, tol=args.curves_tol, mpo_tol=args.curves_mpo_tol,
+                     shots=args.curves_shots, build_tol=args.curves_build_tol)
         return
     dev = "cuda"
     if args.copy_calibration:

@@ -114,9 +114,14 @@ class Grid:
         self.M = 2 ** p.n
         self.eta = p.eta
         self.lam = 2.0 * math.pi / (self.M * p.eta)
+        # The default grid is centred on the money: k0 = ln S0 - M lambda / 2 as a real number,
+        # so that k_u = ln S0 + lambda (u - M/2) with an exact integer offset (kc, us); k0 here
+        # is that value rounded, for display and for search windows only.
         if p.k0 is None:
+            self.kc, self.us = math.log(p.S0), self.M // 2
             self.k0 = math.log(p.S0) - self.M * self.lam / 2.0
         else:
+            self.kc, self.us = float(p.k0), 0
             self.k0 = float(p.k0)
         if p.quad == "rect2":
             self.v0 = -self.M * p.eta / 2.0
@@ -127,7 +132,17 @@ class Grid:
         self.quad = p.quad
 
     def k(self, u):
-        return self.k0 + self.lam * np.asarray(u, dtype=np.float64)
+        """k_u = k0 + 2 pi u / (M eta): the log-strike that the DFT phase exp(-2 pi i j u / M)
+        pairs with index u (the grid relation eta lambda = 2 pi / M of Section 2.1 holds
+        exactly in the sum); the default k0 enters as ln S0 and the exact offset -M/2 of u.
+        Formed in extended precision (64-bit significand) and rounded once: within about
+        2^-63 |lambda (u - us)| plus half an ulp of k_u, even where k0 and lambda u are large
+        and cancel (grids centred far from the money: 1e-14 at n = 40 on the paper's grid);
+        lambda rounded to double first would shift k_u by up to |lambda u| times the double
+        epsilon (4e-11 there)."""
+        uu = (np.asarray(u, dtype=np.int64) - self.us).astype(np.longdouble)
+        step = TWO_PI_LD / (np.longdouble(self.M) * np.longdouble(self.eta))
+        return (np.longdouble(self.kc) + step * uu).astype(np.float64)
 
 
 def grid(p) -> Grid:
@@ -163,7 +178,10 @@ def integrand(p, j):
     g = grid(p)
     j = np.asarray(j, dtype=np.int64)
     v = g.v0 + j.astype(np.float64) * p.eta
-    c = np.longdouble(p.eta) * np.longdouble(g.k0) / TWO_PI_LD
+    # eta k0 / (2 pi) in turns; the default k0 = ln S0 - pi / eta adds half a turn per j
+    c = np.longdouble(p.eta) * np.longdouble(g.kc) / TWO_PI_LD
+    if g.us:
+        c = c - np.longdouble(0.5)
     ang = (TWO_PI_LD * _phase_frac(j, c)).astype(np.float64)
     return weights(p, j) * psi(p, v) * np.exp(-1j * ang)
 
@@ -201,8 +219,11 @@ def prices_from_y(p, u, y):
     k = g.k(u)
     # exp(-i v0 k_u) = exp(-i v0 k0) exp(-i v0 lambda u); by the grid relation
     # v0 lambda = -pi for the symmetric rule (the paper's e^{i pi l}) and 0 for Simpson.
-    a0 = -np.longdouble(g.v0) * np.longdouble(g.k0)
-    a0 = float(a0 - TWO_PI_LD * np.floor(a0 / TWO_PI_LD))
+    # -v0 k0 in turns: (M eta / 2) k0 / (2 pi); the default k0 = ln S0 - pi / eta takes off M/4
+    t0 = -np.longdouble(g.v0) * np.longdouble(g.kc) / TWO_PI_LD
+    if g.us:
+        t0 = t0 - np.longdouble(g.M) / 4
+    a0 = float(TWO_PI_LD * (t0 - np.floor(t0)))
     ph = np.exp(1j * a0) * (np.where(u % 2 == 0, 1.0, -1.0) if g.v0 != 0.0 else 1.0)
     return np.real(np.exp(-p.alpha * k) / (g.s * math.pi) * ph * math.sqrt(g.M) * y)
 

@@ -276,7 +276,10 @@ struct DenseConst {
   int64_t jmid;            // index of v = 0: 2^(n-1) for the symmetric rule, else 0
   double th_hi, th_lo;     // theta / (2 pi) as double-double, theta = eta (m_f - k0)
   double2 g0;              // exp(i v0 m_f)
-  double z0, dz;           // log2 of the readout scale e^{-alpha k_u} / (s pi) is z0 + dz u
+  double k0, nalog2e, lsf; // log2 of the readout scale e^{-alpha k_u} / (s pi) is nalog2e k_u + lsf
+  double dz;               // its step per unit of u, for short runs of consecutive outputs
+  int64_t us;              // k_u = k0 + lambda (u - us): the default grid is centred on ln S0
+  int n;
   double2 ro;              // exp(-i v0 k0)
   int simpson;
   int alt;                 // readout alternates sign with u (symmetric rule)
@@ -311,7 +314,7 @@ __device__ inline DenseConst dense_const(const cm_problem &pr) {
     two_sum(ch, 0.5, s, err);
     c.th_hi = s; c.th_lo = cl + err;
   } else {
-    two_prod(pr.eta, (log(pr.S0) - pr.k0) + rq, p, e);
+    drift_angle(pr.eta, log(pr.S0), pr.k0, rq, p, e);
     c.th_hi = p * CM_INV2PI_HI;
     c.th_lo = fma(p, CM_INV2PI_HI, -c.th_hi) + p * CM_INV2PI_LO + e * CM_INV2PI_HI;
   }
@@ -320,10 +323,16 @@ __device__ inline DenseConst dense_const(const cm_problem &pr) {
     double f = prod_cycles_frac(c.v0, log(pr.S0), 0) + prod_cycles_frac(c.v0, rq, 0);
     c.g0 = turn(f - floor(f));
   }
-  const double k0 = k0_of(pr);
+  // the default k0 = ln S0 - pi/eta is ln S0 - lambda M/2 exactly: strikes from ln S0 and an
+  // exact integer offset
+  const double k0 = k0_is_default(pr) ? log(pr.S0) : pr.k0;
+  c.us = k0_is_default(pr) ? ((int64_t)1 << (n - 1)) : 0;
   const double lam = 2.0 * M_PI / (ldexp(1.0, n) * pr.eta);
   const double sfac = c.simpson ? 1.0 / M_PI : 0.5 / M_PI;
-  c.z0 = -pr.alpha * k0 * M_LOG2E + log2(sfac);
+  c.k0 = k0;
+  c.n = n;
+  c.nalog2e = -pr.alpha * M_LOG2E;
+  c.lsf = log2(sfac);
   c.dz = -pr.alpha * lam * M_LOG2E;
   c.alt = !c.simpson;
   if (c.simpson) c.ro = cmk(1.0, 0.0);
@@ -365,10 +374,11 @@ __device__ __forceinline__ T integrand_at(const DenseProb<T> &d, int64_t j) {
   return fr<T>::mul(fr<T>::mul(hv, ph), g);
 }
 
-// C(k_u) = Re[e^{-alpha k_u}/(s pi) ro (+-1)^u y_u]; the scale is 2^{z0 + dz u} with the
+// C(k_u) = Re[e^{-alpha k_u}/(s pi) ro (+-1)^u y_u]; the scale is 2^z with the
 // exponent kept in FP64.
-// z = z0 + dz u, the log2 of the scale, is passed in: the last pass forms it for its R
-// outputs from the first one by adding multiples of dz times the output stride.
+// z, the log2 of the scale, is passed in: the last pass forms it for the first of its R
+// outputs from the accurate log-strike (strike_log) and for the others by adding multiples
+// of dz times the output stride.
 __device__ __forceinline__ float price_at(const DenseConst &c, int64_t u, double z, float2 y, bool bad) {
   if (bad) return NAN;
   const double zi = floor(z);
@@ -432,7 +442,9 @@ template <typename T> struct PriceDst {   // last pass: readout scalars, prices
     const int64_t k = item & (plen - 1);
     const int64_t b = ((item - k) << logR) + k;
     const int64_t u0 = b + (int64_t)q0 * plen, du = (int64_t)dq * plen;
-    const double z0 = fma(c->dz, (double)u0, c->z0), dz = c->dz * (double)du;
+    // the call's first output from its accurate log-strike; the others by small steps
+    const double z0 = fma(c->nalog2e, strike_log(c->k0, c->eta, c->n, (double)(u0 - c->us)), c->lsf);
+    const double dz = c->dz * (double)du;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int64_t u = u0 + r * du;

@@ -126,8 +126,9 @@ __device__ __forceinline__ double theta_frac(const cm_problem &pr, int s) {
     if (s == 0) { f += 0.5; f -= floor(f); }
     return f;
   }
-  const double a = (log(pr.S0) - pr.k0) + rq;
-  return prod_cycles_frac(pr.eta, a, s);
+  double hi, lo;
+  drift_angle(pr.eta, log(pr.S0), pr.k0, rq, hi, lo);
+  return cycles_frac(hi, lo, s);
 }
 
 // exp(i v0 m_f) as phase fraction (v0 = -eta 2^(n-1) for the symmetric rule, else 0).

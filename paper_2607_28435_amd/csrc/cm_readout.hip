@@ -36,7 +36,9 @@ template <> struct rd<double2> {
 
 // Per-instance readout scalars.
 struct ReadConst {
-  double k0, lam, alpha, sfac;   // sfac = sqrt(M) / (s pi)
+  double k0, eta, alpha, sfac;   // sfac = sqrt(M) / (s pi)
+  int64_t us;                    // k_u = k0 + lambda (u - us): the default grid is centred on ln S0
+  int n;
   double2 ro;                    // exp(-i v0 k0)
   bool alt;                      // sign alternates with u (symmetric rule)
 };
@@ -44,8 +46,12 @@ struct ReadConst {
 __device__ __forceinline__ ReadConst read_const(const cm_problem &pr, int n) {
   ReadConst c;
   const bool simpson = pr.quad == CM_QUAD_SIMPSON1;
-  c.k0 = k0_of(pr);
-  c.lam = 2.0 * M_PI / (ldexp(1.0, n) * pr.eta);
+  // the default k0 = ln S0 - pi/eta is k0 = ln S0 - lambda M/2 exactly, so index u sits at
+  // ln S0 + lambda (u - M/2) with an exact integer offset
+  c.k0 = k0_is_default(pr) ? log(pr.S0) : pr.k0;
+  c.us = k0_is_default(pr) ? ((int64_t)1 << (n - 1)) : 0;
+  c.eta = pr.eta;
+  c.n = n;
   c.alpha = pr.alpha;
   c.sfac = ldexp((n & 1) ? M_SQRT2 : 1.0, n >> 1) / ((simpson ? 1.0 : 2.0) * M_PI);
   c.alt = !simpson;
@@ -64,7 +70,7 @@ __device__ __forceinline__ ReadConst read_const(const cm_problem &pr, int n) {
 }
 
 __device__ __forceinline__ double read_price(const ReadConst &c, int64_t u, double2 yu, int absval) {
-  const double k = c.k0 + c.lam * (double)u;
+  const double k = strike_log(c.k0, c.eta, c.n, (double)(u - c.us));
   if (absval) return exp(-c.alpha * k) * c.sfac * hypot(yu.x, yu.y);
   double2 ro = c.ro;
   if (c.alt && (u & 1)) ro = cmk(-ro.x, -ro.y);
@@ -525,7 +531,7 @@ __global__ __launch_bounds__(256) void k_shot_price(const cm_problem *__restrict
     set_status(status, b, CM_E_INVALID);
   } else {
     const ReadConst rc = read_const(pr, n);
-    const double k = rc.k0 + rc.lam * (double)u;
+    const double k = strike_log(rc.k0, rc.eta, rc.n, (double)(u - rc.us));
     const double c = (double)counts[(int64_t)b * nk + s];
     price = exp(-rc.alpha * k) * rc.sfac * sqrt(nv * c / (double)R);
   }

@@ -40,6 +40,42 @@ __host__ __device__ __forceinline__ double prod_cycles_frac(double a, double b, 
   return cycles_frac(p, e, s);
 }
 
+// Phase angle eta (ln S0 - k0 + (r - q) T) of the first frequency step as a double-double
+// (hi + lo, radians), with ln S0 - k0 + (r - q) T summed error-free: on a grid centred far from
+// the money k0 is ~2^(n/2), and the rounded difference would shift every strike by up to half
+// its ulp (3e-11 at n = 40), moving each price by that times its slope in k.
+__host__ __device__ __forceinline__ void drift_angle(double eta, double lnS0, double k0, double rq, double &hi,
+                                                     double &lo) {
+#pragma clang fp contract(off)
+  double a, al, b, bl;
+  two_sum(lnS0, -k0, a, al);
+  two_sum(a, rq, b, bl);
+  two_prod(eta, b, hi, lo);
+  lo = fma(eta, al + bl, lo);
+}
+
+// Log-strike of grid index u, k_u = k0 + lambda u with lambda = 2 pi / (2^n eta): the strike
+// that the transform's phase exp(-2 pi i j u / 2^n) pairs with u (the grid relation
+// eta lambda = 2 pi / M of Section 2.1 holds exactly there). Formed from 2 pi / eta as a
+// double-double, its exact product with u and exact scaling by 2^-n, and an error-free sum
+// with k0, so that k_u stays within a few ulps of itself even where k0 and lambda u are large
+// and cancel (on a grid centred far from the money both are ~2^(n/2); rounding lambda first
+// would cost |lambda u| ulp(1), 4e-11 at n = 40, and the damping factor alpha times that).
+#define CM_2PI_LO 2.4492935982947064e-16
+__host__ __device__ __forceinline__ double strike_log(double k0, double eta, int n, double u) {
+#pragma clang fp contract(off)
+  const double c = CM_2PI / eta;
+  const double cl = (fma(-c, eta, CM_2PI) + CM_2PI_LO) / eta;   // 2 pi / eta = c + cl
+  double p, e;
+  two_prod(c, u, p, e);
+  e = fma(cl, u, e);
+  p = ldexp(p, -n);
+  e = ldexp(e, -n);
+  double sm, t;
+  two_sum(k0, p, sm, t);
+  return sm + (t + e);
+}
+
 // ------------------------------------------------------------------ rounding sweep
 // Per-workgroup scratch for one rounding job (FP64 complex, global memory). `tt` holds n
 // cores of core_cap elements; Y, X, Z, L, R, C hold mat_cap elements each.

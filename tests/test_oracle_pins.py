@@ -434,3 +434,33 @@ def test_heston_explosion_time_infinite_branch():
     assert len(sol.t_events[0]) == 0
     root = (-k - math.sqrt(D)) / (sv * sv)
     assert abs(sol.y[0, -1] - root) < 1e-8 * abs(root)
+
+
+def test_log_strike_is_the_exact_grid_point():
+    """k_u = k0 + 2 pi u / (M eta) within extended precision's 2^-62 |lambda (u - us)| plus two
+    ulps of k_u, on the paper's grid at n = 40 (k0 near -3.7e5, so lambda u and k0 cancel to
+    ~4.6 in the strike window) and on a default grid (k0 = ln S0 - pi / eta taken as a real
+    number, us = M/2): against the same sum in 50-digit decimal arithmetic (pi to 60 digits)."""
+    from decimal import Decimal, getcontext
+    getcontext().prec = 50
+    PI = Decimal("3.141592653589793238462643383279502884197169399375105820974944")
+    for p in (W.paper_bs_grid(40), W.heston_n24()):
+        g = O.grid(p)
+        M = 2 ** p.n
+        lam = 2.0 * math.pi / (M * p.eta)
+        u_atm = int(round((math.log(100.0) - g.k0) / lam))
+        us = np.array([0, 1, u_atm - 12345, u_atm, u_atm + 777, M - 1], dtype=np.int64)
+        got = g.k(us)
+        for uu, kk in zip(us, got):
+            # the default k0 is ln S0 - pi / eta as a real number
+            k0 = Decimal(p.k0) if p.k0 is not None else Decimal(math.log(p.S0)) - PI / Decimal(p.eta)
+            exact = k0 + 2 * PI * Decimal(int(uu)) / (Decimal(M) * Decimal(p.eta))
+            ush = int(uu) - (M // 2 if p.k0 is None else 0)
+            lamu = abs(2 * PI * Decimal(ush) / (Decimal(M) * Decimal(p.eta)))
+            bound = lamu * Decimal(2.0 ** -62) + 2 * Decimal(np.spacing(abs(float(kk))))
+            assert abs(Decimal(float(kk)) - exact) <= bound, (p.n, uu)
+        # the naive form rounds lambda first and misses the near-money strikes by far more
+        if p.n == 40:
+            naive = g.k0 + lam * float(u_atm)
+            exact = Decimal(g.k0) + 2 * PI * Decimal(u_atm) / (Decimal(M) * Decimal(p.eta))
+            assert abs(Decimal(naive) - exact) > 100 * Decimal(np.spacing(4.6))
