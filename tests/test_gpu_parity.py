@@ -240,6 +240,26 @@ def test_paper_grid_statevector_pin_through_gpu():
     assert e < 1e-13
 
 
+@pytest.mark.parametrize("n", [20, 28])
+def test_paper_grid_dense_fp64_floor(n):
+    """Section 4.1's FFT arm on the GPU dense path in FP64: on the paper's grid the NRMSE
+    against Black–Scholes over 0.5 <= K/S0 <= 1.5 stays at the FFT floor (the paper prints
+    4.4e-15 for n > 12) also at n = 28, where k0 ~ -8e3 and lambda u cancel to the strike."""
+    say("paper grid dense fp64 n", n)
+    p = W.paper_bs_grid(n)
+    got, _ = cm.dense_prices([p], cm.CM_C128)
+    g = O.grid(p)
+    lo = math.ceil((math.log(50.0) - g.k0) / g.lam)
+    hi = math.floor((math.log(150.0) - g.k0) / g.lam)
+    u = np.arange(lo, hi + 1, max(1, (hi - lo) // 100000))
+    sel = got[0][torch.from_numpy(u).to(got.device)].cpu().numpy()
+    del got
+    ref = O.bs_call(100.0, O.strike_of(p, u), 0.05, 0.0, 0.5, 0.3)
+    e = O.nrmse(sel, ref, 100.0)
+    say("  nrmse", e)
+    assert e < 4.4e-15
+
+
 @pytest.mark.parametrize("n", [24, 32, 40])
 def test_paper_grid_large_n_sfft(n):
     """The paper's two-sided grid (Section 4) at n = 24, 32 and 40 through the FP64 SFFT chain:
