@@ -31,9 +31,10 @@ constexpr int QNC = 96;         // max candidate intervals per depth
 constexpr int QI = QNC / 2;     // max split intervals per depth
 constexpr int QNPT = 2 * QP - 1;
 constexpr int PRE_CAP = QI + QP + 1;   // bond bound before rounding (<= 64)
-// LDS arena per workgroup: small on purpose (see cm_round.hip); the tree phase's candidate
-// values then live in the slab as well.
-constexpr int QLDS = 8 * 1024;
+// LDS arena per workgroup: small on purpose (see cm_round.hip), and with the static LDS
+// within a sixteenth of the CU's 160 KB so that the rounding launch keeps four one-wave
+// workgroups per SIMD; the tree phase's candidate values live in the slab.
+constexpr int QLDS = 7680;
 
 struct TreeDepth {
   int n_int;                 // split intervals at this depth

@@ -10,8 +10,10 @@ __host__ __device__ inline size_t al256r(size_t x) { return (x + 255) & ~(size_t
 // LDS arena per workgroup: small on purpose. The sweep is a chain of latency-bound steps, so
 // more resident workgroups per CU (their matrices then live in the L2-cached slab) beat
 // LDS-resident matrices with three workgroups per CU: measured 16.0 -> 7.3 ms for 4096
-// trains at n = 24.
-constexpr int RLDS = 8 * 1024;
+// trains at n = 24. 7.5 KB plus the 2.1 KB of static LDS lets 16 workgroups (the four waves
+// per SIMD that 128 VGPRs allow) share a CU's 160 KB; with 8 KB only 15 fit, and a batch of
+// 16 per CU ran its last sixteenth as a second wave.
+constexpr int RLDS = 7680;
 // Workspace of one persistent workgroup: its hot matrices (Y, X, Z, L, R, C of cap d cap
 // elements and the Jacobi pair of cap^2) and, apart from them, the orthogonalised train of the
 // first sweep (n_max cores). The hot blocks of all workgroups sit next to each other at the
