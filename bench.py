@@ -572,25 +572,31 @@ def surrogate_run(cm, torch, steps):
     ok = acc & (st == 0)
     err = np.abs(res["price"] - ref_prices)
     # network + gate throughput on all queries (device-resident inputs)
+    # (50 untimed calls first: the clocks ramp up over the first tens of milliseconds of load;
+    # then the median of five rounds of ten calls)
     qd = torch.from_numpy(q.astype(np.float32)).cuda()
-    s.predict(qd)
+    for _ in range(50):
+        s.predict(qd)
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    reps = 10
-    e0.record(stream)
-    for _ in range(reps):
-        s.predict(qd)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    net_s = e0.elapsed_time(e1) * 1e-3 / reps
+    reps, rounds = 10, []
+    for _ in range(5):
+        e0.record(stream)
+        for _ in range(reps):
+            s.predict(qd)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        rounds.append(e0.elapsed_time(e1) * 1e-3 / reps)
+    net_s = float(np.median(rounds))
     flops = 2.0 * 199681 * nq          # algorithmic (one multiply-add per weight per query)
     executed = flops + 2.0 * 3 * 65536 * nq   # the activation split runs the 256x256 layers twice
     ach = flops / net_s / 1e12
     return {"train_samples": int(len(Y)), "train_steps": info["steps"], "train_s": info["seconds"],
             "data_gen_s": gen_s, "final_train_loss": info["final_loss"], "gate_calibration": cal,
             "eval_queries": nq, "accept_rate": float(acc.mean()), "in_box_accept_rate": float(acc[:nq - nq // 10].mean()),
-            "in_gate_max_abs_err_over_S0": float(err[ok].max()), "in_gate_p999_abs_err_over_S0":
-                float(np.quantile(err[ok], 0.999)), "sfft_reference_failures": int((st != 0).sum()),
+            "in_gate_max_abs_err_over_S0": float(err[ok].max()) if ok.any() else None,
+            "in_gate_p999_abs_err_over_S0": float(np.quantile(err[ok], 0.999)) if ok.any() else None,
+            "sfft_reference_failures": int((st != 0).sum()),
             "queries_per_s": nq / net_s, "sfft_queries_per_s": nq / sfft_s, "speedup_vs_sfft": sfft_s / net_s,
             "roofline": {"kernel": "k_mlp_fused + k_gate", "bound": "mfma",
                          "achieved": ach, "peak": BF16_DENSE_TFLOPS, "unit": "TFLOP/s",

@@ -281,6 +281,10 @@ constexpr int FM = 64;               // queries per tile
 constexpr int FQB = FM / 32;         // query blocks
 constexpr int FP = NW + 8;           // LDS row pitch (bf16): 528 bytes, 16-byte aligned
 constexpr size_t FUSED_LDS = sizeof(uint16_t) * 2 * FM * FP;
+#ifndef CM_FPD
+#define CM_FPD 3
+#endif
+constexpr int FPD = CM_FPD;          // K steps between a weight fragment's load and its use
 
 __device__ __forceinline__ void split8(const float *v, s16x8 &hi, s16x8 &lo) {
 #pragma unroll
@@ -393,10 +397,17 @@ __global__ __launch_bounds__(256, 2) void k_mlp_fused(const float *__restrict__ 
         for (int qb = 0; qb < FQB; ++qb)
 #pragma unroll
           for (int v = 0; v < 16; ++v) acc[mb][qb][v] = 0.0f;
-      // A fragment of neuron block mb at K step kk: W[n][kk + 8 hi32 .. +7], n = 64 w + 32 mb + l32
+      // A fragment of neuron block mb at K step kk: W[n][kk + 8 hi32 .. +7], n = 64 w + 32 mb + l32,
+      // read from L2 FPD steps ahead (a step's eight MFMAs take less time than an L2 read
+      // under load) into a ring indexed statically by the fully unrolled K loop
       const uint16_t *wrow0 = W + (int64_t)(64 * w + l32) * NW + 8 * hi32;
       const uint16_t *wrow1 = wrow0 + (int64_t)32 * NW;
-      s16x8 an0 = *(const s16x8 *)wrow0, an1 = *(const s16x8 *)wrow1;
+      s16x8 ar0[FPD], ar1[FPD];
+#pragma unroll
+      for (int s = 0; s < FPD; ++s) {
+        ar0[s] = *(const s16x8 *)(wrow0 + 16 * s);
+        ar1[s] = *(const s16x8 *)(wrow1 + 16 * s);
+      }
       // B fragments of query block qb at K step kk: Ah / Al[q][kk + 8 hi32 .. +7], q = 32 qb + l32
       const int boff = l32 * FP + 8 * hi32;
       s16x8 bhn[FQB], bln[FQB];
@@ -405,17 +416,21 @@ __global__ __launch_bounds__(256, 2) void k_mlp_fused(const float *__restrict__ 
         bhn[qb] = *(const s16x8 *)&Ah[boff + 32 * qb * FP];
         bln[qb] = *(const s16x8 *)&Al[boff + 32 * qb * FP];
       }
-      for (int kk = 0; kk < NW; kk += 16) {
-        const bf16x8 A0 = __builtin_bit_cast(bf16x8, an0), A1 = __builtin_bit_cast(bf16x8, an1);
+#pragma unroll
+      for (int ks = 0; ks < NW / 16; ++ks) {
+        const int kk = 16 * ks;
+        const bf16x8 A0 = __builtin_bit_cast(bf16x8, ar0[ks % FPD]), A1 = __builtin_bit_cast(bf16x8, ar1[ks % FPD]);
+        if (ks + FPD < NW / 16) {
+          ar0[ks % FPD] = *(const s16x8 *)(wrow0 + kk + 16 * FPD);
+          ar1[ks % FPD] = *(const s16x8 *)(wrow1 + kk + 16 * FPD);
+        }
         s16x8 bh[FQB], bl[FQB];
 #pragma unroll
         for (int qb = 0; qb < FQB; ++qb) {
           bh[qb] = bhn[qb];
           bl[qb] = bln[qb];
         }
-        if (kk + 16 < NW) {   // next step's operands, in flight during this step's MFMAs
-          an0 = *(const s16x8 *)(wrow0 + kk + 16);
-          an1 = *(const s16x8 *)(wrow1 + kk + 16);
+        if (kk + 16 < NW) {   // next step's activations, in flight during this step's MFMAs
 #pragma unroll
           for (int qb = 0; qb < FQB; ++qb) {
             bhn[qb] = *(const s16x8 *)&Ah[boff + 32 * qb * FP + kk + 16];

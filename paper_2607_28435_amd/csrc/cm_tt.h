@@ -120,6 +120,23 @@ __device__ __forceinline__ double2 dot4(int K, FA a, FB b) {
   return acc;
 }
 
+// Brings two byte ranges into the caches with one memory latency: every lane loads one dword
+// of up to two 128-byte lines of each range and all four values are consumed together. The
+// short dependent dot products that follow then hit the L2 instead of paying one miss per
+// batch of operands (with thousands of resident workgroups the sweep's working set does not
+// stay in the L2 between bonds).
+__device__ __forceinline__ void touch_lines(const void *p, size_t pb, const void *q, size_t qb) {
+  const char *a = (const char *)p, *b = (const char *)q;
+  const int la = (int)((pb + 127) >> 7), lb = (int)((qb + 127) >> 7);
+  const int i0 = threadIdx.x, i1 = threadIdx.x + CM_WG;
+  float v0 = 0.f, v1 = 0.f, v2 = 0.f, v3 = 0.f;
+  if (i0 < la) v0 = *(const float *)(a + ((size_t)i0 << 7));
+  if (i1 < la) v1 = *(const float *)(a + ((size_t)i1 << 7));
+  if (i0 < lb) v2 = *(const float *)(b + ((size_t)i0 << 7));
+  if (i1 < lb) v3 = *(const float *)(b + ((size_t)i1 << 7));
+  asm volatile("" ::"v"(v0), "v"(v1), "v"(v2), "v"(v3));
+}
+
 __device__ __forceinline__ void merge_flags(const la::Sh &sh, int *code) {
   if (threadIdx.x == 0) {
     if (sh.nonfinite && *code == CM_OK) *code = CM_E_NONFINITE;
@@ -236,6 +253,8 @@ __device__ __forceinline__ double round_train(int n, int d, const CoreSrc &src, 
     };
     if (skip_a) {
       const int64_t base = src.off[l];
+      const size_t esz = src.dtype == CM_C64 ? sizeof(float2) : sizeof(double2);
+      touch_lines((const char *)src.cores + esz * base, esz * (size_t)kl * d * kr, Cg, sizeof(double2) * (size_t)kr * rpp);
       if (src.dtype == CM_C64) {
         const float2 *cs = (const float2 *)src.cores + base;
         xform([&](int row, int t) { return cstore<float2>::ld(cs, (int64_t)row * kr + t); });
@@ -245,6 +264,7 @@ __device__ __forceinline__ double round_train(int n, int d, const CoreSrc &src, 
       }
     } else {
       const int64_t ld = (int64_t)kl * d;
+      touch_lines(core, sizeof(double2) * (size_t)ld * kr, Cg, sizeof(double2) * (size_t)kr * rpp);
       xform([&](int row, int t) { return core[row + ld * t]; });
     }
     __syncthreads();
