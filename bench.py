@@ -520,13 +520,32 @@ FFT_SOURCES = ["paper_2607_28435_amd/csrc/cm_fft.hip", "paper_2607_28435_amd/csr
                "paper_2607_28435_amd/csrc/cm_tt.h", "paper_2607_28435_amd/csrc/cm_linalg.h",
                "paper_2607_28435_amd/csrc/cm_internal.h", "include/cm.h"]
 SAMPLE_SOURCES = ["paper_2607_28435_amd/csrc/cm_sample.hip", "paper_2607_28435_amd/csrc/cm_internal.h", "include/cm.h"]
+BUILD_SOURCES = ["paper_2607_28435_amd/csrc/cm_qtt.hip", "paper_2607_28435_amd/csrc/cm_cf.h",
+                 "paper_2607_28435_amd/csrc/cm_tt.h", "paper_2607_28435_amd/csrc/cm_linalg.h",
+                 "paper_2607_28435_amd/csrc/cm_internal.h", "include/cm.h"]
+ROUND_SOURCES = ["paper_2607_28435_amd/csrc/cm_round.hip", "paper_2607_28435_amd/csrc/cm_tt.h",
+                 "paper_2607_28435_amd/csrc/cm_linalg.h", "paper_2607_28435_amd/csrc/cm_internal.h", "include/cm.h"]
+READ_SOURCES = ["paper_2607_28435_amd/csrc/cm_readout.hip", "paper_2607_28435_amd/csrc/cm_cf.h",
+                "paper_2607_28435_amd/csrc/cm_tt.h", "paper_2607_28435_amd/csrc/cm_linalg.h",
+                "paper_2607_28435_amd/csrc/cm_internal.h", "include/cm.h"]
+MLP_SOURCES = ["paper_2607_28435_amd/csrc/cm_mlp.hip", "paper_2607_28435_amd/csrc/cm_internal.h", "include/cm.h"]
+_F = 1.9999246625669753   # FETCH_SIZE scale of the 1 GiB copy (chain runs)
+_FS = 1.9999253777690837  # the same for the surrogate runs
 PROFILED_TRAFFIC = {
-    "k_zipup": {"sha": "64b4c705738e4674", "bytes": (441698.9 * 2.0 + 1062202.1) * 1024,
+    "k_zipup": {"sha": "6fc8f172ada983c7", "bytes": (258571.8 * _F + 977445.4) * 1024,
                 "per": "launch (4096 instances, n=24, 1536 workgroups)"},
-    "dense": {"sha": "c9d4c6c6155acbcc", "bytes": ((156.1 + 65630.0) * 2.0 + 131075.8 + 65536.0) * 1024,
+    "build": {"sha": "8beb164cb51476a9", "bytes": ((36312.4 + 419884.6) * _F + 236218.3 + 899533.4) * 1024,
+              "per": "build (k_build_qtt + k_build_round, 4096 instances, n=24)"},
+    "k_tt_round": {"sha": "55792a2c57b2d5b6", "bytes": (320314.4 * _F + 701396.9) * 1024,
+                   "per": "launch (4096 instances, n=24, 4096 workgroups)"},
+    "k_readout": {"sha": "19c08c73e1c856b4", "bytes": ((787.8 + 105291.2 + 788.7) * _F + 131072.0) * 1024,
+                  "per": "read-out (k_readout<8> + <16> + <32>, 4096 instances x 4096 strikes)"},
+    "dense": {"sha": "fe6604eed381ae90", "bytes": ((151.4 + 65636.5) * _F + 131074.8 + 65536.0) * 1024,
               "per": "grid (k_fft_first + k_fft_next, n=24)"},
-    "k_sample": {"sha": "766aaa9ffdc474f6", "bytes": (3780882.2 * 2.0 + 131072.0) * 1024,
+    "k_sample": {"sha": "8b145612c6a24d0c", "bytes": (3779842.3 * _F + 131072.0) * 1024,
                  "per": "launch (4096 instances x 4096 shots, n=24)"},
+    "surrogate": {"sha": "fa20663cd7bd9d7c", "bytes": ((16041.5 + 16407.0) * _FS + 4096.0 + 8192.0) * 1024,
+                  "per": "pass over 2^20 queries (k_mlp_fused + k_gate)"},
 }
 
 
@@ -591,6 +610,10 @@ def surrogate_run(cm, torch, steps):
     flops = 2.0 * 199681 * nq          # algorithmic (one multiply-add per weight per query)
     executed = flops + 2.0 * 3 * 65536 * nq   # the activation split runs the 256x256 layers twice
     ach = flops / net_s / 1e12
+    # inputs (7 floats) read and network output written by the network; inputs and output
+    # read, price and accept written by the gate
+    algo_bytes = float(nq) * (4 * 8 + 4 * 10)
+    tr = profiled_traffic("surrogate", MLP_SOURCES)
     return {"train_samples": int(len(Y)), "train_steps": info["steps"], "train_s": info["seconds"],
             "data_gen_s": gen_s, "final_train_loss": info["final_loss"], "gate_calibration": cal,
             "eval_queries": nq, "accept_rate": float(acc.mean()), "in_box_accept_rate": float(acc[:nq - nq // 10].mean()),
@@ -600,7 +623,10 @@ def surrogate_run(cm, torch, steps):
             "queries_per_s": nq / net_s, "sfft_queries_per_s": nq / sfft_s, "speedup_vs_sfft": sfft_s / net_s,
             "roofline": {"kernel": "k_mlp_fused + k_gate", "bound": "mfma",
                          "achieved": ach, "peak": BF16_DENSE_TFLOPS, "unit": "TFLOP/s",
-                         "frac": ach / BF16_DENSE_TFLOPS, "executed_tflops": executed / net_s / 1e12}}
+                         "frac": ach / BF16_DENSE_TFLOPS, "executed_tflops": executed / net_s / 1e12,
+                         "algorithmic_bytes": algo_bytes, "traffic": tr,
+                         "traffic_per": PROFILED_TRAFFIC["surrogate"]["per"],
+                         "traffic_over_algorithmic": (tr / algo_bytes) if tr else None}}
 
 
 def main():
@@ -774,7 +800,8 @@ def main():
     B = args.batch
     stage_rooflines = {
         "build": alu_roofline("k_build_qtt + k_build_round (cm_build_qtt)", ms["build"], 0.0, SURVEY_BUILD_F64 * B,
-                              es * b_x + 128 * B, extra={"flops_model": "scope-table estimate, 3e6 FP64 per grid"}),
+                              es * b_x + 128 * B, "build", BUILD_SOURCES,
+                              extra={"flops_model": "scope-table estimate, 3e6 FP64 per grid"}),
         "zipup": alu_roofline("k_zipup (cm_sfft_apply)", ms["apply"], f32, f64, es * (b_x + b_yz), "k_zipup",
                               ZIPUP_SOURCES, extra={
                                   "flops_model": "rank-exact (zipup_flops)",
@@ -782,11 +809,11 @@ def main():
                                                           SURVEY_ZIPUP_F64 / (FP64_VECTOR_TFLOPS * 1e12)) * B /
                                                          (ms["apply"] * 1e-3))}),
         "round": alu_roofline("k_tt_round (cm_tt_round)", ms["round"], 0.0, f_round, es * (b_yz + b_y),
-                              extra={"flops_model": "rank-exact (round_flops)",
+                              "k_tt_round", ROUND_SOURCES, extra={"flops_model": "rank-exact (round_flops)",
                                      "frac_scope_formula": SURVEY_ROUND_F64 * B / (FP64_VECTOR_TFLOPS * 1e12) /
                                      (ms["round"] * 1e-3)}),
         "readout": alu_roofline("k_readout (cm_readout_prices)", ms["read"], f_read, 0.0,
-                                es * b_y + 16 * nk * B, extra={"flops_model": "rank-exact, shared suffixes "
+                                es * b_y + 16 * nk * B, "k_readout", READ_SOURCES, extra={"flops_model": "rank-exact, shared suffixes "
                                                                               "(readout_flops)"}),
     }
     frac = stage_rooflines["zipup"]["frac"]
