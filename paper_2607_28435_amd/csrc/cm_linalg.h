@@ -113,6 +113,19 @@ __device__ __forceinline__ int group_for(int ncols) {
   return g > 64 ? 64 : (g < 1 ? 1 : g);
 }
 
+// q = n / d and r = n - q d for 0 <= n < 2^20 and 1 <= d <= 2^12 (the index decoding of the
+// small matrices here): (float)n is exact and n times the hardware reciprocal of d (within an
+// ulp) is within n / d * 2^-22 < 1/4 of n / d, so the truncated quotient is off by at most
+// one, which one correction each way fixes. A third of the instructions of a general 32-bit
+// division; d is loop-invariant in every use, so the reciprocal is taken once per loop.
+__device__ __forceinline__ int divmod_small(int n, int d, int &r) {
+  int q = (int)((float)n * __builtin_amdgcn_rcpf((float)d));
+  r = n - q * d;
+  if (r >= d) { ++q; r -= d; }
+  if (r < 0) { --q; r += d; }
+  return q;
+}
+
 // Shared per-workgroup bookkeeping for the factorisations (lives in LDS).
 struct Sh {
   double red[CM_WG / 64 + 2];
@@ -281,7 +294,11 @@ __device__ __forceinline__ void qr_form_q(const double2 *T, int m, int k, const 
 // descending order. Sets sh.noconv if the sweep limit was reached, sh.nonfinite on NaN/Inf.
 __device__ __forceinline__ void jacobi_onesided(double2 *S, double2 *J, int m, int s, Sh &sh) {
   const int tid = threadIdx.x;
-  for (int e = tid; e < s * s; e += CM_WG) J[e] = cmk((e % s) == (e / s) ? 1.0 : 0.0, 0.0);
+  for (int e = tid; e < s * s; e += CM_WG) {
+    int i;
+    const int j = divmod_small(e, s, i);
+    J[e] = cmk(i == j ? 1.0 : 0.0, 0.0);
+  }
   if (tid == 0) { sh.noconv = 0; sh.nonfinite = 0; }
   __syncthreads();
   const int N = s + (s & 1);
@@ -424,7 +441,8 @@ __device__ __forceinline__ int qr_thin(double2 *Y, int m, int p, double2 *Qout, 
   qr_householder(Y, m, m, kq, p, sh);
   // R (with trailing columns when p > m)
   for (int e = tid; e < kq * p; e += CM_WG) {
-    const int i = e % kq, j = e / kq;
+    int i;
+    const int j = divmod_small(e, kq, i);
     Rout[e] = (i <= j) ? Y[i + (int64_t)m * j] : cmk(0.0, 0.0);
   }
   __syncthreads();
@@ -564,7 +582,8 @@ __device__ __forceinline__ int cpqr_trunc(double2 *T, int m, int p, double delta
   if (tid == 0) sh.err2 = tail_sh;
   // B = R[:k, :] P^T  (rows r < k; R[r, c] = 0 for r > c)
   for (int e = tid; e < k * p; e += CM_WG) {
-    const int r = e % k, c = e / k;
+    int r;
+    const int c = divmod_small(e, k, r);
     B[r + (int64_t)k * perm[c]] = (r <= c) ? T[r + (int64_t)m * c] : cmk(0.0, 0.0);
   }
   // Qk = H_0 ... H_{k-1} [I_k; 0]
@@ -604,7 +623,8 @@ __device__ __forceinline__ int svd_trunc_rows(double2 *X, bool x_lds, int a, int
   double2 *Jw = sj_lds ? lds + a * kc : J;
   // S = B^H (a x kc, ld a)
   for (int e = tid; e < a * kc; e += CM_WG) {
-    const int i = e % a, j = e / a;
+    int i;
+    const int j = divmod_small(e, a, i);
     Sw[e] = cconj(Y[j + (int64_t)kc * i]);
   }
   __syncthreads();
@@ -615,11 +635,13 @@ __device__ __forceinline__ int svd_trunc_rows(double2 *X, bool x_lds, int a, int
   const int k = sh.k;
   // L = (B^H J)[:, perm[:k]];  Rk^H = Q J[:, perm[:k]]
   for (int e = tid; e < a * k; e += CM_WG) {
-    const int i = e % a, j = e / a;
+    int i;
+    const int j = divmod_small(e, a, i);
     L[e] = Sw[i + (int64_t)a * sh.perm[j]];
   }
   for (int e = tid; e < k * b; e += CM_WG) {
-    const int i = e / b, c = e - i * b;   // lanes run along a row of Rk: Z reads are coalesced
+    int c;
+    const int i = divmod_small(e, b, c);   // lanes run along a row of Rk: Z reads are coalesced
     const double2 *jc = Jw + (int64_t)kc * sh.perm[i];
     double2 acc = cmk(0.0, 0.0);
     for (int t = 0; t < kc; ++t) cfma(acc, Z[c + (int64_t)b * t], jc[t]);

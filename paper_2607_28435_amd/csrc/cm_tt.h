@@ -186,8 +186,9 @@ __device__ __forceinline__ double round_train(int n, int d, const CoreSrc &src, 
     const double2 *Cg = w.C;
     auto yform = [&](auto ld) {
       for (int e = tid; e < rows * rr; e += CM_WG) {
-        const int i = e % rows, j = e / rows;
-        const int a = i / d, ph = i % d;
+        int i, ph;
+        const int j = la::divmod_small(e, rows, i);
+        const int a = la::divmod_small(i, d, ph);
         Yw[e] = dot4(rl, [&](int t) { return Cg[a + kprev * t]; }, [&](int t) { return ld(((int64_t)t * d + ph) * rr + j); });
       }
     };
@@ -245,8 +246,9 @@ __device__ __forceinline__ double round_train(int n, int d, const CoreSrc &src, 
     double2 *Xw = x_lds ? lds : w.X;
     auto xform = [&](auto rowld) {
       for (int e = tid; e < kl * b; e += CM_WG) {
-        const int row = e / rpp, j = e - row * rpp;   // row = i d + ph
-        const int i = row / d, ph = row - i * d;
+        int j, ph;
+        const int row = la::divmod_small(e, rpp, j);   // row = i d + ph
+        const int i = la::divmod_small(row, d, ph);
         const double2 *cj = Cg + kr * j;
         Xw[ph * rpp + j + b * i] = cconj(dot4(kr, [&](int t) { return rowld(row, t); }, [&](int t) { return cj[t]; }));
       }

@@ -338,7 +338,11 @@ __device__ __forceinline__ int zip_site_pair(char *arena, const SiteDims &sd, co
         T *Db = Dch + ((ch0 / 4) & 1) * dchunk;
         __syncthreads();   // staging done (first chunk) / this buffer's previous readers done
         for (int e = tid; e < dchunk; e += CM_WG) {
-          const int rpp = e % r1, j = (e / r1) & 1, ww = (e / (2 * r1)) % w0, cc = e / (2 * r1 * w0);
+          // e = ((cc w0 + ww) 2 + j) r1 + rpp
+          int pr, ww;
+          const int row = la::divmod_small(e, 2 * r1, pr);
+          const int cc = la::divmod_small(row, w0, ww);
+          const int j = pr >= r1 ? 1 : 0, rpp = pr - j * r1;
           typename A::type acc = A::zero();
           if (ch0 + cc < chi) {
             const T *crow = Cl + ((ch0 + cc) * w0 + ww) * r0;
@@ -656,7 +660,11 @@ __global__ __launch_bounds__(CM_WG, 3) void k_zipup(TTView w, int w_slots, TTVie
       T *Yout = Yc + y.coff(b, l);
       int k;
       if (!last && pair_site_fits<T>(sd, chicap, zlds_bytes<T>()))
-        k = (p <= 32 && m <= 32) ? zip_site_pair<T, 4, 8>(lds_arena, sd, Wl, Al, C, Yout, delta2, chicap, &code_sh)
+        k =
+#ifdef CM_ZIP_NARROW_G4
+            (p <= 16 && m <= 32) ? zip_site_pair<T, 8, 4>(lds_arena, sd, Wl, Al, C, Yout, delta2, chicap, &code_sh) :
+#endif
+            (p <= 32 && m <= 32) ? zip_site_pair<T, 4, 8>(lds_arena, sd, Wl, Al, C, Yout, delta2, chicap, &code_sh)
             : (p <= 64 && m <= 32) ? zip_site_pair<T, 8, 4>(lds_arena, sd, Wl, Al, C, Yout, delta2, chicap, &code_sh)
             : p <= 64            ? zip_site_pair<T, 12, 4>(lds_arena, sd, Wl, Al, C, Yout, delta2, chicap, &code_sh)
             : m <= 16            ? zip_site_pair<T, 8, 2>(lds_arena, sd, Wl, Al, C, Yout, delta2, chicap, &code_sh)
