@@ -120,6 +120,30 @@ __device__ __forceinline__ double2 dot4(int K, FA a, FB b) {
   return acc;
 }
 
+// sum_{t < K} a[t] b[t] for a contiguous row a (storage S) and a contiguous FP64 column b:
+// groups of four terms whose eight loads share one base pointer each (immediate offsets) and
+// are issued together, two accumulators, then the remaining terms one by one. No masking
+// inside the groups: a masked tail costs more selects than the arithmetic it guards.
+template <typename S>
+__device__ __forceinline__ double2 dot_contig(const S *__restrict__ a, const double2 *__restrict__ b, int K) {
+  double2 s0 = cmk(0.0, 0.0), s1 = cmk(0.0, 0.0);
+  int t = 0;
+  for (; t + 4 <= K; t += 4) {
+    double2 x[4], y[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      x[u] = cstore<S>::ld(a, t + u);
+      y[u] = b[t + u];
+    }
+    cfma(s0, x[0], y[0]);
+    cfma(s1, x[1], y[1]);
+    cfma(s0, x[2], y[2]);
+    cfma(s1, x[3], y[3]);
+  }
+  for (; t < K; ++t) cfma(s0, cstore<S>::ld(a, t), b[t]);
+  return cadd(s0, s1);
+}
+
 // Brings two byte ranges into the caches with one memory latency: every lane loads one dword
 // of up to two 128-byte lines of each range and all four values are consumed together. The
 // short dependent dot products that follow then hit the L2 instead of paying one miss per
@@ -244,30 +268,37 @@ __device__ __forceinline__ double round_train(int n, int d, const CoreSrc &src, 
     // once per bond so that each element's loads are issued together.
     const bool x_lds = lds != nullptr && kl * b <= lds_elems;
     double2 *Xw = x_lds ? lds : w.X;
-    auto xform = [&](auto rowld) {
+    // the destination is resolved per call so that the LDS case stores with LDS instructions
+    auto xform_to = [&](double2 *Xd, auto rowdot) {
       for (int e = tid; e < kl * b; e += CM_WG) {
         int j, ph;
         const int row = la::divmod_small(e, rpp, j);   // row = i d + ph
         const int i = la::divmod_small(row, d, ph);
-        const double2 *cj = Cg + kr * j;
-        Xw[ph * rpp + j + b * i] = cconj(dot4(kr, [&](int t) { return rowld(row, t); }, [&](int t) { return cj[t]; }));
+        Xd[ph * rpp + j + b * i] = cconj(rowdot(row, Cg + kr * j));
       }
+    };
+    auto xform = [&](auto rowdot) {
+      if (x_lds) xform_to(lds, rowdot);
+      else xform_to(w.X, rowdot);
     };
     if (skip_a) {
       const int64_t base = src.off[l];
       const size_t esz = src.dtype == CM_C64 ? sizeof(float2) : sizeof(double2);
       touch_lines((const char *)src.cores + esz * base, esz * (size_t)kl * d * kr, Cg, sizeof(double2) * (size_t)kr * rpp);
+      // source cores are row-major [row][t]: contiguous rows
       if (src.dtype == CM_C64) {
         const float2 *cs = (const float2 *)src.cores + base;
-        xform([&](int row, int t) { return cstore<float2>::ld(cs, (int64_t)row * kr + t); });
+        xform([&](int row, const double2 *cj) { return dot_contig(cs + row * kr, cj, kr); });
       } else {
         const double2 *cs = (const double2 *)src.cores + base;
-        xform([&](int row, int t) { return cs[(int64_t)row * kr + t]; });
+        xform([&](int row, const double2 *cj) { return dot_contig(cs + row * kr, cj, kr); });
       }
     } else {
       const int64_t ld = (int64_t)kl * d;
       touch_lines(core, sizeof(double2) * (size_t)ld * kr, Cg, sizeof(double2) * (size_t)kr * rpp);
-      xform([&](int row, int t) { return core[row + ld * t]; });
+      xform([&](int row, const double2 *cj) {
+        return dot4(kr, [&](int t) { return core[row + ld * t]; }, [&](int t) { return cj[t]; });
+      });
     }
     __syncthreads();
     OutT *out = dst_cores + dst_off[l];
