@@ -281,10 +281,7 @@ constexpr int FM = 64;               // queries per tile
 constexpr int FQB = FM / 32;         // query blocks
 constexpr int FP = NW + 8;           // LDS row pitch (bf16): 528 bytes, 16-byte aligned
 constexpr size_t FUSED_LDS = sizeof(uint16_t) * 2 * FM * FP;
-#ifndef CM_FPD
-#define CM_FPD 3
-#endif
-constexpr int FPD = CM_FPD;          // K steps between a weight fragment's load and its use
+constexpr int FPD = 3;               // K steps between a weight fragment's load and its use
 
 __device__ __forceinline__ void split8(const float *v, s16x8 &hi, s16x8 &lo) {
 #pragma unroll
