@@ -99,27 +99,6 @@ struct CoreSrc {
   }
 };
 
-// sum_{t < K} a(t) b(t) for complex FP64 operands read through the functors, four terms at
-// a time: the four pairs of loads are issued before any is used, so one memory latency
-// covers four terms instead of one.
-template <typename FA, typename FB>
-__device__ __forceinline__ double2 dot4(int K, FA a, FB b) {
-  double2 acc = cmk(0.0, 0.0);
-  for (int t0 = 0; t0 < K; t0 += 4) {
-    double2 x[4], y[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int t = t0 + u < K ? t0 + u : K - 1;
-      x[u] = a(t);
-      y[u] = b(t);
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (t0 + u < K) cfma(acc, x[u], y[u]);
-  }
-  return acc;
-}
-
 // sum_{t < K} a[t] b[t] for a contiguous row a (storage S) and a contiguous FP64 column b:
 // groups of four terms whose eight loads share one base pointer each (immediate offsets) and
 // are issued together, two accumulators, then the remaining terms one by one. No masking
@@ -141,6 +120,32 @@ __device__ __forceinline__ double2 dot_contig(const S *__restrict__ a, const dou
     cfma(s1, x[3], y[3]);
   }
   for (; t < K; ++t) cfma(s0, cstore<S>::ld(a, t), b[t]);
+  return cadd(s0, s1);
+}
+
+// sum_{t < K} a[t sa] b[t sb] for strided operands (a in storage S, b in FP64): the same
+// groups of four terms with pointers advanced by whole strides, two accumulators, and the
+// remainder one by one.
+template <typename S>
+__device__ __forceinline__ double2 dot_strided(const S *__restrict__ a, int64_t sa, const double2 *__restrict__ b,
+                                               int64_t sb, int K) {
+  double2 s0 = cmk(0.0, 0.0), s1 = cmk(0.0, 0.0);
+  int t = 0;
+  for (; t + 4 <= K; t += 4) {
+    double2 x[4], y[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      x[u] = cstore<S>::ld(a, u * sa);
+      y[u] = b[u * sb];
+    }
+    a += 4 * sa;
+    b += 4 * sb;
+    cfma(s0, x[0], y[0]);
+    cfma(s1, x[1], y[1]);
+    cfma(s0, x[2], y[2]);
+    cfma(s1, x[3], y[3]);
+  }
+  for (; t < K; ++t, a += sa, b += sb) cfma(s0, cstore<S>::ld(a, 0), b[0]);
   return cadd(s0, s1);
 }
 
@@ -208,21 +213,18 @@ __device__ __forceinline__ double round_train(int n, int d, const CoreSrc &src, 
     double2 *Yw = in_lds ? lds : w.Y;
     const int64_t base = src.off[l];
     const double2 *Cg = w.C;
-    auto yform = [&](auto ld) {
+    // Y[(a, ph)][j] = sum_t C[a][t] core[t][ph][j]: the core's column (ph, j) has stride d rr,
+    // C's row a stride kprev
+    auto yform = [&](const auto *cs) {
       for (int e = tid; e < rows * rr; e += CM_WG) {
         int i, ph;
         const int j = la::divmod_small(e, rows, i);
         const int a = la::divmod_small(i, d, ph);
-        Yw[e] = dot4(rl, [&](int t) { return Cg[a + kprev * t]; }, [&](int t) { return ld(((int64_t)t * d + ph) * rr + j); });
+        Yw[e] = dot_strided(cs + ph * rr + j, (int64_t)d * rr, Cg + a, (int64_t)kprev, rl);
       }
     };
-    if (src.dtype == CM_C64) {
-      const float2 *cs = (const float2 *)src.cores + base;
-      yform([&](int64_t e) { return cstore<float2>::ld(cs, e); });
-    } else {
-      const double2 *cs = (const double2 *)src.cores + base;
-      yform([&](int64_t e) { return cs[e]; });
-    }
+    if (src.dtype == CM_C64) yform((const float2 *)src.cores + base);
+    else yform((const double2 *)src.cores + base);
     __syncthreads();
     double2 *core = w.tt + (int64_t)l * w.core_cap;
     if (l == n - 1) {
@@ -296,9 +298,7 @@ __device__ __forceinline__ double round_train(int n, int d, const CoreSrc &src, 
     } else {
       const int64_t ld = (int64_t)kl * d;
       touch_lines(core, sizeof(double2) * (size_t)ld * kr, Cg, sizeof(double2) * (size_t)kr * rpp);
-      xform([&](int row, const double2 *cj) {
-        return dot4(kr, [&](int t) { return core[row + ld * t]; }, [&](int t) { return cj[t]; });
-      });
+      xform([&](int row, const double2 *cj) { return dot_strided(core + row, ld, cj, (int64_t)1, kr); });
     }
     __syncthreads();
     OutT *out = dst_cores + dst_off[l];
