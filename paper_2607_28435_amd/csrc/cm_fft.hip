@@ -280,7 +280,7 @@ struct DenseConst {
   double th_hi, th_lo;     // theta / (2 pi) as double-double, theta = eta (m_f - k0)
   double2 g0;              // exp(i v0 m_f)
   double k0, nalog2e, lsf; // log2 of the readout scale e^{-alpha k_u} / (s pi) is nalog2e k_u + lsf
-  double dz;               // its step per unit of u (single-precision outputs)
+  double dz, zorg;         // its step per unit of u and its value at u = us (single-precision outputs)
   int64_t us;              // k_u = k0 + lambda (u - us): the default grid is centred on ln S0
   int n;
   double2 ro;              // exp(-i v0 k0)
@@ -336,6 +336,7 @@ __device__ inline DenseConst dense_const(const cm_problem &pr) {
   c.nalog2e = -pr.alpha * M_LOG2E;
   c.dz = c.nalog2e * (2.0 * M_PI / (ldexp(1.0, n) * pr.eta));
   c.lsf = log2(sfac);
+  c.zorg = fma(c.nalog2e, k0, c.lsf);
   c.alt = !c.simpson;
   if (c.simpson) c.ro = cmk(1.0, 0.0);
   else {
@@ -453,9 +454,10 @@ template <typename T> struct PriceDst {   // last pass: readout scalars, prices
         prices[u] = price_at(*c, u, z, v[r], bad != 0);
       }
     } else {
-      // single-precision prices: the first output from its accurate log-strike, the others by
-      // steps (their FP64 error stays far below the FP32 rounding of the price)
-      const double z0 = fma(c->nalog2e, strike_log(c->k0, c->eta, c->n, (double)(u0 - c->us)), c->lsf);
+      // single-precision prices: the scale's exponent as z_org + dz (u - us) in FP64, one FMA per
+      // call and steps for its outputs (the FP64 error of a rounded lambda, at most the strike
+      // range times ulp(1), stays far below the FP32 rounding of the price)
+      const double z0 = fma(c->dz, (double)(u0 - c->us), c->zorg);
       const double dz = c->dz * (double)du;
 #pragma unroll
       for (int r = 0; r < R; ++r) {

@@ -126,6 +126,56 @@ __device__ __forceinline__ int divmod_small(int n, int d, int &r) {
   return q;
 }
 
+// sum_{t < K} a[t] b[t] for a contiguous row a (storage S) and a contiguous FP64 column b:
+// groups of four terms whose eight loads share one base pointer each (immediate offsets) and
+// are issued together, two accumulators, then the remaining terms one by one. No masking
+// inside the groups: a masked tail costs more selects than the arithmetic it guards.
+template <typename S>
+__device__ __forceinline__ double2 dot_contig(const S *__restrict__ a, const double2 *__restrict__ b, int K) {
+  double2 s0 = cmk(0.0, 0.0), s1 = cmk(0.0, 0.0);
+  int t = 0;
+  for (; t + 4 <= K; t += 4) {
+    double2 x[4], y[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      x[u] = cstore<S>::ld(a, t + u);
+      y[u] = b[t + u];
+    }
+    cfma(s0, x[0], y[0]);
+    cfma(s1, x[1], y[1]);
+    cfma(s0, x[2], y[2]);
+    cfma(s1, x[3], y[3]);
+  }
+  for (; t < K; ++t) cfma(s0, cstore<S>::ld(a, t), b[t]);
+  return cadd(s0, s1);
+}
+
+// sum_{t < K} a[t sa] b[t sb] for strided operands (a in storage S, b in FP64): the same
+// groups of four terms with pointers advanced by whole strides, two accumulators, and the
+// remainder one by one.
+template <typename S>
+__device__ __forceinline__ double2 dot_strided(const S *__restrict__ a, int64_t sa, const double2 *__restrict__ b,
+                                               int64_t sb, int K) {
+  double2 s0 = cmk(0.0, 0.0), s1 = cmk(0.0, 0.0);
+  int t = 0;
+  for (; t + 4 <= K; t += 4) {
+    double2 x[4], y[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      x[u] = cstore<S>::ld(a, u * sa);
+      y[u] = b[u * sb];
+    }
+    a += 4 * sa;
+    b += 4 * sb;
+    cfma(s0, x[0], y[0]);
+    cfma(s1, x[1], y[1]);
+    cfma(s0, x[2], y[2]);
+    cfma(s1, x[3], y[3]);
+  }
+  for (; t < K; ++t, a += sa, b += sb) cfma(s0, cstore<S>::ld(a, 0), b[0]);
+  return cadd(s0, s1);
+}
+
 // Shared per-workgroup bookkeeping for the factorisations (lives in LDS).
 struct Sh {
   double red[CM_WG / 64 + 2];
@@ -642,10 +692,7 @@ __device__ __forceinline__ int svd_trunc_rows(double2 *X, bool x_lds, int a, int
   for (int e = tid; e < k * b; e += CM_WG) {
     int c;
     const int i = divmod_small(e, b, c);   // lanes run along a row of Rk: Z reads are coalesced
-    const double2 *jc = Jw + (int64_t)kc * sh.perm[i];
-    double2 acc = cmk(0.0, 0.0);
-    for (int t = 0; t < kc; ++t) cfma(acc, Z[c + (int64_t)b * t], jc[t]);
-    R[e] = cconj(acc);
+    R[e] = cconj(dot_strided(Z + c, (int64_t)b, Jw + (int64_t)kc * sh.perm[i], (int64_t)1, kc));
   }
   __syncthreads();
   if (tid == 0) sh.err2 += err_c;

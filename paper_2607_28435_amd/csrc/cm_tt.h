@@ -99,56 +99,6 @@ struct CoreSrc {
   }
 };
 
-// sum_{t < K} a[t] b[t] for a contiguous row a (storage S) and a contiguous FP64 column b:
-// groups of four terms whose eight loads share one base pointer each (immediate offsets) and
-// are issued together, two accumulators, then the remaining terms one by one. No masking
-// inside the groups: a masked tail costs more selects than the arithmetic it guards.
-template <typename S>
-__device__ __forceinline__ double2 dot_contig(const S *__restrict__ a, const double2 *__restrict__ b, int K) {
-  double2 s0 = cmk(0.0, 0.0), s1 = cmk(0.0, 0.0);
-  int t = 0;
-  for (; t + 4 <= K; t += 4) {
-    double2 x[4], y[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      x[u] = cstore<S>::ld(a, t + u);
-      y[u] = b[t + u];
-    }
-    cfma(s0, x[0], y[0]);
-    cfma(s1, x[1], y[1]);
-    cfma(s0, x[2], y[2]);
-    cfma(s1, x[3], y[3]);
-  }
-  for (; t < K; ++t) cfma(s0, cstore<S>::ld(a, t), b[t]);
-  return cadd(s0, s1);
-}
-
-// sum_{t < K} a[t sa] b[t sb] for strided operands (a in storage S, b in FP64): the same
-// groups of four terms with pointers advanced by whole strides, two accumulators, and the
-// remainder one by one.
-template <typename S>
-__device__ __forceinline__ double2 dot_strided(const S *__restrict__ a, int64_t sa, const double2 *__restrict__ b,
-                                               int64_t sb, int K) {
-  double2 s0 = cmk(0.0, 0.0), s1 = cmk(0.0, 0.0);
-  int t = 0;
-  for (; t + 4 <= K; t += 4) {
-    double2 x[4], y[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      x[u] = cstore<S>::ld(a, u * sa);
-      y[u] = b[u * sb];
-    }
-    a += 4 * sa;
-    b += 4 * sb;
-    cfma(s0, x[0], y[0]);
-    cfma(s1, x[1], y[1]);
-    cfma(s0, x[2], y[2]);
-    cfma(s1, x[3], y[3]);
-  }
-  for (; t < K; ++t, a += sa, b += sb) cfma(s0, cstore<S>::ld(a, 0), b[0]);
-  return cadd(s0, s1);
-}
-
 // Brings two byte ranges into the caches with one memory latency: every lane loads one dword
 // of up to two 128-byte lines of each range and all four values are consumed together. The
 // short dependent dot products that follow then hit the L2 instead of paying one miss per
@@ -220,7 +170,7 @@ __device__ __forceinline__ double round_train(int n, int d, const CoreSrc &src, 
         int i, ph;
         const int j = la::divmod_small(e, rows, i);
         const int a = la::divmod_small(i, d, ph);
-        Yw[e] = dot_strided(cs + ph * rr + j, (int64_t)d * rr, Cg + a, (int64_t)kprev, rl);
+        Yw[e] = la::dot_strided(cs + ph * rr + j, (int64_t)d * rr, Cg + a, (int64_t)kprev, rl);
       }
     };
     if (src.dtype == CM_C64) yform((const float2 *)src.cores + base);
@@ -290,15 +240,15 @@ __device__ __forceinline__ double round_train(int n, int d, const CoreSrc &src, 
       // source cores are row-major [row][t]: contiguous rows
       if (src.dtype == CM_C64) {
         const float2 *cs = (const float2 *)src.cores + base;
-        xform([&](int row, const double2 *cj) { return dot_contig(cs + row * kr, cj, kr); });
+        xform([&](int row, const double2 *cj) { return la::dot_contig(cs + row * kr, cj, kr); });
       } else {
         const double2 *cs = (const double2 *)src.cores + base;
-        xform([&](int row, const double2 *cj) { return dot_contig(cs + row * kr, cj, kr); });
+        xform([&](int row, const double2 *cj) { return la::dot_contig(cs + row * kr, cj, kr); });
       }
     } else {
       const int64_t ld = (int64_t)kl * d;
       touch_lines(core, sizeof(double2) * (size_t)ld * kr, Cg, sizeof(double2) * (size_t)kr * rpp);
-      xform([&](int row, const double2 *cj) { return dot_strided(core + row, ld, cj, (int64_t)1, kr); });
+      xform([&](int row, const double2 *cj) { return la::dot_strided(core + row, ld, cj, (int64_t)1, kr); });
     }
     __syncthreads();
     OutT *out = dst_cores + dst_off[l];
