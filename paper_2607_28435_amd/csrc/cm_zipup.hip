@@ -660,11 +660,7 @@ __global__ __launch_bounds__(CM_WG, 3) void k_zipup(TTView w, int w_slots, TTVie
       T *Yout = Yc + y.coff(b, l);
       int k;
       if (!last && pair_site_fits<T>(sd, chicap, zlds_bytes<T>()))
-        k =
-#ifdef CM_ZIP_NARROW_G4
-            (p <= 16 && m <= 32) ? zip_site_pair<T, 8, 4>(lds_arena, sd, Wl, Al, C, Yout, delta2, chicap, &code_sh) :
-#endif
-            (p <= 32 && m <= 32) ? zip_site_pair<T, 4, 8>(lds_arena, sd, Wl, Al, C, Yout, delta2, chicap, &code_sh)
+        k = (p <= 32 && m <= 32) ? zip_site_pair<T, 4, 8>(lds_arena, sd, Wl, Al, C, Yout, delta2, chicap, &code_sh)
             : (p <= 64 && m <= 32) ? zip_site_pair<T, 8, 4>(lds_arena, sd, Wl, Al, C, Yout, delta2, chicap, &code_sh)
             : p <= 64            ? zip_site_pair<T, 12, 4>(lds_arena, sd, Wl, Al, C, Yout, delta2, chicap, &code_sh)
             : m <= 16            ? zip_site_pair<T, 8, 2>(lds_arena, sd, Wl, Al, C, Yout, delta2, chicap, &code_sh)
