@@ -73,6 +73,10 @@ def parse():
     ap.add_argument("--curves-list", type=int, nargs="*", default=None, help="explicit grid exponents instead of "
                     "the --curves-n range")
     ap.add_argument("--curves-shots", type=int, default=4096)
+    ap.add_argument("--sweep", action="store_true", help="instead of the benchmark line, print one JSON line per "
+                    "grid exponent of --sweep-list: the batched SFFT chain and the dense complex64 FFT on the same "
+                    "seeded Heston draws with n fixed (grids/s of each)")
+    ap.add_argument("--sweep-list", type=int, nargs="*", default=[12, 14, 16, 18, 20, 22, 24, 26, 28])
     ap.add_argument("--curves-build-tol", type=float, default=None, help="QTT construction tolerance of the curves "
                     "(default: a tenth of --curves-tol)")
     return ap.parse_args()
@@ -422,6 +426,48 @@ def _bs_call(S0, K, r, q, T, sigma):
     return S0 * math.exp(-q * T) * special.ndtr(d1) - K * math.exp(-r * T) * special.ndtr(d1 - sq)
 
 
+def batched_sweep_point(cm, torch, n, batch, steps):
+    """The headline workload's draws with n fixed: the SFFT chain (QTT build, zip-up,
+    rounding, read-out of 4096 near-money strikes; operator cached) for the whole batch as
+    one replayed HIP graph, and the dense complex64 FFT (all 2^n prices) on a subset of the
+    same instances, both as grids/s; where the two cross is the batched crossover."""
+    probs = W.heston_batch(batch, seed=20261203, n=n)
+    nk = min(4096, 2 ** n)
+    strikes = torch.from_numpy(np.stack([W.near_money(p, nk) for p in probs])).cuda()
+    mpo = cm.MpoCache([n], 1e-9, 32, cm.CM_C64)
+    pr = cm.SfftPricer(probs, cm.CM_C64, tol=1e-8, cap=32, mpo=mpo)
+    pr.slots.update({"build": batch, "apply": min(batch, 1536), "round": batch})
+    pr.capture(strikes)
+    for _ in range(2):
+        pr.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        pr.replay()
+    torch.cuda.synchronize()
+    sfft_s = (time.perf_counter() - t0) / steps
+    bad = int(sum((v != 0).sum() for v in pr.statuses().values()))
+    # dense: as many instances as keep the price array near 4 GB, one launch each call
+    nd = max(1, min(64, (1 << 30) // (2 ** n)))
+    dprob = cm.pack_problems(probs[:nd], "cuda")
+    dprices = torch.empty((nd, 2 ** n), dtype=torch.float32, device="cuda")
+    dstat = torch.zeros(nd, dtype=torch.int32, device="cuda")
+    dws = cm.Workspace("cuda")
+    cm.cm_fft_price(dprob, nd, n, cm.CM_C64, None, 0, dprices, dstat, dws)
+    torch.cuda.synchronize()
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        cm.cm_fft_price(dprob, nd, n, cm.CM_C64, None, 0, dprices, dstat, dws)
+    torch.cuda.synchronize()
+    dense_s = (time.perf_counter() - t0) / (reps * nd)
+    bad += int((dstat != 0).sum())
+    del dprices, pr
+    return {"n": n, "batch": batch, "sfft_grids_per_s": batch / sfft_s, "sfft_ms_per_step": sfft_s * 1e3,
+            "dense_grids_per_s": 1.0 / dense_s, "dense_instances": nd,
+            "sfft_over_dense": dense_s * batch / sfft_s, "status_errors": bad}
+
+
 def paper_curves(cm, torch, ns, dense_max, tol=1e-10, mpo_tol=None, reps=3, shots=4096, build_tol=None):
     """Memory, maximal rank, run time and NRMSE against n on the paper's Black–Scholes grid
     (Section 4: S0 = 100, r = 0.05, sigma = 0.3, T = 0.5, alpha = 2.5, N = 2^(n-1),
@@ -638,6 +684,10 @@ def main():
     import paper_2607_28435_amd as cm
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.sweep:
+        for n in args.sweep_list:
+            print(json.dumps(batched_sweep_point(cm, torch, n, args.batch, args.steps)), flush=True)
+        return
     if args.curves:
         ns = args.curves_list if args.curves_list else list(range(args.curves_n[0], args.curves_n[1] + 1))
         paper_curves(cm, torch, ns, args.curves_dense_max, tol=args.curves_tol, mpo_tol=args.curves_mpo_tol,
