@@ -653,13 +653,15 @@ __device__ __forceinline__ int cpqr_trunc(double2 *T, int m, int p, double delta
 //   X : the input, in the LDS scratch `lds` (x_lds) or in global memory
 //   Y : scratch of at least a*b complex (receives B);  Z : scratch of at least a*b complex
 //   S, J : at least a*min(a,b) and min(a,b)^2 complex
-//   L (ld a) and R (row-major, k x b) : outputs.
+//   L (ld a, FP64) and R (row-major, k x b, stored as RT) : outputs, written straight to
+//   where the caller keeps them (the sweep's carry and its output core).
 //   lds, lds_elems : optional LDS scratch; the Jacobi pair moves there when it fits (the
 //   factorisations are latency-bound chains of small steps).
 // Returns k (uniform); sh.err2 holds the dropped squared norm.
+template <typename RT>
 __device__ __forceinline__ int svd_trunc_rows(double2 *X, bool x_lds, int a, int b, double delta2, int cap,
                                               double2 *Y, double2 *Z, double2 *S, double2 *J,
-                                              double2 *L, double2 *R, Sh &sh, double2 *lds = nullptr,
+                                              double2 *L, RT *R, Sh &sh, double2 *lds = nullptr,
                                               int lds_elems = 0) {
   const int tid = threadIdx.x;
   // X P = Q R, truncated: Q -> Z (b x kc), B = R[:kc] P^T -> Y (kc x a, ld kc)
@@ -692,7 +694,7 @@ __device__ __forceinline__ int svd_trunc_rows(double2 *X, bool x_lds, int a, int
   for (int e = tid; e < k * b; e += CM_WG) {
     int c;
     const int i = divmod_small(e, b, c);   // lanes run along a row of Rk: Z reads are coalesced
-    R[e] = cconj(dot_strided(Z + c, (int64_t)b, Jw + (int64_t)kc * sh.perm[i], (int64_t)1, kc));
+    cstore<RT>::st(R, e, cconj(dot_strided(Z + c, (int64_t)b, Jw + (int64_t)kc * sh.perm[i], (int64_t)1, kc)));
   }
   __syncthreads();
   if (tid == 0) sh.err2 += err_c;

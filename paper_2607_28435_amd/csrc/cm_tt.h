@@ -259,13 +259,12 @@ __device__ __forceinline__ double round_train(int n, int d, const CoreSrc &src, 
       __syncthreads();
       break;
     }
-    const int k = la::svd_trunc_rows(Xw, x_lds, kl, b, delta2, cap, w.Y, w.Z, S, J, w.L, w.R, sh, lds, lds_elems);
+    // core l = Rk (k x b, row-major, the element order of [k][d][rpp]) goes straight to the
+    // output (the source core l was read in full into X above, so in-place rounding is safe)
+    // and the carry L (kl x k, ld kl) straight to C (read only by the product above)
+    const int k = la::svd_trunc_rows(Xw, x_lds, kl, b, delta2, cap, w.Y, w.Z, S, J, w.C, out, sh, lds, lds_elems);
     merge_flags(sh, code);
     err2 += sh.err2;
-    // core l = Rk (k x b, row-major) as [k][d][rpp]: the same element order
-    for (int e = tid; e < k * b; e += CM_WG) cstore<OutT>::st(out, e, w.R[e]);
-    // carry = L (kl x k, ld kl)
-    for (int e = tid; e < kl * k; e += CM_WG) w.C[e] = w.L[e];
     if (tid == 0) { dst_ranks[l + 1] = rpp; }
     __syncthreads();
     rpp = k;
