@@ -107,7 +107,8 @@ __device__ __forceinline__ double wg_sum(double v, double *red) {
   return s;
 }
 
-// Lane-group size for processing `ncols` independent columns with the whole workgroup.
+// Lane-group size (a power of two) for processing `ncols` independent columns with the whole
+// workgroup.
 __device__ __forceinline__ int group_for(int ncols) {
   int g = pow2floor(CM_WG / (ncols > 0 ? ncols : 1));
   return g > 64 ? 64 : (g < 1 ? 1 : g);
@@ -222,11 +223,11 @@ __device__ __forceinline__ void qr_householder(double2 *Y, int lda, int m, int s
     __syncthreads();
     const int ncols = ntot - c - 1;
     if (ncols > 0) {
-      const int G = group_for(ncols), groups = CM_WG / G;
-      const int lane = tid % G;
+      const int G = group_for(ncols), lgG = __builtin_ctz(G), groups = CM_WG >> lgG;
+      const int lane = tid & (G - 1);
       const double2 ctc = cconj(tc);
       for (int jb = 0; jb < ncols; jb += groups) {
-        const int j = c + 1 + jb + tid / G;
+        const int j = c + 1 + jb + (tid >> lgG);
         const bool ok = j < ntot;
         double2 w = cmk(0.0, 0.0);
         if (ok) {
@@ -252,12 +253,12 @@ __device__ __forceinline__ void qr_householder(double2 *Y, int lda, int m, int s
 // Z (m x k, ldz) <- Q Z with Q from qr_householder(Y, lda, m, s).
 __device__ __forceinline__ void qr_apply_q(const double2 *Y, int lda, int m, int s, const Sh &sh, double2 *Z, int ldz, int k) {
   const int tid = threadIdx.x;
-  const int G = group_for(k), groups = CM_WG / G, lane = tid % G;
+  const int G = group_for(k), lgG = __builtin_ctz(G), groups = CM_WG >> lgG, lane = tid & (G - 1);
   for (int c = s - 1; c >= 0; --c) {
     const double2 tc = sh.tau[c];
     if (tc.x == 0.0 && tc.y == 0.0) continue;
     for (int jb = 0; jb < k; jb += groups) {
-      const int j = jb + tid / G;
+      const int j = jb + (tid >> lgG);
       const bool ok = j < k;
       double2 w = cmk(0.0, 0.0);
       if (ok) {
@@ -288,9 +289,9 @@ __device__ __forceinline__ void qr_form_q_reg(const double2 *T, int m, int k, co
   const int tid = threadIdx.x;
   int G = group_for(k);
   while (G * NR < m) G *= 2;
-  const int groups = CM_WG / G, g = tid % G;
+  const int lgG = __builtin_ctz(G), groups = CM_WG >> lgG, g = tid & (G - 1);
   for (int jb = 0; jb < k; jb += groups) {   // uniform
-    const int j = jb + tid / G;
+    const int j = jb + (tid >> lgG);
     const bool ok = j < k;   // uniform over each group
     double2 q[NR];
 #pragma unroll
@@ -353,8 +354,8 @@ __device__ __forceinline__ void jacobi_onesided(double2 *S, double2 *J, int m, i
   __syncthreads();
   const int N = s + (s & 1);
   const int npairs = N / 2;
-  const int G = group_for(npairs);
-  const int lane = tid % G, pi = tid / G;
+  const int G = group_for(npairs), lgG = __builtin_ctz(G);
+  const int lane = tid & (G - 1), pi = tid >> lgG;
   // A pair is rotated while its cosine |<s_p, s_q>| / (|s_p| |s_q|) exceeds 1e-13, far below
   // any truncation threshold used (singular values then carry relative errors of that
   // order). Columns below 1e-32 of the largest squared norm are numerically null and are left
@@ -385,7 +386,13 @@ __device__ __forceinline__ void jacobi_onesided(double2 *S, double2 *J, int m, i
       int p = -1, q = -1;
       if (pi < npairs && N > 1) {
         if (pi == 0) { p = N - 1; q = r; }
-        else { p = (r + pi) % (N - 1); q = (r - pi + (N - 1)) % (N - 1); }
+        else {
+          // (r + pi) mod (N - 1) and (r - pi) mod (N - 1), both arguments in [0, 2 (N - 1))
+          p = r + pi;
+          if (p >= N - 1) p -= N - 1;
+          q = r - pi + (N - 1);
+          if (q >= N - 1) q -= N - 1;
+        }
         if (p > q) { int t = p; p = q; q = t; }
         if (q >= s) p = -1;
       }
@@ -518,9 +525,9 @@ __device__ __forceinline__ int cpqr_trunc(double2 *T, int m, int p, double delta
   const int kmax = m < p ? m : p;
   // column norms
   {
-    const int G = group_for(p), groups = CM_WG / G, lane = tid % G;
+    const int G = group_for(p), lgG = __builtin_ctz(G), groups = CM_WG >> lgG, lane = tid & (G - 1);
     for (int cb = 0; cb < p; cb += groups) {
-      const int c = cb + tid / G;
+      const int c = cb + (tid >> lgG);
       double a = 0.0;
       if (c < p)
         for (int r = lane; r < m; r += G) a += cabs2(T[r + (int64_t)m * c]);
@@ -597,10 +604,10 @@ __device__ __forceinline__ int cpqr_trunc(double2 *T, int m, int p, double delta
     // apply H^H to trailing columns; refresh their norms below row i
     const int ncols = p - i - 1;
     if (ncols > 0) {
-      const int G = group_for(ncols), groups = CM_WG / G, lane = tid % G;
+      const int G = group_for(ncols), lgG = __builtin_ctz(G), groups = CM_WG >> lgG, lane = tid & (G - 1);
       const double2 ctc = cconj(tc);
       for (int jb = 0; jb < ncols; jb += groups) {
-        const int j = i + 1 + jb + tid / G;
+        const int j = i + 1 + jb + (tid >> lgG);
         const bool ok = j < p;
         double2 w = cmk(0.0, 0.0);
         if (ok && refl) {
