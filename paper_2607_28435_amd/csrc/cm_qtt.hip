@@ -102,18 +102,20 @@ __device__ __forceinline__ double bary_w(int q) {
   return (q == 0 || q == QP - 1) ? 0.5 * w : w;
 }
 
-// Lagrange basis value L_p(x) on nodes t_q = Lm1 (1 - cos(pi q/(P-1)))/2.
-__device__ double lagrange(int p, double x, double Lm1, const double *cq) {
-  double den = 0.0, mine = 0.0;
+// All QP Lagrange basis values L_p(x) on the nodes t_q = Lm1 (1 - cos(pi q/(P-1)))/2, in
+// barycentric form: the weights w_q / (x - t_q) and their sum are shared by the whole row. At a
+// node the row is the unit vector of that node.
+__device__ void lagrange_row(double x, double Lm1, const double *cq, double *out) {
+  double w[QP], den = 0.0;
+  int hit = -1;
   for (int q = 0; q < QP; ++q) {
-    const double t = node_pos(Lm1, cq[q]);
-    const double dx = x - t;
-    if (fabs(dx) <= 1e-13 * (Lm1 + 1.0)) return q == p ? 1.0 : 0.0;
-    const double w = bary_w(q) / dx;
-    den += w;
-    if (q == p) mine = w;
+    const double dx = x - node_pos(Lm1, cq[q]);
+    if (hit < 0 && fabs(dx) <= 1e-13 * (Lm1 + 1.0)) hit = q;
+    w[q] = bary_w(q) / dx;
+    den += w[q];
   }
-  return mine / den;
+  const double rd = 1.0 / den;
+  for (int p = 0; p < QP; ++p) out[p] = (hit >= 0) ? (p == hit ? 1.0 : 0.0) : w[p] * rd;
 }
 
 }  // namespace
@@ -173,6 +175,17 @@ __global__ __launch_bounds__(CM_WG, 2) void k_build_qtt(const cm_problem *__rest
   }
   if (tid == 0) W.pre_ranks[QMARK] = -1;
   __syncthreads();
+  // Leaf-test weights: the interpolant at check point k is sum_q lw[k][q] f(t_q). Nodes and
+  // check points are the same affine image of fixed Chebyshev points, so the interval length
+  // cancels from the normalised barycentric weights and one table serves every depth.
+  __shared__ double lw[QP - 1][QP];
+  if (tid < QP - 1) {
+    double w[QP], den = 0.0;
+    for (int q = 0; q < QP; ++q) { w[q] = bary_w(q) / (cq[q] - ck[tid]); den += w[q]; }
+    const double rd = 1.0 / den;
+    for (int q = 0; q < QP; ++q) lw[tid][q] = w[q] * rd;
+  }
+  __syncthreads();
 
   // exactly one instance per workgroup (the host launches one workgroup per instance of the
   // chunk); the loop form keeps `continue` for the early exits
@@ -228,7 +241,8 @@ __global__ __launch_bounds__(CM_WG, 2) void k_build_qtt(const cm_problem *__rest
       }
       if (tid == 0) T[d].n_cand = NC;
       for (int e = tid; e < NC * npts; e += CM_WG) {
-        const int ci = e / npts, q = e % npts;
+        int q;
+        const int ci = la::divmod_small(e, npts, q);
         const int64_t c = T[d - 1].int_a[ci >> 1] + ((int64_t)(ci & 1) << m);
         double pos;
         if (exact) pos = (double)q;
@@ -242,36 +256,52 @@ __global__ __launch_bounds__(CM_WG, 2) void k_build_qtt(const cm_problem *__rest
       }
       __syncthreads();
       const double eps = eps_rel * hscale * exp2(-0.5 * m);
-      for (int ci = tid; ci < NC; ci += CM_WG) {
-        const int64_t c = T[d - 1].int_a[ci >> 1] + ((int64_t)(ci & 1) << m);
-        const bool forced = simpson && c == 0;
-        int kind;
-        if (exact) {
-          kind = 2;
-          if (simpson && c == 0) vals[ci * QNPT] = cscale(vals[ci * QNPT], 0.5);
-        } else {
-          double mx = 0.0;
-          for (int q = 0; q < QNPT; ++q) mx = fmax(mx, sqrt(cabs2(vals[ci * QNPT + q])));
-          if (!(mx == mx) || isinf(mx)) { kind = -1; }
-          else if (mx <= eps && !forced) kind = 0;
-          else {
-            double err = 0.0;
-            for (int k = 0; k < QP - 1; ++k) {
-              const double xk = node_pos(Lm1, ck[k]);
-              double2 num = cmk(0.0, 0.0);
-              double den = 0.0;
-              for (int q = 0; q < QP; ++q) {
-                const double w = bary_w(q) / (xk - node_pos(Lm1, cq[q]));
-                den += w;
-                num = cadd(num, cscale(vals[ci * QNPT + q], w));
-              }
-              const double2 p = cscale(num, 1.0 / den);
-              err = fmax(err, sqrt(cabs2(csub(p, vals[ci * QNPT + QP + k]))));
+      if (!exact) {
+        // LG lanes per candidate: lane j takes the magnitudes of points j and j + LG and the
+        // interpolation error at check point j; the group reduces both maxima by lane swaps.
+        // The loop runs whole groups (NC LG is a multiple of LG) so every swap partner is live.
+        constexpr int LG = 16;
+        static_assert(QNPT <= 2 * LG && QP - 1 <= LG && CM_WG % LG == 0, "leaf-test lane groups");
+        for (int e0 = 0; e0 < NC * LG; e0 += CM_WG) {
+          const int e = e0 + tid, ci = e / LG, j = e % LG;
+          const bool on = e < NC * LG;
+          double mx2 = 0.0, er2 = 0.0;
+          if (on) {
+            const double2 *vc = vals + ci * QNPT;
+            const double a = cabs2(vc[j]);
+            mx2 = (a == a) ? a : INFINITY;
+            if (j + LG < QNPT) {
+              const double a2 = cabs2(vc[j + LG]);
+              mx2 = fmax(mx2, (a2 == a2) ? a2 : INFINITY);
             }
-            kind = (err <= eps && !forced) ? 2 : 1;
+            if (j < QP - 1) {
+              double2 p = cmk(0.0, 0.0);
+              for (int q = 0; q < QP; ++q) p = cadd(p, cscale(vc[q], lw[j][q]));
+              er2 = cabs2(csub(p, vc[QP + j]));
+            }
+          }
+          for (int o = 1; o < LG; o <<= 1) {
+            mx2 = fmax(mx2, __shfl_xor(mx2, o, LG));
+            er2 = fmax(er2, __shfl_xor(er2, o, LG));
+          }
+          if (on && j == 0) {
+            const int64_t c = T[d - 1].int_a[ci >> 1] + ((int64_t)(ci & 1) << m);
+            const bool forced = simpson && c == 0;
+            const double mx = sqrt(mx2), err = sqrt(er2);
+            int kind;
+            if (isinf(mx)) kind = -1;
+            else if (mx <= eps && !forced) kind = 0;
+            else kind = (err <= eps && !forced) ? 2 : 1;
+            kind_sh[ci] = (int8_t)kind;
           }
         }
-        kind_sh[ci] = (int8_t)kind;
+      } else {
+        // point leaves: every candidate keeps its values (the Simpson end weight halves u = 0)
+        for (int ci = tid; ci < NC; ci += CM_WG) {
+          const int64_t c = T[d - 1].int_a[ci >> 1] + ((int64_t)(ci & 1) << m);
+          if (simpson && c == 0) vals[ci * QNPT] = cscale(vals[ci * QNPT], 0.5);
+          kind_sh[ci] = 2;
+        }
       }
       __syncthreads();
       if (tid == 0) {
@@ -290,7 +320,8 @@ __global__ __launch_bounds__(CM_WG, 2) void k_build_qtt(const cm_problem *__rest
       __syncthreads();
       const int pv = exact ? (int)L : QP;
       for (int e = tid; e < NC * pv; e += CM_WG) {
-        const int ci = e / pv, q = e % pv;
+        int q;
+        const int ci = la::divmod_small(e, pv, q);
         T[d].vals[ci][q] = vals[ci * QNPT + q];
       }
       __syncthreads();
@@ -355,8 +386,19 @@ __global__ __launch_bounds__(CM_WG, 2) void k_build_qtt(const cm_problem *__rest
         wt0 = cmul(wt0, g);
         wt1 = cmul(wt1, g);
       }
+      // Lagrange rows of the child nodes in the parent interval: lt[beta][q][p] = L_p(x_q)
+      __shared__ double lt[2][QP][QP];
+      if (actl && !exl) {
+        if (tid < 2 * QP) {
+          const int beta = tid >= QP, q = tid - beta * QP;
+          const double tq = exr ? (double)q : node_pos(Lm1r, cq[q]);
+          lagrange_row(beta * ldexp(1.0, m) + tq, Lm1l, cq, lt[beta][q]);
+        }
+        __syncthreads();
+      }
       for (int e = tid; e < rl * 2 * rr; e += CM_WG) {
-        const int i = e / (2 * rr), beta = (e / rr) & 1, jr = e % rr;
+        int jr;
+        const int ib = la::divmod_small(e, rr, jr), i = ib >> 1, beta = ib & 1;
         double2 v = cmk(0.0, 0.0);
         if (i < Il || l == 1) {
           // split interval i (at depth l-1), child ci = 2 i + beta
@@ -375,7 +417,7 @@ __global__ __launch_bounds__(CM_WG, 2) void k_build_qtt(const cm_problem *__rest
             const double xq = beta * ldexp(1.0, m) + tq;
             double lv;
             if (exl) lv = (fabs(xq - (double)p) < 0.5) ? 1.0 : 0.0;
-            else lv = lagrange(p, xq, Lm1l, cq);
+            else lv = lt[beta][q][p];
             v = cmk(lv, 0.0);
           }
         }
