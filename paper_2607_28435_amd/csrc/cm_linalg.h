@@ -40,9 +40,11 @@ __device__ __forceinline__ int pow2floor(int x) {
 // log2(G) steps every lane of the group holds the same (bit-identical) reduction.
 constexpr int DPP_XOR1 = 0xB1, DPP_XOR2 = 0x4E, DPP_HALF_MIRROR = 0x141, DPP_MIRROR = 0x140;
 
+// Every lane has a valid source lane under these four controls, so no lane keeps an old value
+// and the move needs no copy of its source in front of it.
 template <int CTRL>
 __device__ __forceinline__ int dpp_i(int v) {
-  return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xF, 0xF, false);
+  return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, true);
 }
 template <int CTRL>
 __device__ __forceinline__ double dpp_d(double v) {

@@ -16,6 +16,7 @@
 // lanes (zip_site_pair); other sites stage their matrices in LDS when they fit, otherwise in the
 // workgroup's global slab.
 #include <mutex>
+#include <type_traits>
 
 #include "cm_tt.h"
 
@@ -168,9 +169,10 @@ __device__ __forceinline__ int zip_site(char *arena, const SiteDims &sd, const T
 // is static; rows finished before i in the same group of G sit in slot 0 of the lanes below
 // and take no part (their reflector entries are zero). A dot product is lane-local plus
 // log2 G DPP exchanges within the group. A pivot step needs one workgroup barrier, at which
-// each wave publishes its best candidate column (norm, index, the sum of its columns'
-// norms, its entry alpha in row i and its rows from i on, with the Householder data it
-// would give) and all waves then take the same global choice. Column
+// each wave publishes its best candidate column (its pivot key, which packs norm and index
+// into one integer, the sum of its columns' norms, its entry alpha in row i and its rows from
+// i on, with the Householder data it would give) and all waves then take the same global
+// choice. Column
 // norms are recomputed exactly from the updated entries at every step. Rows of
 // B = R P^T are emitted as they are finished, straight into the carry buffer in the
 // [k][w'][r'] order the next site reads. Q = H_0 ... H_{k-1} [I_k; 0] is then accumulated
@@ -185,9 +187,9 @@ constexpr int SM = MR / 2;        // register slots per lane at the largest m
 // them across the barrier, and a wider G spreads a step's column work over more waves.
 constexpr int CP = CM_WG / 2;     // columns: p <= 128
 struct CandInfo {
-  double best, sum;
-  int idx, pad0;
-  double pad1;
+  unsigned long long key;   // pivot key (see pivot_key), 0 when the wave has no candidate
+  double sum;
+  double pad[2];
 };
 static_assert(sizeof(CandInfo) == 32, "CandInfo layout");
 // LDS layout (bytes): candidate columns [2][PW][MR] (two buffers, by step parity; entry
@@ -221,29 +223,55 @@ __device__ __forceinline__ double lane_d(double x, int l) {
                           __builtin_amdgcn_readlane(__double2loint(x), l));
 }
 
-// Over the 64 lanes of a wave: the largest `best` (ties to the smaller index) and the sum
-// of `sum`, returned wave-uniform. DPP inside rows of 16 lanes, then the four row results
-// combined in a fixed order. `best` and `bi` are already equal on the G lanes of an aligned
-// group, so the stages inside a group exchange only `sum`.
+// Pivot key of column c (< 128) with squared norm n2 >= 0: the bit pattern of n2 (non-negative
+// doubles order as their bits do) with the low byte replaced by 255 - c, so that the largest
+// key belongs to the largest norm, ties going to the smaller column, and 0 means no candidate.
+// Norms that differ only in their last eight bits (relative 2^-44) count as tied, which does
+// not matter for the quality of a pivot. A NaN or infinite norm gives a key above every finite
+// one; the tail sum reports it before the pivot is used.
+__device__ __forceinline__ unsigned long long pivot_key(double n2, int c) {
+  return ((unsigned long long)__double_as_longlong(n2) & ~0xFFull) | (unsigned long long)(255 - c);
+}
+__device__ __forceinline__ int key_col(unsigned long long key) { return 255 - (int)(key & 0xFF); }
+
+template <int CTRL>
+__device__ __forceinline__ unsigned long long dpp_u64(unsigned long long v) {
+  const unsigned lo = (unsigned)la::dpp_i<CTRL>((int)(unsigned)v), hi = (unsigned)la::dpp_i<CTRL>((int)(unsigned)(v >> 32));
+  return ((unsigned long long)hi << 32) | lo;
+}
+__device__ __forceinline__ unsigned long long lane_u64(unsigned long long v, int l) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), l);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+// Over the 64 lanes of a wave: the largest pivot key and the sum of one `sum` per aligned
+// group of G lanes, returned wave-uniform. Both are already equal on the G lanes of a group, so
+// only the stages across groups run: DPP inside rows of 16 lanes, then the four row results
+// combined in a fixed order.
 template <int G>
-__device__ __forceinline__ void wave_argmax_sum_uni(double &best, int &bi, double &sum) {
-  if (G > 1) sum += la::dpp_d<la::DPP_XOR1>(sum);
-  else la::argmax_sum_step<la::DPP_XOR1>(best, bi, sum);
-  if (G > 2) sum += la::dpp_d<la::DPP_XOR2>(sum);
-  else la::argmax_sum_step<la::DPP_XOR2>(best, bi, sum);
-  if (G > 4) sum += la::dpp_d<la::DPP_HALF_MIRROR>(sum);
-  else la::argmax_sum_step<la::DPP_HALF_MIRROR>(best, bi, sum);
-  la::argmax_sum_step<la::DPP_MIRROR>(best, bi, sum);
-  double b = lane_d(best, 0), s = lane_d(sum, 0);
-  int ix = __builtin_amdgcn_readlane(bi, 0);
+__device__ __forceinline__ void wave_keymax_sum_uni(unsigned long long &key, double &sum) {
+  auto step = [&](auto ctrl, bool across) {
+    constexpr int C = decltype(ctrl)::value;
+    if (across) {
+      const unsigned long long o = dpp_u64<C>(key);
+      key = o > key ? o : key;
+      sum += la::dpp_d<C>(sum);
+    }
+  };
+  step(std::integral_constant<int, la::DPP_XOR1>{}, G <= 1);
+  step(std::integral_constant<int, la::DPP_XOR2>{}, G <= 2);
+  step(std::integral_constant<int, la::DPP_HALF_MIRROR>{}, G <= 4);
+  step(std::integral_constant<int, la::DPP_MIRROR>{}, true);
+  unsigned long long k = lane_u64(key, 0);
+  double s = lane_d(sum, 0);
 #pragma unroll
   for (int r = 1; r < 4; ++r) {
-    const double ob = lane_d(best, 16 * r);
-    const int oi = __builtin_amdgcn_readlane(bi, 16 * r);
+    const unsigned long long ok = lane_u64(key, 16 * r);
     s += lane_d(sum, 16 * r);
-    if (ob > b || (ob == b && oi < ix)) { b = ob; ix = oi; }
+    k = ok > k ? ok : k;
   }
-  best = b; bi = ix; sum = s;
+  key = k; sum = s;
 }
 
 // Householder data of a pivot column with squared norm n2 (rows >= i) and entry alpha in row
@@ -388,58 +416,70 @@ __device__ __forceinline__ int zip_site_pair(char *arena, const SiteDims &sd, co
   // wave). The loop below exits only at its end, which keeps T in registers.
   int pc = 0;
   double beta = 0.0;
-  double2 am = cmk(0.0, 0.0), scal = cmk(0.0, 0.0), ctau = cmk(0.0, 0.0);
+  double2 scal = cmk(0.0, 0.0), ctau = cmk(0.0, 0.0);
   const double2 *X = cand;
   auto select = [&](int i) -> bool {
     const int b = i & 1, j = i / G;
-    double best = act ? nrm : -1.0, sum = (act && g == 0) ? nrm : 0.0;
-    int bi = act ? c : 0x7fffffff;
-    if (__ballot(act) != 0) wave_argmax_sum_uni<G>(best, bi, sum);   // else already the reduction's result
+    unsigned long long key = act ? pivot_key(nrm, c) : 0ull;
+    double sum = act ? nrm : 0.0;   // one term per group (all of its lanes hold it)
+    // every lane forms the reflector its column would give from its own (exact) norm; only the
+    // winner's row-i lane keeps it. Formed ahead of the pivot reduction, whose result it does
+    // not need.
+    const House Hs = householder(nrm, t[0]);
+    if (__ballot(act) != 0) wave_keymax_sum_uni<G>(key, sum);   // else already the reduction's result
     double2 *mine = cand + (b * PW + wv) * MR;
     CandInfo *inf = info + b * PW + wv;
-    if (c == bi) {
+    if (key != 0ull && c == key_col(key)) {
       // slot 0 is row G j + g: finished (zero), row i (x_i = alpha - beta) or a later row
       const int r0w = G * j + g;
       double2 v0 = t[0];
       if (r0w < i) v0 = cmk(0.0, 0.0);
       if (r0w == i) {
-        const House H = householder(best, t[0]);
+        const House &H = Hs;
         v0 = H.am;
         hinf[b * PW + wv] = H;
         CandInfo ci;
-        ci.best = best; ci.sum = sum; ci.idx = bi; ci.pad0 = 0; ci.pad1 = 0.0;
+        ci.key = key; ci.sum = sum; ci.pad[0] = 0.0; ci.pad[1] = 0.0;
         *inf = ci;
       }
       mine[g] = v0;
 #pragma unroll
       for (int sl = 1; sl < SMX; ++sl) mine[G * sl + g] = t[sl];
     }
-    if (bi == 0x7fffffff && lane == 0) {   // no candidate left in this wave
+    if (key == 0ull && lane == 0) {   // no candidate left in this wave
       CandInfo ci;
-      ci.best = -1.0; ci.sum = sum; ci.idx = bi; ci.pad0 = 0; ci.pad1 = 0.0;
+      ci.key = 0ull; ci.sum = sum; ci.pad[0] = 0.0; ci.pad[1] = 0.0;
       *inf = ci;
     }
     __syncthreads();
     // every wave's record is loaded before any is compared, so that one LDS latency covers
     // all four, and the choice is made with selects
-    double cb[PW], cs[PW];
-    int cx[PW];
+    unsigned long long ck[PW];
+    double cs[PW];
 #pragma unroll
     for (int q = 0; q < PW; ++q) {
-      cb[q] = info[b * PW + q].best;
+      ck[q] = info[b * PW + q].key;
       cs[q] = info[b * PW + q].sum;
-      cx[q] = info[b * PW + q].idx;
     }
-    double gbest = -1.0, tail = 0.0;
-    int gidx = 0x7fffffff, gw = 0;
+    unsigned long long gkey = 0ull;
+    double tail = 0.0;
+    int gw = 0;
 #pragma unroll
     for (int q = 0; q < PW; ++q) {
       tail += cs[q];
-      const bool better = (cb[q] > gbest) | ((cb[q] == gbest) & (cx[q] < gidx));
-      gbest = better ? cb[q] : gbest;
-      gidx = better ? cx[q] : gidx;
+      const bool better = ck[q] > gkey;
+      gkey = better ? ck[q] : gkey;
       gw = better ? q : gw;
     }
+    // the winner's column and reflector are taken before the stop tests, so that every path
+    // through here defines them (no copies of the previous step's values are kept for the
+    // exit); with no candidate left they are stale and unused
+    pc = key_col(gkey);
+    X = cand + (b * PW + gw) * MR;
+    const House H = hinf[b * PW + gw];
+    beta = H.beta;
+    scal = H.scal;
+    ctau = cconj(H.tau);
     if (!(tail == tail) || isinf(tail)) {
       if (tid == 0 && *code == CM_OK) *code = CM_E_NONFINITE;
       return true;
@@ -449,13 +489,6 @@ __device__ __forceinline__ int zip_site_pair(char *arena, const SiteDims &sd, co
       if (tid == 0 && *code == CM_OK) *code = CM_E_RANKCAP;
       return true;
     }
-    pc = gidx;
-    X = cand + (b * PW + gw) * MR;
-    const House H = hinf[b * PW + gw];
-    beta = H.beta;
-    am = H.am;
-    scal = H.scal;
-    ctau = cconj(H.tau);
     if (tid == 0) taus[i] = H.tau;
     return false;
   };
