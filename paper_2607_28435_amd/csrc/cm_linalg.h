@@ -8,6 +8,7 @@
 // the tall orientation, then Jacobi rotations on the small square factor, with the
 // column pairs of one round (circle-method ordering) handled by disjoint lane groups.
 #pragma once
+#include <type_traits>
 
 #include "cm_internal.h"
 
@@ -52,6 +53,30 @@ __device__ __forceinline__ double dpp_d(double v) {
   return __hiloint2double(hi, lo);
 }
 
+// Exchanges across rows of 16 lanes and across halves of the wave with the lane swaps
+// (VALU, no LDS round trip). Swapping a value with itself leaves, at every lane, the value of
+// the lower member of its pair (lane l and l ^ W) in `lo` and the upper member's in `hi`, so a
+// symmetric combination of lo and hi is bit-identical on both lanes of a pair.
+template <int W>
+__device__ __forceinline__ void swap_pair_i(int v, int &lo, int &hi) {
+  static_assert(W == 16 || W == 32, "lane swap width");
+  if constexpr (W == 16) {
+    const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    lo = r[0]; hi = r[1];
+  } else {
+    const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    lo = r[0]; hi = r[1];
+  }
+}
+template <int W>
+__device__ __forceinline__ void swap_pair_d(double v, double &lo, double &hi) {
+  int l0, h0, l1, h1;
+  swap_pair_i<W>(__double2loint(v), l0, h0);
+  swap_pair_i<W>(__double2hiint(v), l1, h1);
+  lo = __hiloint2double(l1, l0);
+  hi = __hiloint2double(h1, h0);
+}
+
 // Sum over aligned groups of G lanes (G a power of two <= 64); every lane of the wave must
 // take part.
 __device__ __forceinline__ double grp_sum(double v, int G) {
@@ -59,8 +84,8 @@ __device__ __forceinline__ double grp_sum(double v, int G) {
   if (G >= 4) v += dpp_d<DPP_XOR2>(v);
   if (G >= 8) v += dpp_d<DPP_HALF_MIRROR>(v);
   if (G >= 16) v += dpp_d<DPP_MIRROR>(v);
-  if (G >= 32) v += __shfl_xor(v, 16, 64);
-  if (G >= 64) v += __shfl_xor(v, 32, 64);
+  if (G >= 32) { double a, b; swap_pair_d<16>(v, a, b); v = a + b; }
+  if (G >= 64) { double a, b; swap_pair_d<32>(v, a, b); v = a + b; }
   return v;
 }
 
@@ -70,8 +95,11 @@ __device__ __forceinline__ double wave_max(double v) {
   v = fmax(v, dpp_d<DPP_XOR2>(v));
   v = fmax(v, dpp_d<DPP_HALF_MIRROR>(v));
   v = fmax(v, dpp_d<DPP_MIRROR>(v));
-  v = fmax(v, __shfl_xor(v, 16, 64));
-  return fmax(v, __shfl_xor(v, 32, 64));
+  double a, b;
+  swap_pair_d<16>(v, a, b);
+  v = fmax(a, b);
+  swap_pair_d<32>(v, a, b);
+  return fmax(a, b);
 }
 
 // Over the 64 lanes of a wave: the largest `best` (ties to the smaller index `bi`) and the
@@ -88,12 +116,21 @@ __device__ __forceinline__ void wave_argmax_sum(double &best, int &bi, double &s
   argmax_sum_step<DPP_XOR2>(best, bi, sum);
   argmax_sum_step<DPP_HALF_MIRROR>(best, bi, sum);
   argmax_sum_step<DPP_MIRROR>(best, bi, sum);
-  for (int o = 16; o <= 32; o <<= 1) {
-    const double ob = __shfl_xor(best, o, 64);
-    const int oi = __shfl_xor(bi, o, 64);
-    sum += __shfl_xor(sum, o, 64);
-    if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-  }
+  // across rows, then halves: both members of a pair combine the same (lower, upper) values
+  auto cross = [&](auto wc) {
+    constexpr int W = decltype(wc)::value;
+    double b0, b1, s0, s1;
+    int i0, i1;
+    swap_pair_d<W>(best, b0, b1);
+    swap_pair_i<W>(bi, i0, i1);
+    swap_pair_d<W>(sum, s0, s1);
+    sum = s0 + s1;
+    const bool up = b1 > b0 || (b1 == b0 && i1 < i0);
+    best = up ? b1 : b0;
+    bi = up ? i1 : i0;
+  };
+  cross(std::integral_constant<int, 16>{});
+  cross(std::integral_constant<int, 32>{});
 }
 
 // Block-wide sum; `red` = LDS scratch of at least CM_WG/64 + 1 doubles. Includes syncs.

@@ -258,10 +258,10 @@ __global__ __launch_bounds__(CM_WG, 2) void k_build_qtt(const cm_problem *__rest
       const double eps = eps_rel * hscale * exp2(-0.5 * m);
       if (!exact) {
         // LG lanes per candidate: lane j takes the magnitudes of points j and j + LG and the
-        // interpolation error at check point j; the group reduces both maxima by lane swaps.
+        // interpolation error at check point j; the group reduces both maxima by lane moves.
         // The loop runs whole groups (NC LG is a multiple of LG) so every swap partner is live.
         constexpr int LG = 16;
-        static_assert(QNPT <= 2 * LG && QP - 1 <= LG && CM_WG % LG == 0, "leaf-test lane groups");
+        static_assert(QNPT <= 2 * LG && QP - 1 <= LG && CM_WG % 64 == 0, "leaf-test lane groups");
         for (int e0 = 0; e0 < NC * LG; e0 += CM_WG) {
           const int e = e0 + tid, ci = e / LG, j = e % LG;
           const bool on = e < NC * LG;
@@ -280,10 +280,15 @@ __global__ __launch_bounds__(CM_WG, 2) void k_build_qtt(const cm_problem *__rest
               er2 = cabs2(csub(p, vc[QP + j]));
             }
           }
-          for (int o = 1; o < LG; o <<= 1) {
-            mx2 = fmax(mx2, __shfl_xor(mx2, o, LG));
-            er2 = fmax(er2, __shfl_xor(er2, o, LG));
-          }
+          // groups of LG = 16 lanes are the rows of the DPP lane moves
+          mx2 = fmax(mx2, la::dpp_d<la::DPP_XOR1>(mx2));
+          er2 = fmax(er2, la::dpp_d<la::DPP_XOR1>(er2));
+          mx2 = fmax(mx2, la::dpp_d<la::DPP_XOR2>(mx2));
+          er2 = fmax(er2, la::dpp_d<la::DPP_XOR2>(er2));
+          mx2 = fmax(mx2, la::dpp_d<la::DPP_HALF_MIRROR>(mx2));
+          er2 = fmax(er2, la::dpp_d<la::DPP_HALF_MIRROR>(er2));
+          mx2 = fmax(mx2, la::dpp_d<la::DPP_MIRROR>(mx2));
+          er2 = fmax(er2, la::dpp_d<la::DPP_MIRROR>(er2));
           if (on && j == 0) {
             const int64_t c = T[d - 1].int_a[ci >> 1] + ((int64_t)(ci & 1) << m);
             const bool forced = simpson && c == 0;
