@@ -216,12 +216,8 @@ __device__ __forceinline__ bool pair_site_fits(const SiteDims &s, int kcap, size
   return PL_REGION + (dwa > v ? dwa : v) <= lds_bytes;
 }
 
-// wave-uniform copies of values every lane already holds, and reads of one lane's value
+// a wave-uniform copy of a value every lane already holds
 __device__ __forceinline__ int uni_i(int x) { return __builtin_amdgcn_readfirstlane(x); }
-__device__ __forceinline__ double lane_d(double x, int l) {
-  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), l),
-                          __builtin_amdgcn_readlane(__double2loint(x), l));
-}
 
 // Pivot key of column c (< 128) with squared norm n2 >= 0: the bit pattern of n2 (non-negative
 // doubles order as their bits do) with the low byte replaced by 255 - c, so that the largest
@@ -237,11 +233,6 @@ __device__ __forceinline__ int key_col(unsigned long long key) { return 255 - (i
 template <int CTRL>
 __device__ __forceinline__ unsigned long long dpp_u64(unsigned long long v) {
   const unsigned lo = (unsigned)la::dpp_i<CTRL>((int)(unsigned)v), hi = (unsigned)la::dpp_i<CTRL>((int)(unsigned)(v >> 32));
-  return ((unsigned long long)hi << 32) | lo;
-}
-__device__ __forceinline__ unsigned long long lane_u64(unsigned long long v, int l) {
-  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, l);
-  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), l);
   return ((unsigned long long)hi << 32) | lo;
 }
 
@@ -263,15 +254,22 @@ __device__ __forceinline__ void wave_keymax_sum_uni(unsigned long long &key, dou
   step(std::integral_constant<int, la::DPP_XOR2>{}, G <= 2);
   step(std::integral_constant<int, la::DPP_HALF_MIRROR>{}, G <= 4);
   step(std::integral_constant<int, la::DPP_MIRROR>{}, true);
-  unsigned long long k = lane_u64(key, 0);
-  double s = lane_d(sum, 0);
-#pragma unroll
-  for (int r = 1; r < 4; ++r) {
-    const unsigned long long ok = lane_u64(key, 16 * r);
-    s += lane_d(sum, 16 * r);
-    k = ok > k ? ok : k;
-  }
-  key = k; sum = s;
+  // across rows, then halves, by the lane swaps: both lanes of a pair combine the same
+  // (lower, upper) values, so every lane ends with the same key and sum
+  auto cross = [&](auto wc) {
+    constexpr int W = decltype(wc)::value;
+    int l0, l1, h0, h1;
+    la::swap_pair_i<W>((int)(unsigned)key, l0, l1);
+    la::swap_pair_i<W>((int)(unsigned)(key >> 32), h0, h1);
+    const unsigned long long k0 = ((unsigned long long)(unsigned)h0 << 32) | (unsigned)l0;
+    const unsigned long long k1 = ((unsigned long long)(unsigned)h1 << 32) | (unsigned)l1;
+    key = k1 > k0 ? k1 : k0;
+    double s0, s1;
+    la::swap_pair_d<W>(sum, s0, s1);
+    sum = s0 + s1;
+  };
+  cross(std::integral_constant<int, 16>{});
+  cross(std::integral_constant<int, 32>{});
 }
 
 // Householder data of a pivot column with squared norm n2 (rows >= i) and entry alpha in row
@@ -327,6 +325,12 @@ __device__ __forceinline__ int zip_site_pair(char *arena, const SiteDims &sd, co
   T *Dch = Ac + r0 * 2 * r1;                       // two chunks of D[4][w0][2][r1]
   double2 *V = (double2 *)(arena + PL_REGION);   // reuses the region once T is in registers
   const int dchunk = 4 * w0 * 2 * r1;
+  // the whole D (rows padded with zero rows to a multiple of four, which the chunk reads below
+  // cover) in the region after the staged operands, when it fits
+  const int chi4 = (chi + 3) & ~3;
+  const bool fullD = chi > 4 &&
+                     PL_REGION + sizeof(T) * ((size_t)chi * w0 * r0 + (size_t)w0 * 4 * w1 + (size_t)r0 * 2 * r1 +
+                                              (size_t)chi4 * w0 * 2 * r1) <= (size_t)zlds_bytes<T>();
   // stage the carry (in the storage precision, which the contraction uses) and the cores;
   // loads are issued in batches so that their latencies overlap
   {
@@ -363,22 +367,28 @@ __device__ __forceinline__ int zip_site_pair(char *arena, const SiteDims &sd, co
 #pragma unroll
     for (int ch0 = 0; ch0 < SMX * G / 2; ch0 += 4) {
       if (ch0 < chi) {
-        T *Db = Dch + ((ch0 / 4) & 1) * dchunk;
-        __syncthreads();   // staging done (first chunk) / this buffer's previous readers done
-        for (int e = tid; e < dchunk; e += CM_WG) {
-          // e = ((cc w0 + ww) 2 + j) r1 + rpp
-          int pr, ww;
-          const int row = la::divmod_small(e, 2 * r1, pr);
-          const int cc = la::divmod_small(row, w0, ww);
-          const int j = pr >= r1 ? 1 : 0, rpp = pr - j * r1;
-          typename A::type acc = A::zero();
-          if (ch0 + cc < chi) {
-            const T *crow = Cl + ((ch0 + cc) * w0 + ww) * r0;
-            for (int r = 0; r < r0; ++r) A::fma_(acc, crow[r], Ac[(r * 2 + j) * r1 + rpp]);
+        // D rows ch0 .. ch0 + 3: one chunk of the double buffer, or of the whole D (all chi4
+        // rows, formed in one pass before the first chunk) when it fits the region
+        T *Db = fullD ? Dch + ch0 * w0 * 2 * r1 : Dch + ((ch0 / 4) & 1) * dchunk;
+        if (!fullD || ch0 == 0) {
+          T *Dw = fullD ? Dch : Db;
+          const int ne = fullD ? chi4 * w0 * 2 * r1 : dchunk;
+          __syncthreads();   // staging done (first chunk) / this buffer's previous readers done
+          for (int e = tid; e < ne; e += CM_WG) {
+            // e = ((cc w0 + ww) 2 + j) r1 + rpp
+            int pr, ww;
+            const int row = la::divmod_small(e, 2 * r1, pr);
+            const int cc = la::divmod_small(row, w0, ww);
+            const int j = pr >= r1 ? 1 : 0, rpp = pr - j * r1;
+            typename A::type acc = A::zero();
+            if (ch0 + cc < chi) {
+              const T *crow = Cl + ((ch0 + cc) * w0 + ww) * r0;
+              for (int r = 0; r < r0; ++r) A::fma_(acc, crow[r], Ac[(r * 2 + j) * r1 + rpp]);
+            }
+            Dw[e] = acc;
           }
-          Db[e] = acc;
+          __syncthreads();
         }
-        __syncthreads();
         if (wcols) {
           // this lane's rows in the chunk: ch = ch0 + gh + (G / 2) e, in slot ch / (G / 2)
           constexpr int NE = 8 / G;
