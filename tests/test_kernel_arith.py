@@ -40,3 +40,45 @@ def test_divmod_small_needs_the_correction():
     n = np.arange(0, 1 << 16, dtype=np.int64)
     f = n.astype(np.float32) * rcp
     assert np.any(np.trunc(f).astype(np.int64) != n // d)
+
+
+def _pivot_key(n2, c):
+    """The zip-up's pivot key: the bit pattern of the squared norm n2 >= 0 with its low byte
+    replaced by 255 - c (column c < 128); the argmax over keys is the pivot."""
+    bits = np.asarray(n2, dtype=np.float64).view(np.uint64)
+    return (bits & ~np.uint64(0xFF)) | (np.uint64(255) - np.asarray(c, dtype=np.uint64))
+
+
+def _key_col(key):
+    return 255 - int(key & np.uint64(0xFF))
+
+
+def test_pivot_key_orders_by_norm_with_ties_to_the_smaller_column():
+    """On random norms (including zeros, a subnormal and exact ties) the largest key is a
+    column whose norm is within 2^-44 relative of the largest when that is a normal number
+    (the exact argmax whenever the norms differ by more), ties go to the smaller column, no
+    key is 0 (the mark of an empty wave), and non-finite norms outrank every finite one."""
+    rng = np.random.default_rng(20261203)
+    for trial in range(2000):
+        p = int(rng.integers(1, 129))
+        n2 = rng.exponential(1.0, p) * 10.0 ** rng.integers(-300, 300)
+        if trial % 5 == 0:
+            n2[rng.integers(0, p, max(1, p // 4))] = 0.0
+        if trial % 7 == 0:
+            n2[rng.integers(0, p, 3)] = n2.max()            # exact ties at the top
+        if trial % 11 == 0:
+            n2[rng.integers(0, p)] = 5e-324                  # smallest subnormal
+        c = np.arange(p)
+        keys = _pivot_key(n2, c)
+        assert (keys != 0).all()
+        win = _key_col(keys.max())
+        top = n2.max()
+        assert n2[win] >= top * (1.0 - 2.0 ** -44)
+        ties = np.flatnonzero(n2 == n2[win])
+        assert win == ties.min()
+        exact = int(np.argmax(n2))                           # first index of the maximum
+        if np.sort(n2)[-2:][0] < top * (1.0 - 2.0 ** -40) or (n2 == top).sum() > 1:
+            assert win == exact
+    for bad in (np.inf, np.nan):
+        n2 = np.array([1.0, 2.0, bad, 3.0])
+        assert _key_col(_pivot_key(n2, np.arange(4)).max()) == 2
