@@ -448,18 +448,16 @@ __device__ __forceinline__ int zip_site_pair(char *arena, const SiteDims &sd, co
         const House &H = Hs;
         v0 = H.am;
         hinf[b * PW + wv] = H;
-        CandInfo ci;
-        ci.key = key; ci.sum = sum; ci.pad[0] = 0.0; ci.pad[1] = 0.0;
-        *inf = ci;
+        inf->key = key;   // the pad is never read
+        inf->sum = sum;
       }
       mine[g] = v0;
 #pragma unroll
       for (int sl = 1; sl < SMX; ++sl) mine[G * sl + g] = t[sl];
     }
     if (key == 0ull && lane == 0) {   // no candidate left in this wave
-      CandInfo ci;
-      ci.key = 0ull; ci.sum = sum; ci.pad[0] = 0.0; ci.pad[1] = 0.0;
-      *inf = ci;
+      inf->key = 0ull;
+      inf->sum = sum;
     }
     __syncthreads();
     // every wave's record is loaded before any is compared, so that one LDS latency covers
