@@ -89,6 +89,39 @@ __device__ __forceinline__ double grp_sum(double v, int G) {
   return v;
 }
 
+// grp_sum of several values at once: every stage moves all of them before the next, so that
+// their dependent chains overlap (and a run-time G costs one test per stage, not per value).
+template <int N>
+__device__ __forceinline__ void grp_sum_n(double (&v)[N], int G) {
+  auto dpp_stage = [&](auto ctrl) {
+    constexpr int C = decltype(ctrl)::value;
+    double t[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) t[i] = dpp_d<C>(v[i]);
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] += t[i];
+  };
+  auto swap_stage = [&](auto wc) {
+    constexpr int W = decltype(wc)::value;
+    double a[N], b[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) swap_pair_d<W>(v[i], a[i], b[i]);
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = a[i] + b[i];
+  };
+  if (G >= 2) dpp_stage(std::integral_constant<int, DPP_XOR1>{});
+  if (G >= 4) dpp_stage(std::integral_constant<int, DPP_XOR2>{});
+  if (G >= 8) dpp_stage(std::integral_constant<int, DPP_HALF_MIRROR>{});
+  if (G >= 16) dpp_stage(std::integral_constant<int, DPP_MIRROR>{});
+  if (G >= 32) swap_stage(std::integral_constant<int, 16>{});
+  if (G >= 64) swap_stage(std::integral_constant<int, 32>{});
+}
+__device__ __forceinline__ void grp_sum2(double &x, double &y, int G) {
+  double v[2] = {x, y};
+  grp_sum_n(v, G);
+  x = v[0]; y = v[1];
+}
+
 // Maximum over the 64 lanes of a wave; every lane must take part.
 __device__ __forceinline__ double wave_max(double v) {
   v = fmax(v, dpp_d<DPP_XOR1>(v));
@@ -273,8 +306,7 @@ __device__ __forceinline__ void qr_householder(double2 *Y, int lda, int m, int s
           if (lane == 0) w = Y[c + (int64_t)lda * j];
           for (int i = c + 1 + lane; i < m; i += G) ccfma(w, Y[i + (int64_t)lda * c], Y[i + (int64_t)lda * j]);
         }
-        w.x = grp_sum(w.x, G);
-        w.y = grp_sum(w.y, G);
+        grp_sum2(w.x, w.y, G);
         if (ok) {
           w = cmul(ctc, w);
           if (lane == 0) Y[c + (int64_t)lda * j] = csub(Y[c + (int64_t)lda * j], w);
@@ -304,8 +336,7 @@ __device__ __forceinline__ void qr_apply_q(const double2 *Y, int lda, int m, int
         if (lane == 0) w = Z[c + (int64_t)ldz * j];
         for (int i = c + 1 + lane; i < m; i += G) ccfma(w, Y[i + (int64_t)lda * c], Z[i + (int64_t)ldz * j]);
       }
-      w.x = grp_sum(w.x, G);
-      w.y = grp_sum(w.y, G);
+      grp_sum2(w.x, w.y, G);
       if (ok) {
         w = cmul(tc, w);
         if (lane == 0) Z[c + (int64_t)ldz * j] = csub(Z[c + (int64_t)ldz * j], w);
@@ -347,8 +378,7 @@ __device__ __forceinline__ void qr_form_q_reg(const double2 *T, int m, int k, co
         v[s] = (r > c && r < m) ? T[r + (int64_t)m * c] : cmk(r == c ? 1.0 : 0.0, 0.0);
         ccfma(w, v[s], q[s]);
       }
-      w.x = grp_sum(w.x, G);
-      w.y = grp_sum(w.y, G);
+      grp_sum2(w.x, w.y, G);
       w = cmul(tc, w);
 #pragma unroll
       for (int s = 0; s < NR; ++s) q[s] = csub(q[s], cmul(v[s], w));
@@ -444,7 +474,11 @@ __device__ __forceinline__ void jacobi_onesided(double2 *S, double2 *J, int m, i
           gi += xp.x * xq.y - xp.y * xq.x;
         }
       }
-      a = grp_sum(a, G); b = grp_sum(b, G); gr = grp_sum(gr, G); gi = grp_sum(gi, G);
+      {
+        double r4[4] = {a, b, gr, gi};
+        grp_sum_n(r4, G);
+        a = r4[0]; b = r4[1]; gr = r4[2]; gi = r4[3];
+      }
       if (p >= 0) {
         if (!(a == a) || !(b == b)) {
           if (lane == 0) sh.nonfinite = 1;
@@ -653,8 +687,7 @@ __device__ __forceinline__ int cpqr_trunc(double2 *T, int m, int p, double delta
           if (lane == 0) w = T[i + (int64_t)m * j];
           for (int r = i + 1 + lane; r < m; r += G) ccfma(w, T[r + (int64_t)m * i], T[r + (int64_t)m * j]);
         }
-        w.x = grp_sum(w.x, G);
-        w.y = grp_sum(w.y, G);
+        grp_sum2(w.x, w.y, G);
         double a = 0.0;
         if (ok) {
           if (refl) {
