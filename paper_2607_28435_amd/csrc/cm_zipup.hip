@@ -533,8 +533,7 @@ __device__ __forceinline__ int zip_site_pair(char *arena, const SiteDims &sd, co
         for (int e = 0; e < 4; ++e) ccfma(pz[e], xat(4 * q4 + e), t[4 * q4 + e]);
       }
     double2 pw = cadd(cadd(pz[0], pz[1]), cadd(pz[2], pz[3]));
-    pw.x = la::grp_sum(pw.x, G);
-    pw.y = la::grp_sum(pw.y, G);
+    la::grp_sum2(pw.x, pw.y, G);   // both parts' stages interleaved
     const double2 ws = cmul(cscale(ctau, cabs2(scal)), pw);   // scal w_c
     // row i of R, from slot 0 of lane i % G
     {
@@ -610,8 +609,7 @@ __device__ __forceinline__ int zip_site_pair(char *arena, const SiteDims &sd, co
 #pragma unroll
           for (int sl = 0; sl < QS; ++sl)
             if (8 * sl + 7 >= jj && 8 * sl < m) ccfma(d, vc[sl], qv[sl]);   // V[jj][r] = 0 for r < jj, r >= m
-          d.x = la::grp_sum(d.x, 8);
-          d.y = la::grp_sum(d.y, 8);
+          la::grp_sum2(d.x, d.y, 8);
           const double2 wq = cmul(tc, d);
 #pragma unroll
           for (int sl = 0; sl < QS; ++sl)
