@@ -62,6 +62,7 @@ template <> struct acc_t<float2> {
   __device__ __forceinline__ static void fma_(float2 &a, float2 b, float2 c) { ffma(a, b, c); }
   __device__ __forceinline__ static float2 from(double2 v) { return make_float2((float)v.x, (float)v.y); }
   __device__ __forceinline__ static double2 to(float2 v) { return cmk(v.x, v.y); }
+  __device__ __forceinline__ static float2 add(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 };
 template <> struct acc_t<double2> {
   using type = double2;
@@ -69,6 +70,7 @@ template <> struct acc_t<double2> {
   __device__ __forceinline__ static void fma_(double2 &a, double2 b, double2 c) { cfma(a, b, c); }
   __device__ __forceinline__ static double2 from(double2 v) { return v; }
   __device__ __forceinline__ static double2 to(double2 v) { return v; }
+  __device__ __forceinline__ static double2 add(double2 a, double2 b) { return cadd(a, b); }
 };
 
 struct SiteDims {
@@ -392,19 +394,22 @@ __device__ __forceinline__ int zip_site_pair(char *arena, const SiteDims &sd, co
         if (wcols) {
           // this lane's rows in the chunk: ch = ch0 + gh + (G / 2) e, in slot ch / (G / 2)
           constexpr int NE = 8 / G;
-          typename A::type acc[NE];
+          // the two input bits j accumulate separately (two dependent chains of w0 terms
+          // instead of one of 2 w0), summed at the end
+          typename A::type acc[2][NE];
 #pragma unroll
-          for (int e = 0; e < NE; ++e) acc[e] = A::zero();
+          for (int e = 0; e < NE; ++e) acc[0][e] = acc[1][e] = A::zero();
           for (int ww = 0; ww < w0; ++ww)
+#pragma unroll
             for (int j = 0; j < 2; ++j) {
               const T wvv = Wc[(ww * 4 + 2 * u + j) * w1 + wp];
               const T *dd = Db + (ww * 2 + j) * r1 + rp;
 #pragma unroll
-              for (int e = 0; e < NE; ++e) A::fma_(acc[e], dd[(gh + (G / 2) * e) * w0 * 2 * r1], wvv);
+              for (int e = 0; e < NE; ++e) A::fma_(acc[j][e], dd[(gh + (G / 2) * e) * w0 * 2 * r1], wvv);
             }
 #pragma unroll
           for (int e = 0; e < NE; ++e)
-            if (cok && ch0 + gh + (G / 2) * e < chi) t[ch0 / (G / 2) + e] = A::to(acc[e]);
+            if (cok && ch0 + gh + (G / 2) * e < chi) t[ch0 / (G / 2) + e] = A::to(A::add(acc[0][e], acc[1][e]));
         }
       }
     }
