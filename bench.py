@@ -578,7 +578,7 @@ MLP_SOURCES = ["paper_2607_28435_amd/csrc/cm_mlp.hip", "paper_2607_28435_amd/csr
 _F = 1.9999229937640446   # FETCH_SIZE scale of the 1 GiB copy (chain runs)
 _FS = 1.9999246625669753  # the same for the surrogate runs
 PROFILED_TRAFFIC = {
-    "k_zipup": {"sha": "b71c0f6c8f02613b", "bytes": (226491.1 * _F + 826752.3) * 1024,
+    "k_zipup": {"sha": "afba71c42f126791", "bytes": (226491.1 * _F + 826752.3) * 1024,
                 "per": "launch (4096 instances, n=24, 1536 workgroups)"},
     "build": {"sha": "d9bc5c6ff8258cb0", "bytes": ((37187.2 + 400374.9) * _F + 229892.0 + 820500.6) * 1024,
               "per": "build (k_build_qtt + k_build_round, 4096 instances, n=24)"},

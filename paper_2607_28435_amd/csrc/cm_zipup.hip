@@ -240,8 +240,8 @@ __device__ __forceinline__ unsigned long long dpp_u64(unsigned long long v) {
 
 // Over the 64 lanes of a wave: the largest pivot key and the sum of one `sum` per aligned
 // group of G lanes, returned wave-uniform. Both are already equal on the G lanes of a group, so
-// only the stages across groups run: DPP inside rows of 16 lanes, then the four row results
-// combined in a fixed order.
+// only the stages across groups run: DPP inside rows of 16 lanes, then lane swaps across rows
+// and across the two halves of the wave.
 template <int G>
 __device__ __forceinline__ void wave_keymax_sum_uni(unsigned long long &key, double &sum) {
   auto step = [&](auto ctrl, bool across) {
