@@ -254,6 +254,7 @@ struct Sh {
   double red[CM_WG / 64 + 2];
   double2 scal;
   int flag;
+  int flag_big;
   int k;
   int rankcap;
   int nonfinite;
@@ -446,10 +447,11 @@ __device__ __forceinline__ void jacobi_onesided(double2 *S, double2 *J, int m, i
   __syncthreads();
   const double null2 = 1e-32 * amax;
   const double tol = 1e-13;
+  const double last_tol = 1e-8;   // see the end of the sweep loop
   const int max_sweeps = 30;
   int sweep = 0;
   for (; sweep < max_sweeps; ++sweep) {
-    if (tid == 0) sh.flag = 0;
+    if (tid == 0) { sh.flag = 0; sh.flag_big = 0; }
     __syncthreads();
     for (int r = 0; r < N - 1; ++r) {
       int p = -1, q = -1;
@@ -507,15 +509,21 @@ __device__ __forceinline__ void jacobi_onesided(double2 *S, double2 *J, int m, i
               J[i + s * p] = csub(cscale(vp, c), cmul(sce, vq));
               J[i + s * q] = cadd(cmul(se, vp), cscale(vq, c));
             }
-            if (lane == 0) sh.flag = 1;
+            if (lane == 0) {
+              sh.flag = 1;
+              if (ag2 > (last_tol * last_tol) * a * b) sh.flag_big = 1;
+            }
           }
         }
       }
       __syncthreads();
     }
-    const int f = sh.flag;
+    const int f = sh.flag, fb = sh.flag_big;
     __syncthreads();
-    if (f == 0) break;
+    // A sweep whose rotations all had cosines below last_tol leaves off-diagonal cosines of
+    // order its square (the cyclic sweeps converge quadratically), under the rotation
+    // threshold: the next sweep would rotate nothing, so it is not run.
+    if (f == 0 || fb == 0) break;
   }
   if (sweep == max_sweeps && tid == 0) sh.noconv = 1;
   // squared column norms and descending order
