@@ -252,7 +252,6 @@ __device__ __forceinline__ double2 dot_strided(const S *__restrict__ a, int64_t 
 // Shared per-workgroup bookkeeping for the factorisations (lives in LDS).
 struct Sh {
   double red[CM_WG / 64 + 2];
-  double2 scal;
   int flag;
   int flag_big;
   int k;
@@ -276,24 +275,21 @@ __device__ __forceinline__ void qr_householder(double2 *Y, int lda, int m, int s
     double part = 0.0;
     for (int i = c + 1 + tid; i < m; i += CM_WG) part += cabs2(Y[i + (int64_t)lda * c]);
     const double xn2 = wg_sum(part, sh.red);
-    if (tid == 0) {
-      double2 a = Y[c + (int64_t)lda * c];
-      if (xn2 == 0.0 && a.y == 0.0) {
-        sh.tau[c] = cmk(0.0, 0.0);
-        sh.scal = cmk(0.0, 0.0);
-      } else {
-        double beta = -copysign(sqrt(a.x * a.x + a.y * a.y + xn2), a.x);
-        sh.tau[c] = cmk((beta - a.x) / beta, -a.y / beta);
-        sh.scal = cdiv(cmk(1.0, 0.0), csub(a, cmk(beta, 0.0)));
-        Y[c + (int64_t)lda * c] = cmk(beta, 0.0);
-      }
+    // every thread forms the reflector from the same inputs with the same operations (no
+    // barrier and LDS round trip to share it); beta replaces the diagonal once all have read it
+    const double2 a = Y[c + (int64_t)lda * c];
+    double2 tc = cmk(0.0, 0.0), sc = cmk(0.0, 0.0);
+    double beta = 0.0;
+    if (!(xn2 == 0.0 && a.y == 0.0)) {
+      beta = -copysign(sqrt(a.x * a.x + a.y * a.y + xn2), a.x);
+      tc = cmk((beta - a.x) / beta, -a.y / beta);
+      sc = cdiv(cmk(1.0, 0.0), csub(a, cmk(beta, 0.0)));
     }
-    __syncthreads();
-    const double2 tc = sh.tau[c];
-    if (tc.x == 0.0 && tc.y == 0.0) continue;  // uniform
-    const double2 sc = sh.scal;
+    if (tid == 0) sh.tau[c] = tc;
+    if (tc.x == 0.0 && tc.y == 0.0) continue;  // uniform; the next column starts with barriers
     for (int i = c + 1 + tid; i < m; i += CM_WG) Y[i + (int64_t)lda * c] = cmul(Y[i + (int64_t)lda * c], sc);
     __syncthreads();
+    if (tid == 0) Y[c + (int64_t)lda * c] = cmk(beta, 0.0);
     const int ncols = ntot - c - 1;
     if (ncols > 0) {
       const int G = group_for(ncols), lgG = __builtin_ctz(G), groups = CM_WG >> lgG;
