@@ -284,6 +284,14 @@ struct House {
   double beta, pad;
 };
 static_assert(sizeof(House) == 64, "House layout");
+// The published reflector: the step's factor conj(tau) |scal|^2 of w_c (formed once by the
+// winning lane instead of by every lane of every wave) in place of alpha - beta, which only
+// the winner needs.
+struct HouseRec {
+  double2 wf, tau, scal;
+  double beta, pad;
+};
+static_assert(sizeof(HouseRec) == 64, "HouseRec layout");
 __device__ __forceinline__ House householder(double n2, double2 alpha) {
   House H;
   H.beta = 0.0;
@@ -319,7 +327,7 @@ __device__ __forceinline__ int zip_site_pair(char *arena, const SiteDims &sd, co
   const int u = g & 1, gh = g >> 1;     // its rows are 2 ch + u with ch = gh (mod G / 2)
   double2 *cand = (double2 *)(arena + PL_CAND);
   CandInfo *info = (CandInfo *)(arena + PL_INFO);
-  House *hinf = (House *)(arena + PL_HOUSE);
+  HouseRec *hinf = (HouseRec *)(arena + PL_HOUSE);
   double2 *taus = (double2 *)(arena + PL_TAU);
   T *Cl = (T *)(arena + PL_REGION);
   T *Wc = Cl + chi * w0 * r0;
@@ -431,7 +439,7 @@ __device__ __forceinline__ int zip_site_pair(char *arena, const SiteDims &sd, co
   // wave). The loop below exits only at its end, which keeps T in registers.
   int pc = 0;
   double beta = 0.0;
-  double2 scal = cmk(0.0, 0.0), ctau = cmk(0.0, 0.0);
+  double2 scal = cmk(0.0, 0.0), wf = cmk(0.0, 0.0);
   const double2 *X = cand;
   auto select = [&](int i) -> bool {
     const int b = i & 1, j = i / G;
@@ -452,7 +460,13 @@ __device__ __forceinline__ int zip_site_pair(char *arena, const SiteDims &sd, co
       if (r0w == i) {
         const House &H = Hs;
         v0 = H.am;
-        hinf[b * PW + wv] = H;
+        HouseRec rec;
+        rec.wf = cscale(cconj(H.tau), cabs2(H.scal));
+        rec.tau = H.tau;
+        rec.scal = H.scal;
+        rec.beta = H.beta;
+        rec.pad = 0.0;
+        hinf[b * PW + wv] = rec;
         inf->key = key;   // the pad is never read
         inf->sum = sum;
       }
@@ -489,10 +503,10 @@ __device__ __forceinline__ int zip_site_pair(char *arena, const SiteDims &sd, co
     // exit); with no candidate left they are stale and unused
     pc = key_col(gkey);
     X = cand + (b * PW + gw) * MR;
-    const House H = hinf[b * PW + gw];
+    const HouseRec H = hinf[b * PW + gw];
     beta = H.beta;
     scal = H.scal;
-    ctau = cconj(H.tau);
+    wf = H.wf;
     if (!(tail == tail) || isinf(tail)) {
       if (tid == 0 && *code == CM_OK) *code = CM_E_NONFINITE;
       return true;
@@ -539,15 +553,7 @@ __device__ __forceinline__ int zip_site_pair(char *arena, const SiteDims &sd, co
       }
     double2 pw = cadd(cadd(pz[0], pz[1]), cadd(pz[2], pz[3]));
     la::grp_sum2(pw.x, pw.y, G);   // both parts' stages interleaved
-    const double2 ws = cmul(cscale(ctau, cabs2(scal)), pw);   // scal w_c
-    // row i of R, from slot 0 of lane i % G
-    {
-      const double2 x0 = xat(0);
-      double2 r0v = t[0];
-      r0v.x = fma(x0.y, ws.y, fma(-x0.x, ws.x, r0v.x));
-      r0v.y = fma(-x0.y, ws.x, fma(-x0.x, ws.y, r0v.y));
-      if (cok && g == i % G) C[(int64_t)i * p + c] = (c == pc) ? cmk(beta, 0.0) : (act ? r0v : cmk(0.0, 0.0));
-    }
+    const double2 ws = cmul(wf, pw);   // scal w_c
     // T <- H^H T; slot 0 of lane g holds row G j + g: row i (g = i % G) or a row finished
     // before it (g < i % G), neither of which counts towards the remaining norms
     double nz[2] = {0.0, 0.0};
@@ -567,6 +573,9 @@ __device__ __forceinline__ int zip_site_pair(char *arena, const SiteDims &sd, co
           if (sl > 0 || !skip0) nz[e & 1] = fma(y.y, y.y, fma(y.x, y.x, nz[e & 1]));
         }
       }
+    // row i of R: slot 0 of lane i % G, just updated (a wave with no candidate left updates
+    // nothing and writes zeros)
+    if (cok && g == i % G) C[(int64_t)i * p + c] = (c == pc) ? cmk(beta, 0.0) : (act ? t[0] : cmk(0.0, 0.0));
     // after the last step of a group of G, every lane moves its slots down by one (every
     // slot moves: a copy bounded by the live count would become a memmove that keeps T out
     // of registers)
