@@ -79,3 +79,37 @@ def test_headline_workload_graph_replay_vs_oracle():
         worst = max(worst, float(np.abs(got[b, cols] - ref).max() / p.S0))
     say(f"headline workload: max |err| / S0 over {len(inst)} x {len(cols)} sampled prices = {worst:.3e}")
     assert worst < C64_TOL, worst
+
+
+def test_ragged_workload_graph_replay_vs_oracle():
+    """The ragged batch of the same draws with n ~ U{16..28} (the benchmark's ragged leg):
+    longest chain first, graph replay; one sampled instance at every n against the oracle's
+    direct sums on 64 strikes each, every price within the call's no-arbitrage bounds."""
+    say("ragged workload: 4096 Heston instances, n = 16..28, graph replay")
+    probs = W.heston_batch(BATCH, seed=20261203, n_range=(16, 28))
+    ns = sorted(set(p.n for p in probs))
+    assert ns == list(range(16, 29))
+    strikes = np.stack([W.near_money(p, NK) for p in probs]).astype(np.int64)
+    mpo = cm.MpoCache(ns, 1e-9, 32, cm.CM_C64)
+    pr = cm.SfftPricer(probs, cm.CM_C64, tol=1e-8, cap=32, mpo=mpo)
+    pr.capture(torch.from_numpy(strikes).cuda())
+    for _ in range(2):
+        pr.replay()
+    torch.cuda.synchronize()
+    got = pr.graph_prices.cpu().numpy()
+    bad = {k: int((v != 0).sum()) for k, v in pr.statuses().items()}
+    assert all(v == 0 for v in bad.values()), bad
+    assert np.isfinite(got).all()
+    for b, p in enumerate(probs):
+        K = O.strike_of(p, strikes[b])
+        fwd = p.S0 * np.exp(-p.q * p.T)
+        lo_b = np.maximum(0.0, fwd - K * np.exp(-p.r * p.T))
+        assert (got[b] >= lo_b - C64_TOL * p.S0).all() and (got[b] <= fwd + C64_TOL * p.S0).all(), b
+    cols = np.linspace(0, NK - 1, 64).round().astype(int)
+    worst = {}
+    for n in ns:
+        b = next(i for i, p in enumerate(probs) if p.n == n)
+        ref = O.prices_direct(probs[b], strikes[b, cols])
+        worst[n] = float(np.abs(got[b, cols] - ref).max() / probs[b].S0)
+    say("ragged workload: max |err| / S0 per n:", {n: f"{e:.1e}" for n, e in worst.items()})
+    assert max(worst.values()) < C64_TOL, worst
