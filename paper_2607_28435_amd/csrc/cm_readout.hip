@@ -192,6 +192,7 @@ __global__ __launch_bounds__(RD_WG) void k_readout(TTView y, const cm_problem *_
                                                    int rm_lo, int absval) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   __shared__ int32_t s_off[CM_MAX_N + 1], s_rk[CM_MAX_N + 1];
+  __shared__ int64_t s_goff[CM_MAX_N];   // the cores' offsets in global memory
   __shared__ int s_ok;
   const int b = blockIdx.y;
   const int n = y.n[b];
@@ -206,6 +207,7 @@ __global__ __launch_bounds__(RD_WG) void k_readout(TTView y, const cm_problem *_
     for (int l = 0; l < n; ++l) {
       s_off[l] = o;
       s_rk[l] = rk[l];
+      s_goff[l] = y.coff(b, l);
       o += rk[l] * 2 * rk[l + 1];
     }
     s_rk[n] = rk[n];
@@ -228,7 +230,7 @@ __global__ __launch_bounds__(RD_WG) void k_readout(TTView y, const cm_problem *_
         dst[k] = -1;
         if (e < total) {
           while (s_off[l + 1] <= e) ++l;
-          v[k] = gcores[y.coff(b, l) + (e - s_off[l])];
+          v[k] = gcores[s_goff[l] + (e - s_off[l])];
           dst[k] = e;
         }
       }
