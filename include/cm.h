@@ -296,7 +296,10 @@ cm_status cm_fft_price(const cm_problem *prob, int batch, int n, int dtype, cons
 
 typedef struct {
   float *params;       /* device [CM_MLP_NPARAMS] FP32 master parameters */
-  uint16_t *w_bf16;    /* device [3][256][256] BF16 bit patterns of W2, W3, W4 */
+  uint16_t *w_bf16;    /* device [3][65536] BF16 bit patterns of W2, W3, W4 in MFMA fragment
+                        * order: W_l[n][k] at (l - 2) 65536 + 8 (64 (16 (n / 32) + k / 16)
+                        * + 32 ((k / 8) mod 2) + n mod 32) + k mod 8 (written by
+                        * cm_mlp_sync_bf16 and cm_adam_step; callers only allocate it) */
   float shift[7];      /* host values: input normalisation xn = (x - shift) * scale */
   float scale[7];
 } cm_mlp;

@@ -26,6 +26,16 @@ __host__ __device__ constexpr int off_w(int l) { return l == 2 ? 2048 : l == 3 ?
 __host__ __device__ constexpr int off_b(int l) { return l == 2 ? 67584 : l == 3 ? 133376 : 199168; }
 static_assert(OFF_B5 + 1 == CM_MLP_NPARAMS, "parameter layout");
 
+// The BF16 copies of W2..W4 (w_bf16) are kept in MFMA fragment order: the eight weights
+// W_l[n][k8 .. k8 + 7] (k8 a multiple of 8) are lane 32 ((k8 / 8) mod 2) + n mod 32 of the
+// 64-lane, 1 KB block (n / 32) 16 + k8 / 16, which is what lane of a 32 x 32 x 16 MFMA
+// A fragment holds them. One neuron block's fragment for one K step is then one contiguous
+// 1 KB read (eight full cache lines) rather than 32 pieces of 32 rows.
+constexpr int WFB = 512;   // weights per fragment block
+__host__ __device__ constexpr int wfrag(int n, int k) {
+  return ((((n >> 5) * 16 + (k >> 4)) * 64 + ((k >> 3) & 1) * 32 + (n & 31)) << 3) + (k & 7);
+}
+
 __device__ __forceinline__ float silu_f(float z) { return z / (1.0f + expf(-z)); }
 // SiLU from the hardware exp2 and reciprocal (a few ulps): for the activation operand of the
 // layer GEMMs, whose hi + lo BF16 split keeps about 2^-16 of it anyway. Large |z| behave:
@@ -192,15 +202,19 @@ __global__ __launch_bounds__(WS_THREADS) void k_gemm_ws(const float *__restrict_
                                                         const float *__restrict__ Z) {
   extern __shared__ __align__(16) uint16_t Ws[];   // [NW][WSP]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // W is in fragment order: 16-byte piece c holds row 32 (c / 1024) + c mod 32, columns
+  // 16 ((c / 64) mod 16) + 8 ((c / 32) mod 2) .. +7
   if (WL == W_NK) {
-    for (int e = tid; e < NW * NW / 8; e += WS_THREADS) {
-      const int n = e / (NW / 8), k8 = (e % (NW / 8)) * 8;
-      *(uint4 *)&Ws[n * WSP + k8] = *(const uint4 *)&W[n * NW + k8];
+    for (int c = tid; c < NW * NW / 8; c += WS_THREADS) {
+      const int blk = c >> 6, ln = c & 63;
+      const int n = 32 * (blk >> 4) + (ln & 31), k8 = 16 * (blk & 15) + 8 * (ln >> 5);
+      *(uint4 *)&Ws[n * WSP + k8] = *(const uint4 *)&W[8 * c];
     }
   } else {
     for (int e = tid; e < NW * NW; e += WS_THREADS) {
-      const int k = e / NW, n = e % NW;
-      Ws[n * WSP + k] = W[e];
+      const int blk = e >> 9, ln = (e >> 3) & 63;
+      const int row = 32 * (blk >> 4) + (ln & 31), col = 16 * (blk & 15) + 8 * (ln >> 5) + (e & 7);
+      Ws[col * WSP + row] = W[e];
     }
   }
   __syncthreads();
@@ -263,25 +277,34 @@ __global__ __launch_bounds__(WS_THREADS) void k_gemm_ws(const float *__restrict_
 constexpr size_t WS_LDS = sizeof(uint16_t) * NW * WSP;
 
 // ------------------------------------------------------------------ fused inference
-// The whole network for a tile of FM = 64 queries in one workgroup of four waves, with no
-// activation leaving the CU. Each layer is computed transposed, Z^T = W A^T: the weights are
-// the MFMA's A operand (32 output neurons x 16 inputs per fragment, 16-byte loads of W rows
-// from L2, where the three 256 x 256 BF16 matrices stay) and the activations its B operand,
-// read from LDS, where the tile's activations live as their hi and lo BF16 parts (Ah, Al:
-// [query][neuron], 68 KB, two workgroups per CU so that one's VALU epilogue overlaps the
-// other's MFMAs). Wave w computes neurons 64 w .. 64 w + 63 for all 64 queries: four 32 x 32
-// accumulators, K in steps of 16, the A fragments of the next step loaded before the current
-// step's MFMAs, all hi products of a step before the lo products. An accumulator lane holds
-// four consecutive neurons of one query per group, so the epilogue (bias, SiLU, hi / lo split)
-// converts in pairs and stores eight-byte packets. The first layer (7 -> 256, FP32 weights)
-// is three MFMAs per block with both operands split into hi and lo parts
-// (W_hi x_hi + W_hi x_lo + W_lo x_hi: relative error ~2^-16, below the hidden layers' own);
-// the last folds W5 silu(z4) into per-query partial sums.
+// The whole network for tiles of FM = 64 queries, with no activation leaving the CU. Each
+// layer is computed transposed, Z^T = W A^T: the weights are the MFMA's A operand (32 output
+// neurons x 16 inputs per fragment, 16-byte loads of W rows from L2, where the three
+// 256 x 256 BF16 matrices stay) and the activations its B operand, read from LDS, where a
+// tile's activations live as their hi and lo BF16 parts (Ah, Al: [query][neuron], 68 KB per
+// tile). A wave computes neurons 64 w .. 64 w + 63 for all 64 queries of its tile: four
+// 32 x 32 accumulators, K in steps of 16, the A fragments loaded a few steps ahead, all hi
+// products of a step before the lo products. An accumulator lane holds four consecutive
+// neurons of one query per group, so the epilogue (bias, SiLU, hi / lo split) converts in
+// pairs and stores eight-byte packets. The first layer (7 -> 256, FP32 weights) is three
+// MFMAs per block with both operands split into hi and lo parts (W_hi x_hi + W_hi x_lo +
+// W_lo x_hi: relative error ~2^-16, below the hidden layers' own); the last folds
+// W5 silu(z4) into per-query partial sums.
+//
+// A workgroup is two groups of four waves, each with a tile of its own, and a tile goes
+// through six phases: (0) the previous tile's output fold, then layer 1 and its epilogue,
+// (1) layer 2's MFMAs, (2) its epilogue, (3) layer 3's MFMAs, (4) its epilogue, (5) layer
+// 4's MFMAs. Group 1 runs one phase behind group 0 and one barrier of the whole workgroup
+// ends every phase, so the two waves that share a SIMD (wave w of each group) alternate:
+// one issues MFMAs while the other runs its VALU epilogue. The barrier also orders each
+// group's own LDS traffic: a phase's epilogue writes the activations the next phase's MFMAs
+// read, after every wave of the group has read the previous layer's.
 constexpr int FM = 64;               // queries per tile
 constexpr int FQB = FM / 32;         // query blocks
 constexpr int FP = NW + 8;           // LDS row pitch (bf16): 528 bytes, 16-byte aligned
-constexpr size_t FUSED_LDS = sizeof(uint16_t) * 2 * FM * FP;
+constexpr size_t FUSED_LDS = sizeof(uint16_t) * 2 * 2 * FM * FP;   // two tiles, hi and lo
 constexpr int FPD = 3;               // K steps between a weight fragment's load and its use
+constexpr int FPH = 6;               // phases per tile
 
 __device__ __forceinline__ void split8(const float *v, s16x8 &hi, s16x8 &lo) {
 #pragma unroll
@@ -292,17 +315,18 @@ __device__ __forceinline__ void split8(const float *v, s16x8 &hi, s16x8 &lo) {
   }
 }
 
-__global__ __launch_bounds__(256, 2) void k_mlp_fused(const float *__restrict__ x, int B, const float *__restrict__ p,
+__global__ __launch_bounds__(512, 1) void k_mlp_fused(const float *__restrict__ x, int B, const float *__restrict__ p,
                                                    const uint16_t *__restrict__ wbf, cm_mlp net,
                                                    float *__restrict__ y) {
   extern __shared__ __align__(16) uint16_t fl[];
-  uint16_t *Ah = fl, *Al = fl + FM * FP;
   __shared__ float bsh[4][NW];   // b1..b4
   __shared__ float w5s[NW];
-  __shared__ float ys[4][FM];    // per-wave partial outputs
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  __shared__ float ys[2][4][FM];  // per-group, per-wave partial outputs
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int grp = tid >> 8, w = (tid >> 6) & 3, gtid = tid & 255;
   const int l32 = lane & 31, hi32 = lane >> 5;
-  for (int e = tid; e < NW; e += 256) {
+  uint16_t *Ah = fl + grp * 2 * FM * FP, *Al = Ah + FM * FP;
+  for (int e = tid; e < NW; e += 512) {
     bsh[0][e] = p[OFF_B1 + e];
     bsh[1][e] = p[off_b(2) + e];
     bsh[2][e] = p[off_b(3) + e];
@@ -327,155 +351,172 @@ __global__ __launch_bounds__(256, 2) void k_mlp_fused(const float *__restrict__ 
     w1l[mb] = __builtin_bit_cast(bf16x8, l);
   }
   __syncthreads();
-  // epilogue of a hidden layer: neurons 64 w + 32 mb + 8 g + 4 hi32 + j (j < 4) of query
-  // 32 qb + l32 are acc[mb][qb][4 g + j]
-  auto store_act = [&](const f32x16 (&acc)[2][FQB], const float *bias) {
-#pragma unroll
-    for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-      for (int qb = 0; qb < FQB; ++qb)
-#pragma unroll
-        for (int g = 0; g < 4; ++g) {
-          const int n = 64 * w + 32 * mb + 8 * g + 4 * hi32;
-          float v[4];
-#pragma unroll
-          for (int j = 0; j < 4; ++j) v[j] = silu_fast(acc[mb][qb][4 * g + j] + bias[n + j]);
-          uint16_t h[4], lo[4];
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            h[j] = __builtin_bit_cast(uint16_t, (__bf16)v[j]);
-            lo[j] = __builtin_bit_cast(uint16_t, (__bf16)(v[j] - bf2f(h[j])));
-          }
-          const int off = (32 * qb + l32) * FP + n;
-          *(uint2 *)&Ah[off] = make_uint2(h[0] | ((uint32_t)h[1] << 16), h[2] | ((uint32_t)h[3] << 16));
-          *(uint2 *)&Al[off] = make_uint2(lo[0] | ((uint32_t)lo[1] << 16), lo[2] | ((uint32_t)lo[3] << 16));
-        }
-  };
+  // the tiles of group g are 2 blockIdx.x + g + i stride, i = 0, 1, ...
   const int ntiles = (B + FM - 1) / FM;
-  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const int q0 = t * FM;
-    f32x16 acc[2][FQB];
-    // layer 1: B fragments xn[q][k], q = 32 qb + l32, k = 8 hi32 + i
-    {
-      bf16x8 xh[FQB], xl[FQB];
-#pragma unroll
-      for (int qb = 0; qb < FQB; ++qb) {
-        const int q = q0 + 32 * qb + l32;
-        float v[8];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          const int k = 8 * hi32 + i;
-          v[i] = (k < NIN && q < B) ? (x[(int64_t)q * NIN + k] - net.shift[k]) * net.scale[k] : 0.0f;
+  const int stride = 2 * gridDim.x;
+  const int f0 = 2 * blockIdx.x, f1 = f0 + 1;
+  const int n0 = f0 < ntiles ? (ntiles - 1 - f0) / stride + 1 : 0;
+  const int n1 = f1 < ntiles ? (ntiles - 1 - f1) / stride + 1 : 0;
+  const int nmine = grp ? n1 : n0;
+  // a group's own steps: FPH per tile, then the last tile's fold (phase 0) and output
+  // (phase 1); group 1 starts one step late. Every wave runs the same number of barriers.
+  const int last0 = n0 ? FPH * n0 + 2 : 0, last1 = n1 ? 1 + FPH * n1 + 2 : 0;
+  const int nsteps = last0 > last1 ? last0 : last1;
+  f32x16 acc[2][FQB];
+  s16x8 ar0[FPD], ar1[FPD];
+  for (int st = 0; st < nsteps; ++st) {
+    const int ls = st - grp;
+    if (ls >= 0 && ls < FPH * nmine + 2) {
+      const int i = ls / FPH, ph = ls - FPH * i;
+      const int q0 = (f0 + grp + i * stride) * FM;   // this step's tile (while i < nmine)
+      if (ph & 1) {
+        if (ph == 1 && i > 0 && gtid < FM && q0 - stride * FM + gtid < B) {
+          const int t = gtid;
+          y[q0 - stride * FM + t] = ((ys[grp][0][t] + ys[grp][1][t]) + (ys[grp][2][t] + ys[grp][3][t])) + p[OFF_B5];
         }
-        s16x8 h, l;
-        split8(v, h, l);
-        xh[qb] = __builtin_bit_cast(bf16x8, h);
-        xl[qb] = __builtin_bit_cast(bf16x8, l);
-      }
-#pragma unroll
-      for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-        for (int qb = 0; qb < FQB; ++qb) {
-#pragma unroll
-          for (int v = 0; v < 16; ++v) acc[mb][qb][v] = 0.0f;
-          acc[mb][qb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1h[mb], xh[qb], acc[mb][qb], 0, 0, 0);
-          acc[mb][qb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1h[mb], xl[qb], acc[mb][qb], 0, 0, 0);
-          acc[mb][qb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1l[mb], xh[qb], acc[mb][qb], 0, 0, 0);
-        }
-      store_act(acc, bsh[0]);
-    }
-    __syncthreads();
-    float ypart[FQB][16];
-    for (int l = 2; l <= 4; ++l) {
-      const uint16_t *W = wbf + (int64_t)(l - 2) * NW * NW;
-#pragma unroll
-      for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-        for (int qb = 0; qb < FQB; ++qb)
-#pragma unroll
-          for (int v = 0; v < 16; ++v) acc[mb][qb][v] = 0.0f;
-      // A fragment of neuron block mb at K step kk: W[n][kk + 8 hi32 .. +7], n = 64 w + 32 mb + l32,
-      // read from L2 FPD steps ahead (a step's eight MFMAs take less time than an L2 read
-      // under load) into a ring indexed statically by the fully unrolled K loop
-      const uint16_t *wrow0 = W + (int64_t)(64 * w + l32) * NW + 8 * hi32;
-      const uint16_t *wrow1 = wrow0 + (int64_t)32 * NW;
-      s16x8 ar0[FPD], ar1[FPD];
-#pragma unroll
-      for (int s = 0; s < FPD; ++s) {
-        ar0[s] = *(const s16x8 *)(wrow0 + 16 * s);
-        ar1[s] = *(const s16x8 *)(wrow1 + 16 * s);
-      }
-      // B fragments of query block qb at K step kk: Ah / Al[q][kk + 8 hi32 .. +7], q = 32 qb + l32
-      const int boff = l32 * FP + 8 * hi32;
-      s16x8 bhn[FQB], bln[FQB];
-#pragma unroll
-      for (int qb = 0; qb < FQB; ++qb) {
-        bhn[qb] = *(const s16x8 *)&Ah[boff + 32 * qb * FP];
-        bln[qb] = *(const s16x8 *)&Al[boff + 32 * qb * FP];
-      }
-#pragma unroll
-      for (int ks = 0; ks < NW / 16; ++ks) {
-        const int kk = 16 * ks;
-        const bf16x8 A0 = __builtin_bit_cast(bf16x8, ar0[ks % FPD]), A1 = __builtin_bit_cast(bf16x8, ar1[ks % FPD]);
-        if (ks + FPD < NW / 16) {
-          ar0[ks % FPD] = *(const s16x8 *)(wrow0 + kk + 16 * FPD);
-          ar1[ks % FPD] = *(const s16x8 *)(wrow1 + kk + 16 * FPD);
-        }
-        s16x8 bh[FQB], bl[FQB];
-#pragma unroll
-        for (int qb = 0; qb < FQB; ++qb) {
-          bh[qb] = bhn[qb];
-          bl[qb] = bln[qb];
-        }
-        if (kk + 16 < NW) {   // next step's activations, in flight during this step's MFMAs
-#pragma unroll
-          for (int qb = 0; qb < FQB; ++qb) {
-            bhn[qb] = *(const s16x8 *)&Ah[boff + 32 * qb * FP + kk + 16];
-            bln[qb] = *(const s16x8 *)&Al[boff + 32 * qb * FP + kk + 16];
-          }
-        }
-#pragma unroll
-        for (int qb = 0; qb < FQB; ++qb) {
-          const bf16x8 BH = __builtin_bit_cast(bf16x8, bh[qb]);
-          acc[0][qb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A0, BH, acc[0][qb], 0, 0, 0);
-          acc[1][qb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A1, BH, acc[1][qb], 0, 0, 0);
-        }
-#pragma unroll
-        for (int qb = 0; qb < FQB; ++qb) {
-          const bf16x8 BL = __builtin_bit_cast(bf16x8, bl[qb]);
-          acc[0][qb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A0, BL, acc[0][qb], 0, 0, 0);
-          acc[1][qb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A1, BL, acc[1][qb], 0, 0, 0);
-        }
-      }
-      __syncthreads();   // every wave has read this layer's input
-      if (l < 4) {
-        store_act(acc, bsh[l - 1]);
-        __syncthreads();
-      } else {
-        // y[q] = b5 + sum_n W5[n] silu(z4[n][q]) over this lane's 32 neurons
-#pragma unroll
-        for (int qb = 0; qb < FQB; ++qb) {
-          float sacc = 0.0f;
+        if (i < nmine) {
+          // layers 2, 3, 4 at phases 1, 3, 5
+          const uint16_t *W = wbf + (int64_t)(ph >> 1) * NW * NW;
 #pragma unroll
           for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-            for (int v = 0; v < 16; ++v) {
-              const int n = 64 * w + 32 * mb + 8 * (v >> 2) + 4 * hi32 + (v & 3);
-              sacc += w5s[n] * silu_fast(acc[mb][qb][v] + bsh[3][n]);
+            for (int qb = 0; qb < FQB; ++qb)
+#pragma unroll
+              for (int v = 0; v < 16; ++v) acc[mb][qb][v] = 0.0f;
+          // A fragment of neuron block 2 w + mb at K step ks: W[n][16 ks + 8 hi32 .. +7],
+          // n = 64 w + 32 mb + l32, one contiguous 1 KB block of the fragment-ordered copy,
+          // read from L2 FPD steps ahead into a ring indexed statically by the unrolled K loop
+          const uint16_t *wrow0 = W + (int64_t)(2 * w) * 16 * WFB + 8 * lane;
+          const uint16_t *wrow1 = wrow0 + 16 * WFB;
+          // B fragments of query block qb at K step kk: Ah / Al[q][kk + 8 hi32 .. +7], q = 32 qb + l32
+          const int boff = l32 * FP + 8 * hi32;
+          s16x8 bhn[FQB], bln[FQB];
+#pragma unroll
+          for (int qb = 0; qb < FQB; ++qb) {
+            bhn[qb] = *(const s16x8 *)&Ah[boff + 32 * qb * FP];
+            bln[qb] = *(const s16x8 *)&Al[boff + 32 * qb * FP];
+          }
+#pragma unroll
+          for (int ks = 0; ks < NW / 16; ++ks) {
+            const int kk = 16 * ks;
+            const bf16x8 A0 = __builtin_bit_cast(bf16x8, ar0[ks % FPD]), A1 = __builtin_bit_cast(bf16x8, ar1[ks % FPD]);
+            if (ks + FPD < NW / 16) {
+              ar0[ks % FPD] = *(const s16x8 *)(wrow0 + (ks + FPD) * WFB);
+              ar1[ks % FPD] = *(const s16x8 *)(wrow1 + (ks + FPD) * WFB);
             }
-          ypart[qb][0] = sacc;
+            s16x8 bh[FQB], bl[FQB];
+#pragma unroll
+            for (int qb = 0; qb < FQB; ++qb) {
+              bh[qb] = bhn[qb];
+              bl[qb] = bln[qb];
+            }
+            if (kk + 16 < NW) {   // next step's activations, in flight during this step's MFMAs
+#pragma unroll
+              for (int qb = 0; qb < FQB; ++qb) {
+                bhn[qb] = *(const s16x8 *)&Ah[boff + 32 * qb * FP + kk + 16];
+                bln[qb] = *(const s16x8 *)&Al[boff + 32 * qb * FP + kk + 16];
+              }
+            }
+#pragma unroll
+            for (int qb = 0; qb < FQB; ++qb) {
+              const bf16x8 BH = __builtin_bit_cast(bf16x8, bh[qb]);
+              acc[0][qb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A0, BH, acc[0][qb], 0, 0, 0);
+              acc[1][qb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A1, BH, acc[1][qb], 0, 0, 0);
+            }
+#pragma unroll
+            for (int qb = 0; qb < FQB; ++qb) {
+              const bf16x8 BL = __builtin_bit_cast(bf16x8, bl[qb]);
+              acc[0][qb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A0, BL, acc[0][qb], 0, 0, 0);
+              acc[1][qb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A1, BL, acc[1][qb], 0, 0, 0);
+            }
+          }
+        }
+      } else {
+        if (ph == 0) {
+          if (i > 0) {
+            // the previous tile's y[q] = b5 + sum_n W5[n] silu(z4[n][q]) over this lane's 32
+            // neurons; the two half waves hold the same queries' other neurons
+#pragma unroll
+            for (int qb = 0; qb < FQB; ++qb) {
+              float sacc = 0.0f;
+#pragma unroll
+              for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                  const int n = 64 * w + 32 * mb + 8 * (v >> 2) + 4 * hi32 + (v & 3);
+                  sacc += w5s[n] * silu_fast(acc[mb][qb][v] + bsh[3][n]);
+                }
+              const float s2 = sacc + __shfl_xor(sacc, 32, 64);
+              if (hi32 == 0) ys[grp][w][32 * qb + l32] = s2;
+            }
+          }
+          if (i < nmine) {
+            // layer 1: B fragments xn[q][k], q = 32 qb + l32, k = 8 hi32 + i
+            bf16x8 xh[FQB], xl[FQB];
+#pragma unroll
+            for (int qb = 0; qb < FQB; ++qb) {
+              const int q = q0 + 32 * qb + l32;
+              float v[8];
+#pragma unroll
+              for (int j = 0; j < 8; ++j) {
+                const int k = 8 * hi32 + j;
+                v[j] = (k < NIN && q < B) ? (x[(int64_t)q * NIN + k] - net.shift[k]) * net.scale[k] : 0.0f;
+              }
+              s16x8 h, l;
+              split8(v, h, l);
+              xh[qb] = __builtin_bit_cast(bf16x8, h);
+              xl[qb] = __builtin_bit_cast(bf16x8, l);
+            }
+#pragma unroll
+            for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+              for (int qb = 0; qb < FQB; ++qb) {
+#pragma unroll
+                for (int v = 0; v < 16; ++v) acc[mb][qb][v] = 0.0f;
+                acc[mb][qb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1h[mb], xh[qb], acc[mb][qb], 0, 0, 0);
+                acc[mb][qb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1h[mb], xl[qb], acc[mb][qb], 0, 0, 0);
+                acc[mb][qb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1l[mb], xh[qb], acc[mb][qb], 0, 0, 0);
+              }
+          }
+        }
+        if (i < nmine) {
+          {
+            // the next phase's first weight fragments, in flight during this epilogue
+            const uint16_t *wrow0 = wbf + (int64_t)(ph >> 1) * NW * NW + (int64_t)(2 * w) * 16 * WFB + 8 * lane;
+            const uint16_t *wrow1 = wrow0 + 16 * WFB;
+#pragma unroll
+            for (int s = 0; s < FPD; ++s) {
+              ar0[s] = *(const s16x8 *)(wrow0 + s * WFB);
+              ar1[s] = *(const s16x8 *)(wrow1 + s * WFB);
+            }
+          }
+          // epilogue of layers 1, 2, 3 at phases 0, 2, 4: neurons 64 w + 32 mb + 8 g + 4 hi32 + j
+          // (j < 4) of query 32 qb + l32 are acc[mb][qb][4 g + j]
+          const float *bias = bsh[ph >> 1];
+#pragma unroll
+          for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+            for (int qb = 0; qb < FQB; ++qb)
+#pragma unroll
+              for (int g = 0; g < 4; ++g) {
+                const int n = 64 * w + 32 * mb + 8 * g + 4 * hi32;
+                float v[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) v[j] = silu_fast(acc[mb][qb][4 * g + j] + bias[n + j]);
+                uint16_t h[4], lo[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                  h[j] = __builtin_bit_cast(uint16_t, (__bf16)v[j]);
+                  lo[j] = __builtin_bit_cast(uint16_t, (__bf16)(v[j] - bf2f(h[j])));
+                }
+                const int off = (32 * qb + l32) * FP + n;
+                *(uint2 *)&Ah[off] = make_uint2(h[0] | ((uint32_t)h[1] << 16), h[2] | ((uint32_t)h[3] << 16));
+                *(uint2 *)&Al[off] = make_uint2(lo[0] | ((uint32_t)lo[1] << 16), lo[2] | ((uint32_t)lo[3] << 16));
+              }
         }
       }
     }
-    // the two half waves hold the same queries' other neurons; then the four waves
-#pragma unroll
-    for (int qb = 0; qb < FQB; ++qb) {
-      const float s2 = ypart[qb][0] + __shfl_xor(ypart[qb][0], 32, 64);
-      if (hi32 == 0) ys[w][32 * qb + l32] = s2;
-    }
     __syncthreads();
-    if (tid < FM && q0 + tid < B) y[q0 + tid] = ((ys[0][tid] + ys[1][tid]) + (ys[2][tid] + ys[3][tid])) + p[OFF_B5];
-    __syncthreads();   // ys and the activations are reused by the next tile
   }
 }
 
@@ -573,10 +614,14 @@ __global__ void k_mse(const float *__restrict__ y, const float *__restrict__ t, 
   if ((threadIdx.x & 63) == 0 && loss) atomicAdd(loss, acc);
 }
 
-// BF16 copies of W2..W4 live contiguously in w_bf16: layer l's copy at (l - 2) * 65536
+// BF16 copies of W2..W4 live contiguously in w_bf16, layer l's copy at (l - 2) * 65536 in
+// fragment order
 __device__ __forceinline__ int bf16_slot(int i) {
   for (int l = 2; l <= 4; ++l)
-    if (i >= off_w(l) && i < off_w(l) + NW * NW) return (l - 2) * NW * NW + (i - off_w(l));
+    if (i >= off_w(l) && i < off_w(l) + NW * NW) {
+      const int j = i - off_w(l);
+      return (l - 2) * NW * NW + wfrag(j / NW, j % NW);
+    }
   return -1;
 }
 
@@ -599,7 +644,7 @@ __global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float
 __global__ void k_sync_bf16(const float *__restrict__ p, uint16_t *__restrict__ wbf) {
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < 3 * NW * NW; e += gridDim.x * blockDim.x) {
     const int l = 2 + e / (NW * NW), i = e % (NW * NW);
-    wbf[e] = f2bf(p[off_w(l) + i]);
+    wbf[(l - 2) * NW * NW + wfrag(i / NW, i % NW)] = f2bf(p[off_w(l) + i]);
   }
 }
 
@@ -679,15 +724,16 @@ extern "C" cm_status cm_mlp_forward(const cm_mlp *net, const float *x, int B, fl
   const bool keep = acts && acts_bytes >= cm_mlp_act_bytes(B);
   hipStream_t s = (hipStream_t)stream;
   if (!keep) {
-    // inference: the fused kernel, two persistent workgroups per CU at most
+    // inference: the fused kernel, one persistent workgroup (two tiles in flight) per CU
     CM_HIP_CHECK(cm_allow_lds(k_mlp_fused, FUSED_LDS));
     const int ntiles = (B + FM - 1) / FM;
     int cus = 0;
     int dev = 0;
     CM_HIP_CHECK(hipGetDevice(&dev));
     CM_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    const int grid = ntiles < 2 * cus ? ntiles : 2 * cus;
-    hipLaunchKernelGGL(k_mlp_fused, dim3(grid), dim3(256), FUSED_LDS, s, x, B, net->params, net->w_bf16, *net, y);
+    const int pairs = (ntiles + 1) / 2;
+    const int grid = pairs < cus ? pairs : cus;
+    hipLaunchKernelGGL(k_mlp_fused, dim3(grid), dim3(512), FUSED_LDS, s, x, B, net->params, net->w_bf16, *net, y);
     CM_LAUNCH_CHECK();
     return CM_OK;
   }

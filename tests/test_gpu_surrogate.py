@@ -168,12 +168,16 @@ def test_mse_and_adam_match_reference():
         th, m, v = R.adam_step(th, g.astype(np.float32).astype(np.float64), m, v, step, 1e-3)
     got = net.params.double().cpu().numpy()
     assert np.abs(got - th).max() < 1e-6
-    # the BF16 copies follow the new master weights
+    # the BF16 copies follow the new master weights, in the fragment order the header states:
+    # W_l[n][k] at 8 (64 (16 (n / 32) + k / 16) + 32 ((k / 8) mod 2) + n mod 32) + k mod 8
     wbf = net.wbf.cpu().numpy().astype(np.uint16).astype(np.uint32) << 16
     p = R.unpack(got)
+    n, k = np.meshgrid(np.arange(256), np.arange(256), indexing="ij")
+    at = (8 * (64 * (16 * (n // 32) + k // 16) + 32 * ((k // 8) % 2) + n % 32) + k % 8).reshape(-1)
+    assert np.array_equal(np.sort(at), np.arange(65536))
     for i, l in enumerate((2, 3, 4)):
         blk = wbf[i * 65536:(i + 1) * 65536].view(np.float32).astype(np.float64)
-        assert np.array_equal(blk, R.bf16_round(p[f"W{l}"].reshape(-1)))
+        assert np.array_equal(blk[at], R.bf16_round(p[f"W{l}"].reshape(-1)))
 
 
 def test_gate_box_and_bounds():
