@@ -364,6 +364,24 @@ __global__ __launch_bounds__(512, 1) void k_mlp_fused(const float *__restrict__ 
   const int nsteps = last0 > last1 ? last0 : last1;
   f32x16 acc[2][FQB];
   s16x8 ar0[FPD], ar1[FPD];
+  // accumulators start at the layer's bias: element v of block mb is neuron
+  // 64 w + 32 mb + 8 (v / 4) + 4 hi32 + v mod 4, the same for both query blocks
+  auto bias_init = [&](const float *bias) {
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb) {
+      f32x16 bz;
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const float4 b4 = *(const float4 *)&bias[64 * w + 32 * mb + 8 * g + 4 * hi32];
+        bz[4 * g] = b4.x;
+        bz[4 * g + 1] = b4.y;
+        bz[4 * g + 2] = b4.z;
+        bz[4 * g + 3] = b4.w;
+      }
+#pragma unroll
+      for (int qb = 0; qb < FQB; ++qb) acc[mb][qb] = bz;
+    }
+  };
   for (int st = 0; st < nsteps; ++st) {
     const int ls = st - grp;
     if (ls >= 0 && ls < FPH * nmine + 2) {
@@ -377,12 +395,7 @@ __global__ __launch_bounds__(512, 1) void k_mlp_fused(const float *__restrict__ 
         if (i < nmine) {
           // layers 2, 3, 4 at phases 1, 3, 5
           const uint16_t *W = wbf + (int64_t)(ph >> 1) * NW * NW;
-#pragma unroll
-          for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-            for (int qb = 0; qb < FQB; ++qb)
-#pragma unroll
-              for (int v = 0; v < 16; ++v) acc[mb][qb][v] = 0.0f;
+          bias_init(bsh[1 + (ph >> 1)]);
           // A fragment of neuron block 2 w + mb at K step ks: W[n][16 ks + 8 hi32 .. +7],
           // n = 64 w + 32 mb + l32, one contiguous 1 KB block of the fragment-ordered copy,
           // read from L2 FPD steps ahead into a ring indexed statically by the unrolled K loop
@@ -444,7 +457,7 @@ __global__ __launch_bounds__(512, 1) void k_mlp_fused(const float *__restrict__ 
 #pragma unroll
                 for (int v = 0; v < 16; ++v) {
                   const int n = 64 * w + 32 * mb + 8 * (v >> 2) + 4 * hi32 + (v & 3);
-                  sacc += w5s[n] * silu_fast(acc[mb][qb][v] + bsh[3][n]);
+                  sacc += w5s[n] * silu_fast(acc[mb][qb][v]);
                 }
               const float s2 = sacc + __shfl_xor(sacc, 32, 64);
               if (hi32 == 0) ys[grp][w][32 * qb + l32] = s2;
@@ -467,12 +480,11 @@ __global__ __launch_bounds__(512, 1) void k_mlp_fused(const float *__restrict__ 
               xh[qb] = __builtin_bit_cast(bf16x8, h);
               xl[qb] = __builtin_bit_cast(bf16x8, l);
             }
+            bias_init(bsh[0]);
 #pragma unroll
             for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
               for (int qb = 0; qb < FQB; ++qb) {
-#pragma unroll
-                for (int v = 0; v < 16; ++v) acc[mb][qb][v] = 0.0f;
                 acc[mb][qb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1h[mb], xh[qb], acc[mb][qb], 0, 0, 0);
                 acc[mb][qb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1h[mb], xl[qb], acc[mb][qb], 0, 0, 0);
                 acc[mb][qb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1l[mb], xh[qb], acc[mb][qb], 0, 0, 0);
@@ -491,8 +503,7 @@ __global__ __launch_bounds__(512, 1) void k_mlp_fused(const float *__restrict__ 
             }
           }
           // epilogue of layers 1, 2, 3 at phases 0, 2, 4: neurons 64 w + 32 mb + 8 g + 4 hi32 + j
-          // (j < 4) of query 32 qb + l32 are acc[mb][qb][4 g + j]
-          const float *bias = bsh[ph >> 1];
+          // (j < 4) of query 32 qb + l32 are acc[mb][qb][4 g + j], bias included
 #pragma unroll
           for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
@@ -502,7 +513,7 @@ __global__ __launch_bounds__(512, 1) void k_mlp_fused(const float *__restrict__ 
                 const int n = 64 * w + 32 * mb + 8 * g + 4 * hi32;
                 float v[4];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) v[j] = silu_fast(acc[mb][qb][4 * g + j] + bias[n + j]);
+                for (int j = 0; j < 4; ++j) v[j] = silu_fast(acc[mb][qb][4 * g + j]);
                 uint16_t h[4], lo[4];
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
