@@ -76,13 +76,13 @@ def test_mlp_forward_matches_reference(B):
 
 
 def test_mlp_forward_keep_matches_inference():
-    """The training forward (all four pre-activations kept, one launch per layer) and the
-    fused inference forward (activations on chip) compute the same network, for batches that
-    fill several 64-query tiles and leave a ragged last one, up to one (131149 queries, 2050
+    """The training forward (all four pre-activations kept, one launch per layer) and the fused
+    inference forward (activations on chip) compute the same network, for batches that fill
+    several 64-query tiles and leave a ragged last one, up to one (131149 queries, 2050
     tiles) where every workgroup takes several tiles and the last ones fewer. They differ
-    only in the first layer, FP32 on one side and three BF16 products of hi / lo parts on the other (each
-    product within 3 * 2^-18 relative of the FP32 one), and in the order of the final sum:
-    within 5e-5 of the output scale."""
+    only in the first layer, FP32 on one side and three BF16 products of hi / lo parts on
+    the other (each product within 3 * 2^-18 relative of the FP32 one), and in the order of
+    the final sum: within 5e-5 of the output scale."""
     for B in (1, 777, 4099, 131149):
         net, xd, theta, xn = _net_and_inputs(B, scale_hidden=3.0)
         y1 = net.forward(xd).clone()
